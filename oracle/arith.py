@@ -1,0 +1,282 @@
+"""Product recursion, block substitution and Cholesky factorisation
+(Section 3 "Algebraic operations", Section 6 "Complexity of the LR
+factorization", Section 7 for the Cholesky variant).
+
+The factor L overwrites the lower triangle of an H^2-matrix stored with
+``lower=True`` (row basis V, column basis W); every operation below is
+expressed through the local low-rank update of ``update.addlr``, dense
+operations on inadmissible leaves and products with sub-blocks.
+
+chol(t) (recursion of Section 3 with R = L^*):
+    leaf t:  N_tt <- lower Cholesky factor of N_tt (standard elimination).
+    else:    chol(t1); solve X L_{t1 t1}^* = A_{t2 t1} (block substitution);
+             A_{t2 t2} -= L_{t2 t1} L_{t2 t1}^* (product); chol(t2).
+
+rsolve(c, (r, c)) solves X L_cc^* = Y on the block (r, c) in place
+(substitution X R = Y of Section 3 with R = L^*):
+    inadmissible leaf: dense triangular solve;
+    admissible leaf Y = V_r S W_c^*: the exact solution is
+        V_r S (L_cc^{-1} W_c)^*, applied as the low-rank update
+        (V_r S)(L_cc^{-1} W_c - W_c)^*  because W_c is shared (reading);
+    subdivided with c a leaf: every son (r', c);
+    subdivided with sons c1, c2: for all r' in sons+(r) solve with c1, then
+        for all r' update (r', c2) -= X(r', c1) L(c2, c1)^*, then for all r'
+        solve with c2 (the order of the forward substitution in Section 6).
+
+mm(t, s, r, alpha): Z(t, r) += alpha X(t, s) Y(r, s)^* with X, Y, Z blocks of
+the same factor (Section 3; Section 6, Cases 1 and 2):
+    Case 1, (t,s) and (r,s) subdivided:
+        target subdivided: recursion over s' (outer), t', r' in sons+ (the
+            order of the eight updates printed in Section 3); targets above
+            the diagonal are skipped (lower storage);
+        target inadmissible leaf: dense product added to N_tr;
+        target admissible leaf: one temporary low-rank matrix per son pair
+            (t', r') receives the recursion by truncated addition, then each
+            is extended by zero and added with a low-rank update, in the
+            order (t1,r1), (t1,r2), (t2,r1), (t2,r2).
+    Case 2, a factor is a leaf (precedence in this order, a reading):
+        (r,s) admissible: X~ = X(t,s) W_s by products with the sub-block,
+            emit U = alpha X~ S_rs^*, V = V_r;
+        (t,s) admissible: emit U = alpha V_t S_ts, V = Y(r,s) W_s;
+        (t,s) inadmissible: emit U = alpha N_ts, V = Y(r,s) densely;
+        (r,s) inadmissible: emit U = alpha X(t,s) densely, V = N_rs.
+    An emission is added to the enclosing temporary (truncated addition),
+    to N_tr for an inadmissible target, otherwise by addlr on (t, r).
+
+Truncated addition of low-rank matrices (the H-matrix rule recalled at the
+end of Section 3): QR of both stacked factors, SVD of the small core, drop
+singular values <= eps * ||core||_F (block_rel), <= eps * sigma_1
+(const_rel), or only exact zeros (none).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .h2 import H2Matrix, TruncParams, block_apply, block_dense
+from .trees import ADM, INNER, NEAR
+from .update import addlr
+
+
+class NotSPDError(RuntimeError):
+    def __init__(self, leaf: int):
+        super().__init__(f"leaf block of cluster {leaf} is not positive definite")
+        self.leaf = leaf
+
+
+def _rk_truncate(A: np.ndarray, B: np.ndarray, tp: TruncParams):
+    if A.shape[1] == 0:
+        return A, B
+    Qa, Ra = np.linalg.qr(A)
+    Qb, Rb = np.linalg.qr(B)
+    P, sig, QT = np.linalg.svd(Ra @ Rb.T)
+    if tp.mode == "block_rel":
+        tau = tp.eps * np.sqrt(np.sum(sig ** 2))
+    elif tp.mode == "const_rel":
+        tau = tp.eps * (sig[0] if len(sig) else 0.0)
+    else:
+        tau = 0.0
+    r = int(np.count_nonzero(sig > tau))
+    return Qa @ (P[:, :r] * sig[:r]), Qb @ QT[:r].T
+
+
+class RkTemp:
+    """Temporary low-rank matrix U V^* on the index pair (t, r)."""
+
+    def __init__(self, ct, t: int, r: int):
+        self.ct, self.t, self.r = ct, t, r
+        self.U = np.zeros((int(ct.size[t]), 0))
+        self.V = np.zeros((int(ct.size[r]), 0))
+
+    def add(self, U2, V2, t2, r2, tp):
+        ct = self.ct
+        a = int(ct.offset[t2] - ct.offset[self.t])
+        c = int(ct.offset[r2] - ct.offset[self.r])
+        k2 = U2.shape[1]
+        Ue = np.zeros((self.U.shape[0], k2)); Ue[a:a + U2.shape[0]] = U2
+        Ve = np.zeros((self.V.shape[0], k2)); Ve[c:c + V2.shape[0]] = V2
+        self.U, self.V = _rk_truncate(np.hstack([self.U, Ue]), np.hstack([self.V, Ve]), tp)
+
+
+class _Chol:
+    def __init__(self, L: H2Matrix, tp: TruncParams, stats: dict | None):
+        assert L.lower
+        self.L, self.tp = L, tp
+        self.ct, self.bt = L.ct, L.bt
+        self.stats = stats if stats is not None else {}
+
+    def _count(self, key, inc=1):
+        self.stats[key] = self.stats.get(key, 0) + inc
+
+    # ---------------------------------------------------------------- update
+    def _addlr(self, b, U, V):
+        self._count("addlr_calls")
+        if addlr(self.L, b, U, V, self.tp):
+            self._count("addlr_done")
+
+    def _emit_block(self, t, r, U, V):
+        bZ = self.bt.find(t, r)
+        if self.bt.kind[bZ] == NEAR:
+            self._count("near_add")
+            self.L.N[bZ] = self.L.N[bZ] + U @ V.T
+        else:
+            self._addlr(bZ, U, V)
+
+    # ---------------------------------------------------------------- product
+    def mm(self, t, s, r, alpha, tmp=None):
+        L, ct, bt = self.L, self.ct, self.bt
+        bX, bY = bt.find(t, s), bt.find(r, s)
+        if bt.kind[bX] == INNER and bt.kind[bY] == INNER:
+            triples = [(t2, s2, r2) for s2 in ct.sons_plus(s)
+                       for t2 in ct.sons_plus(t) for r2 in ct.sons_plus(r)]
+            if tmp is not None:
+                for (t2, s2, r2) in triples:
+                    self.mm(t2, s2, r2, alpha, tmp)
+                return
+            bZ = bt.find(t, r)
+            if bt.kind[bZ] == INNER:
+                for (t2, s2, r2) in triples:
+                    if ct.offset[t2] < ct.offset[r2]:
+                        continue              # above the diagonal: not stored
+                    self.mm(t2, s2, r2, alpha)
+            elif bt.kind[bZ] == NEAR:
+                self._count("near_dense_product")
+                cache = {}
+                P = block_dense(L, bX, cache) @ block_dense(L, bY, cache).T
+                L.N[bZ] = L.N[bZ] + alpha * P
+            else:
+                self._count("temp_targets")
+                pairs = [(t2, r2) for t2 in ct.sons_plus(t) for r2 in ct.sons_plus(r)]
+                temps = {p: RkTemp(ct, p[0], p[1]) for p in pairs}
+                for (t2, s2, r2) in triples:
+                    self.mm(t2, s2, r2, alpha, temps[(t2, r2)])
+                for p in pairs:
+                    tm = temps[p]
+                    U = np.zeros((int(ct.size[t]), tm.U.shape[1]))
+                    V = np.zeros((int(ct.size[r]), tm.V.shape[1]))
+                    a = int(ct.offset[p[0]] - ct.offset[t])
+                    c = int(ct.offset[p[1]] - ct.offset[r])
+                    U[a:a + tm.U.shape[0]] = tm.U
+                    V[c:c + tm.V.shape[0]] = tm.V
+                    self._addlr(bZ, U, V)
+            return
+        # Case 2: at least one factor is a leaf -> low-rank emission
+        cache = {}
+        if bt.kind[bY] == ADM:
+            self._count("emit_R3")
+            Xt = block_apply(L, bX, L.basis(1, s, cache), cache=cache)
+            U = alpha * (Xt @ L.S[bY].T)
+            V = L.basis(0, r, cache)
+        elif bt.kind[bX] == ADM:
+            self._count("emit_R4")
+            U = alpha * (L.basis(0, t, cache) @ L.S[bX])
+            V = block_apply(L, bY, L.basis(1, s, cache), cache=cache)
+        elif bt.kind[bX] == NEAR:
+            self._count("emit_R5")
+            U = alpha * L.N[bX]
+            V = block_dense(L, bY, cache)
+        else:
+            self._count("emit_R6")
+            U = alpha * block_dense(L, bX, cache)
+            V = L.N[bY]
+        if tmp is not None:
+            self._count("temp_add")
+            tmp.add(U, V, t, r, self.tp)
+        else:
+            self._emit_block(t, r, U, V)
+
+    # ----------------------------------------------------------- substitution
+    def fsolve(self, c, w):
+        """Solve L_cc y = w (rows of w in cluster order of c)."""
+        L, ct, bt = self.L, self.ct, self.bt
+        if ct.is_leaf(c):
+            return sla.solve_triangular(L.N[bt.find(c, c)], w, lower=True)
+        c1, c2 = ct.sons(c)
+        n1 = int(ct.size[c1])
+        y1 = self.fsolve(c1, w[:n1])
+        y2 = self.fsolve(c2, w[n1:] - block_apply(L, bt.find(c2, c1), y1))
+        return np.concatenate([y1, y2])
+
+    def bsolve(self, c, w):
+        """Solve L_cc^* y = w."""
+        L, ct, bt = self.L, self.ct, self.bt
+        if ct.is_leaf(c):
+            return sla.solve_triangular(L.N[bt.find(c, c)], w, lower=True, trans="T")
+        c1, c2 = ct.sons(c)
+        n1 = int(ct.size[c1])
+        y2 = self.bsolve(c2, w[n1:])
+        y1 = self.bsolve(c1, w[:n1] - block_apply(L, bt.find(c2, c1), y2, trans=True))
+        return np.concatenate([y1, y2])
+
+    def rsolve(self, c, b):
+        L, ct, bt = self.L, self.ct, self.bt
+        r = int(bt.row[b])
+        assert int(bt.col[b]) == c
+        if bt.kind[b] == INNER:
+            if ct.is_leaf(c):
+                for r2 in ct.sons(r):
+                    self.rsolve(c, bt.find(r2, c))
+                return
+            c1, c2 = ct.sons(c)
+            rs = ct.sons_plus(r)
+            for r2 in rs:
+                self.rsolve(c1, bt.find(r2, c1))
+            for r2 in rs:
+                self.mm(r2, c1, c2, -1.0)
+            for r2 in rs:
+                self.rsolve(c2, bt.find(r2, c2))
+        elif bt.kind[b] == NEAR:
+            self._count("near_trsm")
+            Lcc = L.N[bt.find(c, c)]
+            L.N[b] = sla.solve_triangular(Lcc, L.N[b].T, lower=True).T
+        else:
+            self._count("adm_solve")
+            cache = {}
+            Wc = L.basis(1, c, cache)
+            Wp = self.fsolve(c, Wc.copy())
+            U = L.basis(0, r, cache) @ L.S[b]
+            self._addlr(b, U, Wp - Wc)
+
+    def chol(self, t):
+        L, ct, bt = self.L, self.ct, self.bt
+        if ct.is_leaf(t):
+            b = bt.find(t, t)
+            self._count("leaf_potrf")
+            try:
+                L.N[b] = sla.cholesky(L.N[b], lower=True)
+            except np.linalg.LinAlgError:
+                raise NotSPDError(t) from None
+            return
+        t1, t2 = ct.sons(t)
+        self.chol(t1)
+        self.rsolve(t1, bt.find(t2, t1))
+        self.mm(t2, t1, t2, -1.0)
+        self.chol(t2)
+
+
+def cholesky(A: H2Matrix, tp: TruncParams, stats: dict | None = None) -> H2Matrix:
+    """Approximate Cholesky factor L ~ A (A stored with lower=True).  A is
+    overwritten in place and returned."""
+    _Chol(A, tp, stats).chol(0)
+    return A
+
+
+def forward_solve(L: H2Matrix, w: np.ndarray) -> np.ndarray:
+    """L y = w, both in cluster order (vector substitution of Section 3)."""
+    return _Chol(L, TruncParams(), None).fsolve(0, np.asarray(w, dtype=np.float64))
+
+
+def backward_solve(L: H2Matrix, w: np.ndarray) -> np.ndarray:
+    """L^* y = w, both in cluster order."""
+    return _Chol(L, TruncParams(), None).bsolve(0, np.asarray(w, dtype=np.float64))
+
+
+def precond_apply(L: H2Matrix, r: np.ndarray) -> np.ndarray:
+    """z = (L L^*)^{-1} r with r, z in original index order."""
+    perm = L.ct.perm
+    rc = np.asarray(r, dtype=np.float64)[perm]
+    z = backward_solve(L, forward_solve(L, rc))
+    out = np.empty_like(z)
+    out[perm] = z
+    return out
