@@ -1,0 +1,122 @@
+"""Pins of the oracle's Cholesky factorisation, vector substitutions and PCG
+(Sections 3, 6, 7)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import workloads as w
+from oracle.arith import RkTemp, backward_solve, cholesky, forward_solve, precond_apply
+from oracle.h2 import TruncParams, from_csr, to_dense
+from oracle.solve import pcg, power_error
+from oracle.trees import build_block_tree, build_cluster_tree
+
+
+def _setup(N, sigma_seed=None, leaf=32):
+    p = w.problem(N, sigma_seed=sigma_seed, rhs_seed=5)
+    ct = build_cluster_tree(p["coords"], leaf)
+    bt = build_block_tree(ct, 2.0)
+    return p, ct, bt
+
+
+def test_cholesky_exact_equals_lapack():
+    """Without truncation the H^2 Cholesky factor is the Cholesky factor."""
+    p, ct, bt = _setup(32)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(0.0, "none", 1000))
+    D = np.tril(to_dense(L))
+    Ap = p["A"].toarray()[ct.perm][:, ct.perm]
+    Lref = np.linalg.cholesky(Ap)
+    assert np.linalg.norm(D - Lref, 2) / np.linalg.norm(Lref, 2) < 1e-13
+
+
+def test_cholesky_exact_piecewise_sigma_small_leaves():
+    p, ct, bt = _setup(16, sigma_seed=7, leaf=8)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(0.0, "none", 1000))
+    Ap = p["A"].toarray()[ct.perm][:, ct.perm]
+    D = np.tril(to_dense(L))
+    assert np.linalg.norm(D - np.linalg.cholesky(Ap), 2) / np.linalg.norm(D, 2) < 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_cholesky_truncated_accuracy(eps):
+    """||A - L L^*|| / ||A|| = O(eps) and the preconditioner is good."""
+    p, ct, bt = _setup(32, sigma_seed=3)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(eps, "block_rel", 64))
+    Ap = p["A"].toarray()[ct.perm][:, ct.perm]
+    D = np.tril(to_dense(L))
+    rel = np.linalg.norm(Ap - D @ D.T, 2) / np.linalg.norm(Ap, 2)
+    assert rel < 50 * eps
+    assert L.k[0].max() <= 32 and L.k[1].max() <= 32
+
+
+def test_vector_substitution_matches_dense():
+    p, ct, bt = _setup(32, sigma_seed=3)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(1e-6, "block_rel", 64))
+    D = np.tril(to_dense(L))
+    rhs = w.gaussian(ct.n, 2, 4)
+    y = forward_solve(L, rhs)
+    assert np.allclose(y, sla.solve_triangular(D, rhs, lower=True), rtol=1e-11, atol=1e-11)
+    z = backward_solve(L, rhs)
+    assert np.allclose(z, sla.solve_triangular(D, rhs, lower=True, trans="T"), rtol=1e-11, atol=1e-11)
+
+
+def test_pcg_exact_factor_one_step():
+    p, ct, bt = _setup(32)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(0.0, "none", 1000))
+    x, it, rel = pcg(p["A"], p["b"], lambda r: precond_apply(L, r))
+    assert it == 1 and rel < 1e-12
+
+
+def test_pcg_identity_is_plain_cg():
+    p, ct, bt = _setup(32)
+    x, it, rel = pcg(p["A"], p["b"], lambda r: r.copy(), rtol=1e-8)
+    count = [0]
+    def cb(_):
+        count[0] += 1
+    xs, info = spla.cg(p["A"], p["b"], rtol=1e-8, atol=0.0, callback=cb, maxiter=1000)
+    assert info == 0
+    assert abs(count[0] - it) <= 1
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
+
+
+def test_pcg_truncated_factor_and_err():
+    """Table 1 behaviour (qualitative; the settings differ): few CG steps to
+    1e-8 and ||I - B A|| < 1."""
+    p, ct, bt = _setup(32, sigma_seed=3)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(1e-4, "block_rel", 64))
+    x, it, rel = pcg(p["A"], p["b"], lambda r: precond_apply(L, r))
+    assert rel <= 1e-8 and it <= 5
+    assert np.linalg.norm(p["b"] - p["A"] @ x) / np.linalg.norm(p["b"]) <= 1e-8
+    assert power_error(p["A"], lambda r: precond_apply(L, r), ct.n) < 0.5
+
+
+def test_not_spd_detected():
+    from oracle.arith import NotSPDError
+    p, ct, bt = _setup(16, leaf=8)
+    A = p["A"].tolil()
+    A[5, 5] = -1.0
+    with pytest.raises(NotSPDError):
+        cholesky(from_csr(A.tocsr(), ct, bt, lower=True), TruncParams(1e-6, "block_rel", 64))
+
+
+def test_rk_truncated_addition():
+    """Truncated low-rank addition = best approximation of the sum."""
+    ct = build_cluster_tree(w.grid_points(8, 2), 4)
+    t, r = 1, 2
+    tmp = RkTemp(ct, t, r)
+    rng = np.random.Generator(np.random.PCG64(3))
+    nt, nr = int(ct.size[t]), int(ct.size[r])
+    total = np.zeros((nt, nr))
+    tp = TruncParams(1e-12, "block_rel", 64)
+    for i in range(3):
+        U = rng.standard_normal((nt, 2)); V = rng.standard_normal((nr, 2))
+        tmp.add(U, V, t, r, tp)
+        total += U @ V.T
+    assert np.allclose(tmp.U @ tmp.V.T, total, atol=1e-12)
+    assert tmp.U.shape[1] == 6
+    # zero-extended contribution of a son pair
+    s0 = ct.sons(t)[0]
+    U = rng.standard_normal((int(ct.size[s0]), 1)); V = rng.standard_normal((nr, 1))
+    tmp.add(U, V, s0, r, tp)
+    total[:int(ct.size[s0])] += U @ V.T
+    assert np.allclose(tmp.U @ tmp.V.T, total, atol=1e-12)
