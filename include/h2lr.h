@@ -1,0 +1,182 @@
+/*
+ * h2lr -- H^2-matrix local low-rank updates, H^2 Cholesky factorisation and
+ * preconditioned CG on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Boerm, K. Reimer, "Efficient arithmetic operations for
+ * rank-structured matrices based on hierarchical low-rank updates".
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status codes only; no C++ exception crosses this interface.  After an
+ *   error h2_last_error() returns a message for the calling thread.
+ * - Index order: a cluster tree permutes the n indices so that every cluster
+ *   is a contiguous range ("cluster order").  Vectors passed to h2_matvec,
+ *   h2_precond, h2_pcg and h2_spmv are in the caller's ORIGINAL order.  The
+ *   factors X, Y of h2_lowrank_update use cluster order restricted to the
+ *   block's row / column cluster (row i of X belongs to index
+ *   perm[offset(t0) + i]).
+ * - Matrices passed by pointer are column-major with the given leading
+ *   dimension.  Pointers documented as "device" must be HIP device memory
+ *   owned by the caller and stay valid until the context stream is
+ *   synchronised; "host" pointers are read before the call returns.
+ * - All device work is issued on the stream given to h2_ctx_create.  Calls
+ *   that return host values (info/stats/export, h2_pcg counters) synchronise
+ *   that stream; every other call may return before the device work ends.
+ * - Objects are not thread safe; use one context per host thread.
+ */
+#ifndef H2LR_H
+#define H2LR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_ARG = -1,              /* invalid argument (null, size, range)        */
+  H2_ERR_NOMEM = -2,            /* device or host allocation failed            */
+  H2_ERR_HIP = -3,              /* a HIP runtime call failed                   */
+  H2_ERR_NOT_SPD = -4,          /* non-positive pivot in a leaf factorisation  */
+  H2_ERR_RANK_CAP = -5,         /* a recompressed rank exceeded the rank cap   */
+  H2_ERR_NONZERO_FARFIELD = -6, /* sparse input has a non-zero in an admissible block */
+  H2_ERR_NOT_CONVERGED = -7,    /* PCG reached maxit before the tolerance      */
+  H2_ERR_STATE = -8             /* object poisoned by an earlier failed update */
+} h2_status;
+
+typedef struct h2_ctx_s *h2_ctx;
+typedef struct h2_ctree_s *h2_ctree;
+typedef struct h2_btree_s *h2_btree;
+typedef struct h2_mat_s *h2_mat;
+typedef struct h2_csr_s *h2_csr;
+
+/* Recompression accuracy (Section 4, last paragraph; Section 7 "block-relative
+ * accuracy").  mode 0 = block-relative: every block entering a weight stack is
+ * scaled by 1/||block||_F and singular values <= eps are dropped; mode 1 =
+ * constant relative: drop sigma <= eps*sigma_1; mode 2 = no truncation (keep
+ * all non-zero singular values).  rank_cap: 1..H2_MAX_RANK, exceeding it
+ * fails with H2_ERR_RANK_CAP. */
+typedef struct {
+  double eps;
+  int32_t mode;
+  int32_t rank_cap;
+} h2_trunc;
+
+#define H2_MAX_RANK 32       /* rank capacity of every basis slot            */
+#define H2_MAX_LEAF 32       /* largest leaf cluster                          */
+#define H2_MAX_COLS 64       /* right-hand sides of one matvec / solve        */
+#define H2_MAX_UPDATE_RANK 32 /* columns of a low-rank update factor          */
+
+/* ---------------------------------------------------------------- context */
+/* device: HIP device ordinal, or -1 for a host-only context that can build
+ * and export trees but holds no device data; stream: hipStream_t to issue
+ * work on (NULL = the default stream).  The context owns no matrix data. */
+h2_status h2_ctx_create(int device, void *stream, h2_ctx *out);
+h2_status h2_ctx_destroy(h2_ctx ctx);
+h2_status h2_ctx_synchronize(h2_ctx ctx);
+const char *h2_last_error(void);
+
+/* ------------------------------------------------------------ cluster tree */
+/* Cluster tree (Def. "Cluster tree", Section 2; binary as in Section 3) by
+ * geometric bisection of integer points: a cluster with more than leaf_size
+ * points is split at the midpoint of the longest side of its bounding box
+ * (lowest axis on ties), son 0 keeping the points with 2c <= lo+hi in their
+ * current order.  Clusters are numbered breadth first.
+ * coords: host, n x dim int32 row-major (point i at coords[i*dim ..]).
+ * leaf_size: 1..H2_MAX_LEAF; dim 1..3.  Result owned by the caller. */
+h2_status h2_ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords,
+                         int32_t leaf_size, h2_ctree *out);
+h2_status h2_ctree_info(h2_ctree ct, int64_t *n, int64_t *nclusters, int32_t *depth);
+/* Host copies of the tree tables (each array nclusters long, perm n long);
+ * any pointer may be NULL. */
+h2_status h2_ctree_export(h2_ctree ct, int64_t *perm, int32_t *offset, int32_t *size,
+                          int32_t *level, int32_t *son0, int32_t *son1, int32_t *parent);
+h2_status h2_ctree_destroy(h2_ctree ct);
+
+/* -------------------------------------------------------------- block tree */
+/* Block tree (Def. "Block tree", Section 2) of ct x ct: (t,s) is an
+ * admissible leaf iff dist^2 > 0 and max(diam^2) <= eta^2 dist^2 for the
+ * integer bounding boxes; a pair of leaf clusters is an inadmissible leaf;
+ * other pairs are split into sons+(t) x sons+(s), t' outer.  Breadth-first
+ * block numbering.  The block tree keeps a reference to ct. */
+h2_status h2_btree_build(h2_ctx ctx, h2_ctree ct, double eta, h2_btree *out);
+/* csp: largest number of admissible leaves in one block row. */
+h2_status h2_btree_info(h2_btree bt, int64_t *nblocks, int64_t *nadm, int64_t *nnear,
+                        int32_t *csp);
+/* kind: 0 subdivided, 1 admissible leaf, 2 inadmissible leaf.  Arrays are
+ * nblocks long; any pointer may be NULL. */
+h2_status h2_btree_export(h2_btree bt, int32_t *row, int32_t *col, int32_t *kind,
+                          int32_t *parent);
+/* block id of the pair (t, s), or -1 if it is not a block of the tree. */
+h2_status h2_btree_find(h2_btree bt, int64_t t, int64_t s, int64_t *block);
+h2_status h2_btree_destroy(h2_btree bt);
+
+/* ---------------------------------------------------------------- matrices */
+/* H^2 representation (Def. "H^2-matrix", eq. (vsw)) of a sparse matrix whose
+ * admissible blocks vanish: all ranks 0, inadmissible leaves dense.
+ * rowptr (n+1), col (nnz), val (nnz): host CSR in original order.
+ * lower != 0 stores only the blocks on or below the diagonal (the storage
+ * of a Cholesky factor).  rank_cap as in h2_trunc.
+ * Fails with H2_ERR_NONZERO_FARFIELD if a non-zero lies in an admissible
+ * block. */
+h2_status h2_mat_from_csr(h2_ctx ctx, h2_btree bt, int64_t n, const int64_t *rowptr,
+                          const int32_t *col, const double *val, int32_t lower,
+                          h2_mat *out);
+h2_status h2_mat_copy(h2_mat src, h2_mat *out);
+h2_status h2_mat_destroy(h2_mat m);
+/* stored_values: floating point values held by bases, transfers, couplings
+ * and nearfield blocks at the current ranks; max ranks of both bases. */
+h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row,
+                       int32_t *max_rank_col);
+
+/* Local low-rank update Z|_{t0 x s0} += X Y^* of the block tree node
+ * `block` = (t0, s0) (Section 4 for the recompression, Section 5 for the
+ * local update).  X: device, #t0 x k, leading dimension ldx >= #t0;
+ * Y: device, #s0 x k, ldy >= #s0; 0 <= k <= H2_MAX_UPDATE_RANK.  Truncation per tr.
+ * A zero X or Y (or k = 0) leaves Z unchanged.  On H2_ERR_RANK_CAP the matrix
+ * is poisoned (H2_ERR_STATE on later calls). */
+h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X, int64_t ldx,
+                            const double *Y, int64_t ldy, const h2_trunc *tr);
+
+/* y = alpha op(Z) x + beta y, op = identity (trans = 0) or transpose.
+ * x, y: device, n x nrhs column-major (leading dimension n), original order,
+ * 1 <= nrhs <= H2_MAX_COLS.  Evaluated by forward transformation, coupling,
+ * backward transformation and nearfield products (linear complexity, as
+ * stated in the abstract and for the k matrix-vector products of Section 6,
+ * Case 2). */
+h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, double beta,
+                    double *y, int32_t nrhs);
+
+/* In-place approximate Cholesky factorisation A = L L^* of a matrix created
+ * with lower != 0 (Section 3 recursion with R = L^*, block substitution and
+ * products expressed by local low-rank updates; Section 7 uses it as the
+ * preconditioner).  Fails with H2_ERR_NOT_SPD (message names the leaf) or
+ * H2_ERR_RANK_CAP; the matrix is then poisoned. */
+h2_status h2_cholesky(h2_mat a, const h2_trunc *tr);
+
+/* z = (L L^*)^{-1} r by forward and backward substitution with the factor
+ * (Section 3, block forward substitution with vector right-hand sides).
+ * r, z: device, n x nrhs, original order; r and z may alias. */
+h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs);
+
+/* ------------------------------------------------------- sparse A and PCG */
+/* Device copy of a CSR matrix (host arrays, original order). */
+h2_status h2_csr_create(h2_ctx ctx, int64_t n, const int64_t *rowptr, const int32_t *col,
+                        const double *val, h2_csr *out);
+h2_status h2_csr_destroy(h2_csr a);
+/* y = A x, device vectors of length n. */
+h2_status h2_spmv(h2_csr a, const double *x, double *y);
+
+/* Preconditioned conjugate gradients (Section 1; stopping rule of Section 7)
+ * for A x = b with preconditioner (L L^*)^{-1}: x0 = 0, stop when the
+ * recursive residual satisfies ||r||_2 <= rtol ||b||_2.  b, x: device,
+ * length n, original order.  iters: products with A performed; relres: final
+ * ||r||/||b||.  Returns H2_ERR_NOT_CONVERGED if maxit is reached. */
+h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit,
+                 int32_t *iters, double *relres);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2LR_H */

@@ -1,0 +1,982 @@
+// Host side of the h2lr C ABI: trees, H^2 storage in flat device arrays,
+// the planner that turns the recursive algorithms into task lists, and the
+// launches of the task interpreter and helper kernels.
+#include "tasks.hip"
+#include "h2lr.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace h2;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct H2Error : std::runtime_error {
+  h2_status code;
+  H2Error(h2_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
+      throw H2Error(e_ == hipErrorOutOfMemory ? H2_ERR_NOMEM : H2_ERR_HIP,           \
+                    std::string(#x) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+#define REQUIRE(cond, msg) \
+  do { if (!(cond)) throw H2Error(H2_ERR_ARG, msg); } while (0)
+
+template <class F>
+h2_status guarded(F &&f) {
+  try {
+    f();
+    return H2_OK;
+  } catch (const H2Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return H2_ERR_NOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return H2_ERR_HIP;
+  }
+}
+
+// Owning device allocation.
+template <class T>
+struct Dev {
+  T *p = nullptr;
+  size_t n = 0;
+  Dev() = default;
+  Dev(const Dev &) = delete;
+  Dev &operator=(const Dev &) = delete;
+  ~Dev() { if (p) (void)hipFree(p); }
+  void alloc(size_t count) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    n = count;
+    if (count) HIPCHK(hipMalloc(&p, count * sizeof(T)));
+  }
+  void upload(const std::vector<T> &h, hipStream_t s) {
+    alloc(h.size());
+    if (n) HIPCHK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void zero(hipStream_t s) { if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
+};
+
+}  // namespace
+
+// ====================================================================== ctx
+struct h2_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+};
+
+// ============================================================= cluster tree
+struct h2_ctree_s {
+  h2_ctx ctx;
+  int64_t n = 0;
+  int dim = 0, leaf = 0, nc = 0, depth = 0, nlev = 0;
+  std::vector<int64_t> perm;
+  std::vector<int> offset, size, level, son0, son1, parent;
+  std::vector<int64_t> lo, hi;   // nc x dim
+  std::vector<int> desc_lo, desc_hi;
+  Dev<int64_t> d_perm;
+  Dev<int> d_offset, d_size, d_level, d_son0, d_son1, d_parent, d_desc_lo, d_desc_hi;
+};
+
+static void build_ctree(h2_ctree_s &ct, const int32_t *coords) {
+  const int64_t n = ct.n;
+  const int dim = ct.dim;
+  ct.perm.resize(n);
+  for (int64_t i = 0; i < n; ++i) ct.perm[i] = i;
+  std::deque<int> q;
+  auto add = [&](int off, int sz, int lev, int par) {
+    const int id = (int)ct.offset.size();
+    ct.offset.push_back(off); ct.size.push_back(sz); ct.level.push_back(lev);
+    ct.son0.push_back(-1); ct.son1.push_back(-1); ct.parent.push_back(par);
+    for (int d = 0; d < dim; ++d) {
+      int64_t a = INT64_MAX, b = INT64_MIN;
+      for (int i = off; i < off + sz; ++i) {
+        const int64_t v = coords[ct.perm[i] * dim + d];
+        a = std::min(a, v); b = std::max(b, v);
+      }
+      ct.lo.push_back(a); ct.hi.push_back(b);
+    }
+    q.push_back(id);
+    return id;
+  };
+  add(0, (int)n, 0, -1);
+  while (!q.empty()) {
+    const int t = q.front();
+    q.pop_front();
+    const int off = ct.offset[t], sz = ct.size[t];
+    if (sz <= ct.leaf) continue;
+    int dsplit = 0;
+    int64_t best = -1;
+    for (int d = 0; d < dim; ++d) {
+      const int64_t ext = ct.hi[t * dim + d] - ct.lo[t * dim + d];
+      if (ext > best) { best = ext; dsplit = d; }
+    }
+    const int64_t mid2 = ct.lo[t * dim + dsplit] + ct.hi[t * dim + dsplit];
+    auto first = ct.perm.begin() + off;
+    auto mid = std::stable_partition(first, first + sz, [&](int64_t idx) {
+      return 2 * (int64_t)coords[idx * dim + dsplit] <= mid2;
+    });
+    const int n0 = (int)(mid - first);
+    if (n0 <= 0 || n0 >= sz) throw H2Error(H2_ERR_ARG, "cluster cannot be split (duplicate points?)");
+    const int s0 = add(off, n0, ct.level[t] + 1, t);
+    const int s1 = add(off + n0, sz - n0, ct.level[t] + 1, t);
+    ct.son0[t] = s0; ct.son1[t] = s1;
+  }
+  ct.nc = (int)ct.offset.size();
+  ct.depth = *std::max_element(ct.level.begin(), ct.level.end());
+  ct.nlev = ct.depth + 1;
+  // descendants of every cluster per level: contiguous id ranges (BFS order)
+  ct.desc_lo.assign((size_t)ct.nc * ct.nlev, 0);
+  ct.desc_hi.assign((size_t)ct.nc * ct.nlev, 0);
+  for (int t = 0; t < ct.nc; ++t) {
+    int a = t, b = t + 1;
+    for (int lv = ct.level[t]; lv < ct.nlev; ++lv) {
+      ct.desc_lo[(size_t)t * ct.nlev + lv] = a;
+      ct.desc_hi[(size_t)t * ct.nlev + lv] = b;
+      int na = -1, nb = -1;
+      for (int c = a; c < b; ++c) {
+        if (ct.son0[c] >= 0) {
+          if (na < 0) na = ct.son0[c];
+          nb = ct.son1[c] + 1;
+        }
+      }
+      if (na < 0) { a = b = 0; } else { a = na; b = nb; }
+    }
+  }
+}
+
+// =============================================================== block tree
+struct h2_btree_s {
+  h2_ctx ctx;
+  h2_ctree ct;
+  double eta = 2.0;
+  int nb = 0;
+  std::vector<int> row, col, kind, parent, first, nsons;
+  std::unordered_map<int64_t, int> index;
+  Dev<int> d_row, d_col, d_kind, d_first, d_nsons;
+  int find(int t, int s) const {
+    auto it = index.find((int64_t)t * ct->nc + s);
+    return it == index.end() ? -1 : it->second;
+  }
+};
+
+static bool admissible(const h2_ctree_s &ct, int t, int s, double eta2) {
+  int64_t dt = 0, ds = 0, dist = 0;
+  for (int d = 0; d < ct.dim; ++d) {
+    const int64_t lt = ct.lo[t * ct.dim + d], ht = ct.hi[t * ct.dim + d];
+    const int64_t ls = ct.lo[s * ct.dim + d], hs = ct.hi[s * ct.dim + d];
+    dt += (ht - lt) * (ht - lt);
+    ds += (hs - ls) * (hs - ls);
+    const int64_t g = std::max<int64_t>(0, std::max(ls - ht, lt - hs));
+    dist += g * g;
+  }
+  return dist > 0 && (double)std::max(dt, ds) <= eta2 * (double)dist;
+}
+
+static void build_btree(h2_btree_s &bt) {
+  const h2_ctree_s &ct = *bt.ct;
+  const double eta2 = bt.eta * bt.eta;
+  std::deque<int> q;
+  auto add = [&](int t, int s, int par) {
+    bt.row.push_back(t); bt.col.push_back(s); bt.parent.push_back(par);
+    bt.kind.push_back(0); bt.first.push_back(-1); bt.nsons.push_back(0);
+    q.push_back((int)bt.row.size() - 1);
+  };
+  add(0, 0, -1);
+  while (!q.empty()) {
+    const int b = q.front();
+    q.pop_front();
+    const int t = bt.row[b], s = bt.col[b];
+    if (admissible(ct, t, s, eta2)) { bt.kind[b] = 1; continue; }
+    const bool lt = ct.son0[t] < 0, ls = ct.son0[s] < 0;
+    if (lt && ls) { bt.kind[b] = 2; continue; }
+    bt.first[b] = (int)bt.row.size();
+    int cnt = 0;
+    const int ts[2] = {lt ? t : ct.son0[t], ct.son1[t]};
+    const int ss[2] = {ls ? s : ct.son0[s], ct.son1[s]};
+    for (int i = 0; i < (lt ? 1 : 2); ++i)
+      for (int j = 0; j < (ls ? 1 : 2); ++j) { add(ts[i], ss[j], b); ++cnt; }
+    bt.nsons[b] = cnt;
+  }
+  bt.nb = (int)bt.row.size();
+  bt.index.reserve(bt.nb * 2);
+  for (int b = 0; b < bt.nb; ++b) bt.index[(int64_t)bt.row[b] * ct.nc + bt.col[b]] = b;
+}
+
+// ================================================================= matrices
+struct h2_csr_s {
+  h2_ctx ctx;
+  int64_t n = 0;
+  Dev<int64_t> rp;
+  Dev<int> ci;
+  Dev<double> v;
+};
+
+struct TaskList {
+  Dev<Task> d;
+  int count = 0;
+  bool built = false;
+};
+
+struct h2_mat_s {
+  h2_ctx ctx;
+  h2_btree bt;
+  bool lower = false;
+  bool poisoned = false;
+  int nadm = 0, nnear = 0;
+  std::vector<int> bslot, adm, nearb;
+  std::vector<int> rowptr, rowidx, colptr, colidx, nrowptr, nrowidx, ncolptr, ncolidx;
+  Dev<int> d_bslot, d_rowptr, d_rowidx, d_colptr, d_colidx, d_nrowptr, d_nrowidx, d_ncolptr,
+      d_ncolidx;
+  Dev<int> d_k[2], d_rho_m[2], d_wrho_m[2], d_wB_m[2], d_wnewk[2], d_bcols, d_err;
+  Dev<double> d_leaf[2], d_E[2], d_rho[2], d_wrho[2], d_wB[2], d_wR[2], d_S, d_N, d_xh, d_yh, d_buf;
+  Dev<double> d_pcg;   // PCG vectors and scalars
+  TaskList chol, prec;
+  DevEnv env{};
+};
+
+// Device copies of the tree tables, made when the first matrix needs them.
+static void trees_to_device(h2_btree_s &bt, hipStream_t s) {
+  h2_ctree_s &ct = *bt.ct;
+  if (!ct.d_offset.p) {
+    ct.d_perm.upload(ct.perm, s);
+    ct.d_offset.upload(ct.offset, s); ct.d_size.upload(ct.size, s);
+    ct.d_level.upload(ct.level, s); ct.d_son0.upload(ct.son0, s);
+    ct.d_son1.upload(ct.son1, s); ct.d_parent.upload(ct.parent, s);
+    ct.d_desc_lo.upload(ct.desc_lo, s); ct.d_desc_hi.upload(ct.desc_hi, s);
+  }
+  if (!bt.d_row.p) {
+    bt.d_row.upload(bt.row, s); bt.d_col.upload(bt.col, s); bt.d_kind.upload(bt.kind, s);
+    bt.d_first.upload(bt.first, s); bt.d_nsons.upload(bt.nsons, s);
+  }
+}
+
+static void mat_alloc(h2_mat_s &m) {
+  const h2_ctree_s &ct = *m.bt->ct;
+  const size_t nc = ct.nc;
+  hipStream_t s = m.ctx->stream;
+  for (int side = 0; side < 2; ++side) {
+    m.d_k[side].alloc(nc); m.d_k[side].zero(s);
+    m.d_rho_m[side].alloc(nc); m.d_rho_m[side].zero(s);
+    m.d_wrho_m[side].alloc(nc); m.d_wB_m[side].alloc(nc); m.d_wnewk[side].alloc(nc);
+    m.d_leaf[side].alloc(nc * LS * KC);
+    m.d_E[side].alloc(nc * KC * KC);
+    m.d_rho[side].alloc(nc * KC * KC);
+    m.d_wrho[side].alloc(nc * KM * KM);
+    m.d_wB[side].alloc(nc * KM * KM);
+    m.d_wR[side].alloc(nc * KM * KM);
+  }
+  m.d_S.alloc((size_t)std::max(m.nadm, 1) * KC * KC);
+  m.d_N.alloc((size_t)std::max(m.nnear, 1) * LS * LS);
+  m.d_xh.alloc(nc * KC * BC);
+  m.d_yh.alloc(nc * KC * BC);
+  m.d_buf.alloc((size_t)NBUF * ct.n * BC);
+  m.d_bcols.alloc(NBUF); m.d_bcols.zero(s);
+  m.d_err.alloc(4); m.d_err.zero(s);
+}
+
+static void mat_lists(h2_mat_s &m) {
+  const h2_btree_s &bt = *m.bt;
+  const h2_ctree_s &ct = *bt.ct;
+  m.bslot.assign(bt.nb, -1);
+  m.adm.clear(); m.nearb.clear();
+  for (int b = 0; b < bt.nb; ++b) {
+    if (bt.kind[b] == 0) continue;
+    const int t = bt.row[b], s = bt.col[b];
+    if (m.lower && !(t == s || ct.offset[t] > ct.offset[s])) continue;
+    if (bt.kind[b] == 1) { m.bslot[b] = (int)m.adm.size(); m.adm.push_back(b); }
+    else { m.bslot[b] = (int)m.nearb.size(); m.nearb.push_back(b); }
+  }
+  m.nadm = (int)m.adm.size();
+  m.nnear = (int)m.nearb.size();
+  auto csr = [&](const std::vector<int> &blocks, bool byrow, std::vector<int> &ptr, std::vector<int> &idx) {
+    ptr.assign(ct.nc + 1, 0);
+    for (int b : blocks) ptr[(byrow ? bt.row[b] : bt.col[b]) + 1]++;
+    for (int c = 0; c < ct.nc; ++c) ptr[c + 1] += ptr[c];
+    idx.assign(blocks.size(), 0);
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int b : blocks) idx[fill[byrow ? bt.row[b] : bt.col[b]]++] = b;   // blocks ascend by id
+  };
+  csr(m.adm, true, m.rowptr, m.rowidx);
+  csr(m.adm, false, m.colptr, m.colidx);
+  csr(m.nearb, true, m.nrowptr, m.nrowidx);
+  csr(m.nearb, false, m.ncolptr, m.ncolidx);
+  hipStream_t s = m.ctx->stream;
+  m.d_bslot.upload(m.bslot, s);
+  m.d_rowptr.upload(m.rowptr, s); m.d_rowidx.upload(m.rowidx, s);
+  m.d_colptr.upload(m.colptr, s); m.d_colidx.upload(m.colidx, s);
+  m.d_nrowptr.upload(m.nrowptr, s); m.d_nrowidx.upload(m.nrowidx, s);
+  m.d_ncolptr.upload(m.ncolptr, s); m.d_ncolidx.upload(m.ncolidx, s);
+}
+
+static void mat_env(h2_mat_s &m) {
+  const h2_ctree_s &ct = *m.bt->ct;
+  const h2_btree_s &bt = *m.bt;
+  DevEnv &e = m.env;
+  e.n = (int)ct.n; e.nc = ct.nc; e.depth = ct.depth; e.nlev = ct.nlev;
+  e.rank_cap = KC; e.mode = 0; e.eps = 0.0;
+  e.offset = ct.d_offset.p; e.size = ct.d_size.p; e.son0 = ct.d_son0.p; e.son1 = ct.d_son1.p;
+  e.parent = ct.d_parent.p; e.level = ct.d_level.p; e.desc_lo = ct.d_desc_lo.p; e.desc_hi = ct.d_desc_hi.p;
+  e.brow = bt.d_row.p; e.bcol = bt.d_col.p; e.bkind = bt.d_kind.p; e.bfirst = bt.d_first.p;
+  e.bnsons = bt.d_nsons.p; e.bslot = m.d_bslot.p;
+  e.rowptr = m.d_rowptr.p; e.rowidx = m.d_rowidx.p; e.colptr = m.d_colptr.p; e.colidx = m.d_colidx.p;
+  e.nrowptr = m.d_nrowptr.p; e.nrowidx = m.d_nrowidx.p; e.ncolptr = m.d_ncolptr.p; e.ncolidx = m.d_ncolidx.p;
+  for (int side = 0; side < 2; ++side) {
+    e.k[side] = m.d_k[side].p; e.leaf[side] = m.d_leaf[side].p; e.E[side] = m.d_E[side].p;
+    e.rho[side] = m.d_rho[side].p; e.rho_m[side] = m.d_rho_m[side].p;
+    e.wrho[side] = m.d_wrho[side].p; e.wrho_m[side] = m.d_wrho_m[side].p;
+    e.wB[side] = m.d_wB[side].p; e.wB_m[side] = m.d_wB_m[side].p;
+    e.wR[side] = m.d_wR[side].p; e.wnewk[side] = m.d_wnewk[side].p;
+  }
+  e.S = m.d_S.p; e.N = m.d_N.p; e.xh = m.d_xh.p; e.yh = m.d_yh.p;
+  for (int i = 0; i < NBUF; ++i) e.buf[i] = m.d_buf.p + (size_t)i * ct.n * BC;
+  e.bcols = m.d_bcols.p; e.err = m.d_err.p;
+}
+
+// ================================================================== planner
+// Turns the recursive algorithms into task lists; see tasks.hip for the
+// meaning of each task.  The recursion follows Section 3 (product, block
+// substitution, LR/Cholesky) and Section 6 (Cases 1 and 2).
+struct Planner {
+  const h2_mat_s &M;
+  const h2_ctree_s &ct;
+  const h2_btree_s &bt;
+  std::vector<Task> &T;
+  Planner(const h2_mat_s &m, std::vector<Task> &t) : M(m), ct(*m.bt->ct), bt(*m.bt), T(t) {}
+
+  void emit(int op, int a = 0, int b = 0, int c = 0, int d = 0, int e_ = 0, int f = 0, int g = 0,
+            int h = 0, double alpha = 0.0, double beta = 0.0) {
+    Task k{};
+    k.op = op;
+    k.i[0] = a; k.i[1] = b; k.i[2] = c; k.i[3] = d; k.i[4] = e_; k.i[5] = f; k.i[6] = g; k.i[7] = h;
+    k.alpha = alpha; k.beta = beta;
+    T.push_back(k);
+  }
+  int find(int t, int s) const {
+    const int b = bt.find(t, s);
+    if (b < 0) throw H2Error(H2_ERR_ARG, "internal: block not in tree");
+    return b;
+  }
+  bool leaf(int t) const { return ct.son0[t] < 0; }
+  std::vector<int> sons_plus(int t) const {
+    if (leaf(t)) return {t};
+    return {ct.son0[t], ct.son1[t]};
+  }
+  static int TU(int p) { return B_T0U + 2 * p; }
+  static int TV(int p) { return B_T0V + 2 * p; }
+
+  void bapply(int b, int trans, int bin, int bout, double alpha, double beta) {
+    emit(OP_BAPPLY, b, trans, bin, bout, 0, 0, 0, 0, alpha, beta);
+  }
+  void addlr(int b, int bu, int bv) { emit(OP_ADDLR, b, bu, bv); }
+
+  void fsolve(int c, int buf) {
+    if (leaf(c)) { emit(OP_TRSV, find(c, c), buf, 0); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    fsolve(c1, buf);
+    bapply(find(c2, c1), 0, buf, buf, -1.0, 1.0);
+    fsolve(c2, buf);
+  }
+  void bsolve(int c, int buf) {
+    if (leaf(c)) { emit(OP_TRSV, find(c, c), buf, 1); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    bsolve(c2, buf);
+    bapply(find(c2, c1), 1, buf, buf, -1.0, 1.0);
+    bsolve(c1, buf);
+  }
+
+  // Z(t, r) += alpha X(t, s) Y(r, s)^* with X, Y, Z blocks of the factor.
+  void mm(int t, int s, int r, double alpha, int tmp, int tT, int rT) {
+    const int bX = find(t, s), bY = find(r, s);
+    if (bt.kind[bX] == 0 && bt.kind[bY] == 0) {
+      const auto ts = sons_plus(t), ss = sons_plus(s), rs = sons_plus(r);
+      if (tmp >= 0) {
+        for (int s2 : ss) for (int t2 : ts) for (int r2 : rs) mm(t2, s2, r2, alpha, tmp, tT, rT);
+        return;
+      }
+      const int bZ = find(t, r);
+      if (bt.kind[bZ] == 0) {
+        for (int s2 : ss)
+          for (int t2 : ts)
+            for (int r2 : rs) {
+              if (ct.offset[t2] < ct.offset[r2]) continue;   // above the diagonal
+              mm(t2, s2, r2, alpha, -1, 0, 0);
+            }
+      } else if (bt.kind[bZ] == 2) {
+        const int ns = ct.size[s];
+        for (int c0 = 0; c0 < ns; c0 += BC) {
+          const int nc = std::min(BC, ns - c0);
+          emit(OP_IDENT, s, B_I, c0, nc);
+          bapply(bX, 0, B_I, B_A, 1.0, 0.0);
+          bapply(bY, 0, B_I, B_B, 1.0, 0.0);
+          emit(OP_NEAR_ADD, bZ, B_A, B_B, 0, 0, 0, 0, 0, alpha);
+        }
+      } else {
+        std::vector<std::pair<int, int>> pairs;
+        for (int t2 : ts) for (int r2 : rs) pairs.push_back({t2, r2});
+        for (size_t p = 0; p < pairs.size(); ++p) emit(OP_TEMP_INIT, TU((int)p), TV((int)p), t, r);
+        for (int s2 : ss)
+          for (int t2 : ts)
+            for (int r2 : rs) {
+              int p = 0;
+              while (pairs[p].first != t2 || pairs[p].second != r2) ++p;
+              mm(t2, s2, r2, alpha, p, t2, r2);
+            }
+        for (size_t p = 0; p < pairs.size(); ++p) addlr(bZ, TU((int)p), TV((int)p));
+      }
+      return;
+    }
+    // Case 2: a factor is a leaf -> low-rank emission (U, V)
+    if (bt.kind[bY] == 1) {
+      emit(OP_EXPAND, 1, s, B_W);
+      bapply(bX, 0, B_W, B_A, 1.0, 0.0);
+      emit(OP_RMUL_S, B_A, B_U, bY, 1, t, 0, 0, 0, alpha);
+      emit(OP_EXPAND, 0, r, B_V);
+    } else if (bt.kind[bX] == 1) {
+      emit(OP_EXPAND, 0, t, B_A);
+      emit(OP_RMUL_S, B_A, B_U, bX, 0, t, 0, 0, 0, alpha);
+      emit(OP_EXPAND, 1, s, B_W);
+      bapply(bY, 0, B_W, B_V, 1.0, 0.0);
+    } else if (bt.kind[bX] == 2) {
+      emit(OP_COPY_NEAR, bX, B_U, 0, 0, 0, 0, 0, 0, alpha);
+      emit(OP_IDENT, s, B_I, 0, ct.size[s]);
+      bapply(bY, 0, B_I, B_V, 1.0, 0.0);
+    } else {
+      emit(OP_IDENT, s, B_I, 0, ct.size[s]);
+      bapply(bX, 0, B_I, B_U, alpha, 0.0);
+      emit(OP_COPY_NEAR, bY, B_V, 0, 0, 0, 0, 0, 0, 1.0);
+    }
+    if (tmp >= 0) {
+      emit(OP_TEMP_ADD, TU(tmp), TV(tmp), t, r, B_U, B_V, tT, rT);
+    } else {
+      const int bZ = find(t, r);
+      if (bt.kind[bZ] == 2) emit(OP_NEAR_ADD, bZ, B_U, B_V, 0, 0, 0, 0, 0, 1.0);
+      else addlr(bZ, B_U, B_V);
+    }
+  }
+
+  // X L_cc^* = Y on block b = (r, c), in place.
+  void rsolve(int c, int b) {
+    const int r = bt.row[b];
+    if (bt.kind[b] == 0) {
+      if (leaf(c)) {
+        for (int r2 : sons_plus(r)) rsolve(c, find(r2, c));
+        return;
+      }
+      const int c1 = ct.son0[c], c2 = ct.son1[c];
+      const auto rs = sons_plus(r);
+      for (int r2 : rs) rsolve(c1, find(r2, c1));
+      for (int r2 : rs) mm(r2, c1, c2, -1.0, -1, 0, 0);
+      for (int r2 : rs) rsolve(c2, find(r2, c2));
+    } else if (bt.kind[b] == 2) {
+      emit(OP_TRSM, b, find(c, c));
+    } else {
+      emit(OP_EXPAND, 1, c, B_W);
+      emit(OP_COPY, B_W, B_WP, c);
+      fsolve(c, B_WP);
+      emit(OP_SUB, B_WP, B_W, B_V, c);
+      emit(OP_EXPAND, 0, r, B_A);
+      emit(OP_RMUL_S, B_A, B_U, b, 0, r, 0, 0, 0, 1.0);
+      addlr(b, B_U, B_V);
+    }
+  }
+
+  void chol(int t) {
+    if (leaf(t)) { emit(OP_POTRF, find(t, t), t); return; }
+    const int t1 = ct.son0[t], t2 = ct.son1[t];
+    chol(t1);
+    rsolve(t1, find(t2, t1));
+    mm(t2, t1, t2, -1.0, -1, 0, 0);
+    chol(t2);
+  }
+};
+
+static void upload_tasks(h2_mat_s &m, TaskList &tl, const std::vector<Task> &tasks) {
+  tl.d.alloc(tasks.size());
+  if (!tasks.empty())
+    HIPCHK(hipMemcpy(tl.d.p, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
+  tl.count = (int)tasks.size();
+  tl.built = true;
+}
+
+static void set_trunc(h2_mat_s &m, const h2_trunc *tr) {
+  if (!tr) { m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; return; }
+  REQUIRE(tr->mode >= 0 && tr->mode <= 2, "truncation mode must be 0, 1 or 2");
+  REQUIRE(tr->rank_cap >= 1 && tr->rank_cap <= KC, "rank_cap must be in [1, H2_MAX_RANK]");
+  REQUIRE(tr->eps >= 0.0 && std::isfinite(tr->eps), "eps must be finite and >= 0");
+  m.env.eps = tr->eps; m.env.mode = tr->mode; m.env.rank_cap = tr->rank_cap;
+}
+
+static bool g_lds_attr_set = false;
+
+static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
+  const size_t lds = LDS_DOUBLES * sizeof(double);
+  if (!g_lds_attr_set) {
+    HIPCHK(hipFuncSetAttribute((const void *)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    g_lds_attr_set = true;
+  }
+  const int seg = 1 << 18;
+  for (int off = 0; off < count; off += seg) {
+    const int cnt = std::min(seg, count - off);
+    hipLaunchKernelGGL(k_interp, dim3(1), dim3(NT), lds, m.ctx->stream, d_tasks + off, cnt, m.env);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+static void check_device_error(h2_mat_s &m) {
+  int err[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(err, m.d_err.p, 2 * sizeof(int), hipMemcpyDeviceToHost, m.ctx->stream));
+  HIPCHK(hipStreamSynchronize(m.ctx->stream));
+  if (err[0] != 0) {
+    m.poisoned = true;
+    char msg[160];
+    if (err[0] == E_NOT_SPD) {
+      snprintf(msg, sizeof msg, "leaf block of cluster %d is not positive definite", err[1]);
+      throw H2Error(H2_ERR_NOT_SPD, msg);
+    }
+    if (err[0] == E_RANK_CAP) {
+      snprintf(msg, sizeof msg, "rank cap exceeded at cluster %d", err[1]);
+      throw H2Error(H2_ERR_RANK_CAP, msg);
+    }
+    snprintf(msg, sizeof msg, "device task failed (code %d, info %d)", err[0], err[1]);
+    throw H2Error(H2_ERR_ARG, msg);
+  }
+}
+
+static void require_ok(h2_mat m) {
+  REQUIRE(m != nullptr, "null matrix");
+  if (m->poisoned) throw H2Error(H2_ERR_STATE, "matrix poisoned by an earlier failure");
+}
+
+static int grid_for(long work) {
+  long g = (work + 255) / 256;
+  return (int)std::max<long>(1, std::min<long>(g, 4096));
+}
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *h2_last_error(void) { return g_last_error.c_str(); }
+
+h2_status h2_ctx_create(int device, void *stream, h2_ctx *out) {
+  return guarded([&] {
+    REQUIRE(out != nullptr, "null output");
+    REQUIRE(device >= -1, "device must be >= -1");
+    if (device >= 0) HIPCHK(hipSetDevice(device));
+    auto c = std::make_unique<h2_ctx_s>();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c.release();
+  });
+}
+
+h2_status h2_ctx_destroy(h2_ctx ctx) {
+  delete ctx;
+  return H2_OK;
+}
+
+h2_status h2_ctx_synchronize(h2_ctx ctx) {
+  return guarded([&] {
+    REQUIRE(ctx != nullptr, "null context");
+    if (ctx->device >= 0) HIPCHK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+h2_status h2_ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords, int32_t leaf_size,
+                         h2_ctree *out) {
+  return guarded([&] {
+    REQUIRE(ctx && coords && out, "null argument");
+    REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
+    REQUIRE(n >= 1 && n < (int64_t)1 << 30, "n out of range");
+    REQUIRE(leaf_size >= 1 && leaf_size <= H2_MAX_LEAF, "leaf_size must be 1..H2_MAX_LEAF");
+    auto ct = std::make_unique<h2_ctree_s>();
+    ct->ctx = ctx; ct->n = n; ct->dim = dim; ct->leaf = leaf_size;
+    build_ctree(*ct, coords);
+    *out = ct.release();
+  });
+}
+
+h2_status h2_ctree_info(h2_ctree ct, int64_t *n, int64_t *nclusters, int32_t *depth) {
+  return guarded([&] {
+    REQUIRE(ct != nullptr, "null tree");
+    if (n) *n = ct->n;
+    if (nclusters) *nclusters = ct->nc;
+    if (depth) *depth = ct->depth;
+  });
+}
+
+h2_status h2_ctree_export(h2_ctree ct, int64_t *perm, int32_t *offset, int32_t *size, int32_t *level,
+                          int32_t *son0, int32_t *son1, int32_t *parent) {
+  return guarded([&] {
+    REQUIRE(ct != nullptr, "null tree");
+    if (perm) std::copy(ct->perm.begin(), ct->perm.end(), perm);
+    auto cp = [&](const std::vector<int> &v, int32_t *dst) { if (dst) std::copy(v.begin(), v.end(), dst); };
+    cp(ct->offset, offset); cp(ct->size, size); cp(ct->level, level);
+    cp(ct->son0, son0); cp(ct->son1, son1); cp(ct->parent, parent);
+  });
+}
+
+h2_status h2_ctree_destroy(h2_ctree ct) {
+  delete ct;
+  return H2_OK;
+}
+
+h2_status h2_btree_build(h2_ctx ctx, h2_ctree ct, double eta, h2_btree *out) {
+  return guarded([&] {
+    REQUIRE(ctx && ct && out, "null argument");
+    REQUIRE(eta > 0.0 && std::isfinite(eta), "eta must be positive");
+    auto bt = std::make_unique<h2_btree_s>();
+    bt->ctx = ctx; bt->ct = ct; bt->eta = eta;
+    build_btree(*bt);
+    *out = bt.release();
+  });
+}
+
+h2_status h2_btree_info(h2_btree bt, int64_t *nblocks, int64_t *nadm, int64_t *nnear, int32_t *csp) {
+  return guarded([&] {
+    REQUIRE(bt != nullptr, "null tree");
+    int64_t a = 0, nn = 0;
+    std::vector<int> cnt(bt->ct->nc, 0);
+    for (int b = 0; b < bt->nb; ++b) {
+      if (bt->kind[b] == 1) { ++a; cnt[bt->row[b]]++; }
+      if (bt->kind[b] == 2) ++nn;
+    }
+    if (nblocks) *nblocks = bt->nb;
+    if (nadm) *nadm = a;
+    if (nnear) *nnear = nn;
+    if (csp) *csp = cnt.empty() ? 0 : *std::max_element(cnt.begin(), cnt.end());
+  });
+}
+
+h2_status h2_btree_export(h2_btree bt, int32_t *row, int32_t *col, int32_t *kind, int32_t *parent) {
+  return guarded([&] {
+    REQUIRE(bt != nullptr, "null tree");
+    auto cp = [&](const std::vector<int> &v, int32_t *dst) { if (dst) std::copy(v.begin(), v.end(), dst); };
+    cp(bt->row, row); cp(bt->col, col); cp(bt->kind, kind); cp(bt->parent, parent);
+  });
+}
+
+h2_status h2_btree_find(h2_btree bt, int64_t t, int64_t s, int64_t *block) {
+  return guarded([&] {
+    REQUIRE(bt && block, "null argument");
+    REQUIRE(t >= 0 && s >= 0 && t < bt->ct->nc && s < bt->ct->nc, "cluster out of range");
+    *block = bt->find((int)t, (int)s);
+  });
+}
+
+h2_status h2_btree_destroy(h2_btree bt) {
+  delete bt;
+  return H2_OK;
+}
+
+h2_status h2_mat_from_csr(h2_ctx ctx, h2_btree bt, int64_t n, const int64_t *rowptr, const int32_t *col,
+                          const double *val, int32_t lower, h2_mat *out) {
+  return guarded([&] {
+    REQUIRE(ctx && bt && rowptr && col && val && out, "null argument");
+    const h2_ctree_s &ct = *bt->ct;
+    REQUIRE(n == ct.n, "matrix size does not match the cluster tree");
+    REQUIRE(ctx->device >= 0, "a host-only context cannot hold matrices");
+    trees_to_device(*bt, ctx->stream);
+    auto m = std::make_unique<h2_mat_s>();
+    m->ctx = ctx; m->bt = bt; m->lower = lower != 0;
+    mat_lists(*m);
+    // cluster-order position and leaf of every index
+    std::vector<int> pos(n), leafof(n);
+    for (int64_t i = 0; i < n; ++i) pos[ct.perm[i]] = (int)i;
+    for (int c = 0; c < ct.nc; ++c)
+      if (ct.son0[c] < 0)
+        for (int i = ct.offset[c]; i < ct.offset[c] + ct.size[c]; ++i) leafof[i] = c;
+    std::vector<double> N((size_t)std::max(m->nnear, 1) * LS * LS, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        const double v = val[p];
+        if (v == 0.0) continue;
+        const int j = col[p];
+        REQUIRE(j >= 0 && j < n, "column index out of range");
+        const int ci = pos[i], cj = pos[j];
+        const int t = leafof[ci], s = leafof[cj];
+        const int b = bt->find(t, s);
+        if (b < 0 || bt->kind[b] != 2)
+          throw H2Error(H2_ERR_NONZERO_FARFIELD, "non-zero entry in an admissible block");
+        const int slot = m->bslot[b];
+        if (slot < 0) continue;   // upper triangle of a lower-stored matrix
+        N[(size_t)slot * LS * LS + (ci - ct.offset[t]) + (size_t)(cj - ct.offset[s]) * LS] += v;
+      }
+    }
+    mat_alloc(*m);
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemcpyAsync(m->d_N.p, N.data(), N.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    mat_env(*m);
+    HIPCHK(hipStreamSynchronize(s));
+    *out = m.release();
+  });
+}
+
+h2_status h2_mat_copy(h2_mat src, h2_mat *out) {
+  return guarded([&] {
+    REQUIRE(src && out, "null argument");
+    require_ok(src);
+    auto m = std::make_unique<h2_mat_s>();
+    m->ctx = src->ctx; m->bt = src->bt; m->lower = src->lower;
+    mat_lists(*m);
+    mat_alloc(*m);
+    hipStream_t s = src->ctx->stream;
+    auto cp = [&](auto &dst, auto &from) {
+      if (from.n) HIPCHK(hipMemcpyAsync(dst.p, from.p, from.n * sizeof(*from.p), hipMemcpyDeviceToDevice, s));
+    };
+    for (int side = 0; side < 2; ++side) {
+      cp(m->d_k[side], src->d_k[side]); cp(m->d_rho_m[side], src->d_rho_m[side]);
+      cp(m->d_leaf[side], src->d_leaf[side]); cp(m->d_E[side], src->d_E[side]);
+      cp(m->d_rho[side], src->d_rho[side]);
+    }
+    cp(m->d_S, src->d_S); cp(m->d_N, src->d_N);
+    mat_env(*m);
+    HIPCHK(hipStreamSynchronize(s));
+    *out = m.release();
+  });
+}
+
+h2_status h2_mat_destroy(h2_mat m) {
+  if (m) (void)hipStreamSynchronize(m->ctx->stream);
+  delete m;
+  return H2_OK;
+}
+
+h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row, int32_t *max_rank_col) {
+  return guarded([&] {
+    REQUIRE(m != nullptr, "null matrix");
+    const h2_ctree_s &ct = *m->bt->ct;
+    const h2_btree_s &bt = *m->bt;
+    std::vector<int> k[2];
+    for (int side = 0; side < 2; ++side) {
+      k[side].resize(ct.nc);
+      HIPCHK(hipMemcpyAsync(k[side].data(), m->d_k[side].p, ct.nc * sizeof(int), hipMemcpyDeviceToHost,
+                            m->ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(m->ctx->stream));
+    int64_t vals = 0;
+    for (int side = 0; side < 2; ++side)
+      for (int c = 0; c < ct.nc; ++c) {
+        if (ct.son0[c] < 0) vals += (int64_t)ct.size[c] * k[side][c];
+        if (ct.parent[c] >= 0) vals += (int64_t)k[side][c] * k[side][ct.parent[c]];
+      }
+    for (int b : m->adm) vals += (int64_t)k[0][bt.row[b]] * k[1][bt.col[b]];
+    for (int b : m->nearb) vals += (int64_t)ct.size[bt.row[b]] * ct.size[bt.col[b]];
+    if (stored_values) *stored_values = vals;
+    if (max_rank_row) *max_rank_row = *std::max_element(k[0].begin(), k[0].end());
+    if (max_rank_col) *max_rank_col = *std::max_element(k[1].begin(), k[1].end());
+  });
+}
+
+h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X, int64_t ldx,
+                            const double *Y, int64_t ldy, const h2_trunc *tr) {
+  return guarded([&] {
+    require_ok(z);
+    const h2_btree_s &bt = *z->bt;
+    const h2_ctree_s &ct = *bt.ct;
+    REQUIRE(block >= 0 && block < bt.nb, "block out of range");
+    REQUIRE(k >= 0 && k <= H2_MAX_UPDATE_RANK, "update rank out of range");
+    const int t0 = bt.row[block], s0 = bt.col[block];
+    if (z->lower) REQUIRE(t0 == s0 || ct.offset[t0] > ct.offset[s0], "block above the diagonal of a lower matrix");
+    if (k == 0) return;
+    REQUIRE(X && Y, "null factor");
+    REQUIRE(ldx >= ct.size[t0] && ldy >= ct.size[s0], "leading dimension too small");
+    set_trunc(*z, tr);
+    hipStream_t s = z->ctx->stream;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[t0] * k)), dim3(256), 0, s, ct.size[t0],
+                       ct.offset[t0], k, (const int64_t *)nullptr, X, (long)ldx, z->env.buf[B_X], z->d_bcols.p,
+                       (int)B_X);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[s0] * k)), dim3(256), 0, s, ct.size[s0],
+                       ct.offset[s0], k, (const int64_t *)nullptr, Y, (long)ldy, z->env.buf[B_Y], z->d_bcols.p,
+                       (int)B_Y);
+    HIPCHK(hipGetLastError());
+    std::vector<Task> tasks;
+    Planner(*z, tasks).addlr((int)block, B_X, B_Y);
+    TaskList tl;
+    upload_tasks(*z, tl, tasks);
+    run_tasks(*z, tl.d.p, tl.count);
+    check_device_error(*z);
+  });
+}
+
+h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, double beta, double *y,
+                    int32_t nrhs) {
+  return guarded([&] {
+    require_ok(z);
+    REQUIRE(x && y, "null vector");
+    REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
+    const h2_ctree_s &ct = *z->bt->ct;
+    hipStream_t s = z->ctx->stream;
+    const long work = (long)ct.n * nrhs;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, 0, nrhs, ct.d_perm.p, x,
+                       (long)ct.n, z->env.buf[B_X], z->d_bcols.p, (int)B_X);
+    HIPCHK(hipGetLastError());
+    std::vector<Task> tasks;
+    Planner(*z, tasks).bapply(0, trans ? 1 : 0, B_X, B_Y, 1.0, 0.0);
+    TaskList tl;
+    upload_tasks(*z, tl, tasks);
+    run_tasks(*z, tl.d.p, tl.count);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
+                       z->env.buf[B_Y], y, (long)ct.n, alpha, beta);
+    HIPCHK(hipGetLastError());
+    check_device_error(*z);
+  });
+}
+
+h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
+  return guarded([&] {
+    require_ok(a);
+    REQUIRE(a->lower, "h2_cholesky needs a matrix created with lower != 0");
+    set_trunc(*a, tr);
+    if (!a->chol.built) {
+      std::vector<Task> tasks;
+      Planner(*a, tasks).chol(0);
+      upload_tasks(*a, a->chol, tasks);
+    }
+    run_tasks(*a, a->chol.d.p, a->chol.count);
+    check_device_error(*a);
+  });
+}
+
+static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
+  const h2_ctree_s &ct = *l->bt->ct;
+  hipStream_t s = l->ctx->stream;
+  if (!l->prec.built) {
+    std::vector<Task> tasks;
+    Planner P(*l, tasks);
+    P.fsolve(0, B_X);
+    P.bsolve(0, B_X);
+    upload_tasks(*l, l->prec, tasks);
+  }
+  const long work = (long)ct.n * nrhs;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, 0, nrhs, ct.d_perm.p, r,
+                     (long)ct.n, l->env.buf[B_X], l->d_bcols.p, (int)B_X);
+  HIPCHK(hipGetLastError());
+  run_tasks(*l, l->prec.d.p, l->prec.count);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
+                     l->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
+  HIPCHK(hipGetLastError());
+}
+
+h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs) {
+  return guarded([&] {
+    require_ok(l);
+    REQUIRE(l->lower, "h2_precond needs a Cholesky factor");
+    REQUIRE(r && z, "null vector");
+    REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
+    precond_device(l, r, z, nrhs);
+    check_device_error(*l);
+  });
+}
+
+h2_status h2_csr_create(h2_ctx ctx, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                        h2_csr *out) {
+  return guarded([&] {
+    REQUIRE(ctx && rowptr && col && val && out, "null argument");
+    REQUIRE(n >= 1, "n must be positive");
+    REQUIRE(ctx->device >= 0, "a host-only context cannot hold device data");
+    auto a = std::make_unique<h2_csr_s>();
+    a->ctx = ctx; a->n = n;
+    const int64_t nnz = rowptr[n];
+    std::vector<int64_t> rp(rowptr, rowptr + n + 1);
+    std::vector<int> ci(col, col + nnz);
+    std::vector<double> v(val, val + nnz);
+    a->rp.upload(rp, ctx->stream); a->ci.upload(ci, ctx->stream); a->v.upload(v, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = a.release();
+  });
+}
+
+h2_status h2_csr_destroy(h2_csr a) {
+  delete a;
+  return H2_OK;
+}
+
+h2_status h2_spmv(h2_csr a, const double *x, double *y) {
+  return guarded([&] {
+    REQUIRE(a && x && y, "null argument");
+    hipLaunchKernelGGL(k_spmv, dim3(grid_for(a->n)), dim3(256), 0, a->ctx->stream, (int)a->n, a->rp.p, a->ci.p,
+                       a->v.p, x, y);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit, int32_t *iters,
+                 double *relres) {
+  return guarded([&] {
+    REQUIRE(a && b && x, "null argument");
+    require_ok(l);
+    REQUIRE(l->lower, "h2_pcg needs a Cholesky factor");
+    REQUIRE(a->n == l->bt->ct->n, "size mismatch");
+    REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
+    const int n = (int)a->n;
+    hipStream_t s = l->ctx->stream;
+    const int NP = 256;   // partial sums of the dot products
+    if (l->d_pcg.n < (size_t)4 * n + NP + 8) l->d_pcg.alloc((size_t)4 * n + NP + 8);
+    double *r = l->d_pcg.p, *z = r + n, *p = z + n, *q = p + n, *part = q + n, *sc = part + NP;
+    const int g = grid_for(n);
+    auto dot = [&](const double *u, const double *v, double *dst) {
+      hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, n, u, v, part);
+      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, part, dst);
+    };
+    auto host_scalar = [&](const double *dsrc) {
+      double v = 0.0;
+      HIPCHK(hipMemcpyAsync(&v, dsrc, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      return v;
+    };
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dot(b, b, sc + 4);
+    const double nb = std::sqrt(host_scalar(sc + 4));
+    int it = 0;
+    double rel = 0.0;
+    if (nb == 0.0) {
+      if (iters) *iters = 0;
+      if (relres) *relres = 0.0;
+      return;
+    }
+    precond_device(l, r, z, 1);
+    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dot(r, z, sc + 0);
+    bool conv = false;
+    while (it < maxit) {
+      hipLaunchKernelGGL(k_spmv, dim3(g), dim3(256), 0, s, n, a->rp.p, a->ci.p, a->v.p, p, q);
+      ++it;
+      dot(p, q, sc + 1);
+      hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, sc, p, q, x, r);
+      dot(r, r, sc + 3);
+      rel = std::sqrt(host_scalar(sc + 3)) / nb;
+      if (rel <= rtol) { conv = true; break; }
+      precond_device(l, r, z, 1);
+      dot(r, z, sc + 2);
+      hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, sc, z, p);
+      hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, sc + 0, sc + 2);
+    }
+    HIPCHK(hipGetLastError());
+    check_device_error(*l);
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (!conv) throw H2Error(H2_ERR_NOT_CONVERGED, "PCG did not reach the tolerance");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Shared definitions of the h2lr host code and device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace h2 {
+
+constexpr int KC = 32;     // rank capacity of basis / coupling slots
+constexpr int KM = 64;     // capacity of an extended rank k + k'
+constexpr int LS = 32;     // leaf capacity (rows of a leaf basis, nearfield side)
+constexpr int BC = 64;     // columns of a work buffer (row-major, ld = BC)
+constexpr int NT = 256;    // threads of the task interpreter workgroup
+constexpr int KPMAX = KM - KC;  // largest update rank k'
+
+// Device error codes written to err[0] (mirrors h2_status).
+enum : int { E_OK = 0, E_NOT_SPD = -4, E_RANK_CAP = -5, E_ARG = -1 };
+
+// Work buffers: n x BC row-major arrays indexed by cluster-order rows.
+enum Buf : int {
+  B_U, B_V, B_A, B_B, B_W, B_WP, B_I, B_X, B_Y,
+  B_T0U, B_T0V, B_T1U, B_T1V, B_T2U, B_T2V, B_T3U, B_T3V,
+  NBUF
+};
+
+enum Op : int {
+  OP_ADDLR = 1,      // i0 block, i1 bufX, i2 bufY
+  OP_EXPAND,         // i0 side, i1 cluster, i2 buf       -> buf rows = expanded basis, cols = k
+  OP_BAPPLY,         // i0 block, i1 trans, i2 in, i3 out; alpha, beta
+  OP_RMUL_S,         // i0 in, i1 out, i2 block, i3 transS, i4 rows cluster; alpha
+  OP_COPY_NEAR,      // i0 block, i1 out; alpha          -> rows of row cluster, cols = #col cluster
+  OP_IDENT,          // i0 cluster, i1 buf, i2 first col, i3 ncols
+  OP_NEAR_ADD,       // i0 block, i1 U, i2 V; alpha
+  OP_TEMP_INIT,      // i0 U, i1 V, i2 row cluster, i3 col cluster
+  OP_TEMP_ADD,       // i0 tU, i1 tV, i2 t', i3 r', i4 U, i5 V, i6 temp row cluster, i7 temp col cluster
+  OP_POTRF,          // i0 leaf cluster
+  OP_TRSM,           // i0 near block, i1 diagonal leaf cluster
+  OP_TRSV,           // i0 leaf cluster, i1 buf, i2 trans
+  OP_SUB,            // i0 A, i1 B, i2 out, i3 cluster
+  OP_COPY,           // i0 A, i1 out, i2 cluster
+};
+
+struct Task {
+  int op;
+  int i[8];
+  int pad;
+  double alpha, beta;
+};
+
+// Everything a device task needs, passed by value to the interpreter.
+struct DevEnv {
+  int n, nc, depth, nlev;          // nlev = depth + 1
+  int rank_cap, mode;              // truncation
+  double eps;
+  // cluster tree
+  const int *offset, *size, *son0, *son1, *parent, *level;
+  const int *desc_lo, *desc_hi;    // nc x nlev: descendants of t at level l = [lo, hi)
+  // block tree
+  const int *brow, *bcol, *bkind, *bfirst, *bnsons;
+  const int *bslot;                // stored slot of a leaf block, -1 otherwise
+  const int *rowptr, *rowidx;      // row(t): stored admissible blocks, by block id
+  const int *colptr, *colidx;      // col(s)
+  const int *nrowptr, *nrowidx;    // stored inadmissible leaves by row cluster
+  const int *ncolptr, *ncolidx;    // ... by column cluster
+  // matrix data: index 0 row basis V, 1 column basis W
+  int *k[2];
+  double *leaf[2];                 // nc slots LS x KC, col-major ld LS
+  double *E[2];                    // nc slots KC x KC, ld KC (k_t x k_father)
+  double *rho[2];                  // nc slots KC x KC
+  int *rho_m[2];                   // rows of rho
+  double *S;                       // adm slots KC x KC (k_t x k_s)
+  double *N;                       // near slots LS x LS (#t x #s)
+  // update workspace (per cluster)
+  double *wrho[2]; int *wrho_m[2];
+  double *wB[2]; int *wB_m[2];
+  double *wR[2]; int *wnewk[2];
+  // products with sub-blocks
+  double *xh, *yh;                 // nc slots KC x BC row-major
+  // work buffers
+  double *buf[NBUF];
+  int *bcols;
+  int *err;                        // err[0] code, err[1] info
+};
+
+}  // namespace h2

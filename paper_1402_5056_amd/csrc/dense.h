@@ -1,0 +1,333 @@
+// Workgroup-cooperative small dense linear algebra in FP64 for gfx950.
+//
+// Every routine is executed by all threads of one workgroup (blockDim.x a
+// multiple of 64), works on strided views that may point to LDS or global
+// memory, and ends with a workgroup barrier so that its results are visible
+// to every thread.  Sizes are runtime values; the callers keep them within
+// the LDS capacities of the task interpreter.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace h2 {
+
+struct MV {
+  double *p;
+  int rs, cs;
+  __device__ __forceinline__ double &operator()(int i, int j) const {
+    return p[(long)i * rs + (long)j * cs];
+  }
+};
+__device__ __forceinline__ MV mv_col(double *p, int ld) { return MV{p, 1, ld}; }
+__device__ __forceinline__ MV mv_row(double *p, int ld) { return MV{p, ld, 1}; }
+__device__ __forceinline__ MV mv_t(MV a) { return MV{a.p, a.cs, a.rs}; }
+__device__ __forceinline__ MV mv_at(MV a, int i, int j) {
+  return MV{a.p + (long)i * a.rs + (long)j * a.cs, a.rs, a.cs};
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ int num_waves() { return blockDim.x >> 6; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of one value per thread over the workgroup; red holds >= 16 doubles.
+__device__ __forceinline__ double wg_sum(double v, double *red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < num_waves(); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ int wg_or(int v, int *ired) {
+  __syncthreads();
+  if (threadIdx.x == 0) *ired = 0;
+  __syncthreads();
+  if (v) *ired = 1;
+  __syncthreads();
+  int r = *ired;
+  __syncthreads();
+  return r;
+}
+
+// C (m x n) = alpha * A (m x k) * B (k x n) + beta * C.  C must not alias A/B.
+__device__ void wg_gemm(int m, int n, int k, double alpha, MV A, MV B, double beta, MV C) {
+  const int mn = m * n;
+  for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) {
+    const int i = idx % m, j = idx / m;
+    double s = 0.0;
+    for (int l = 0; l < k; ++l) s = fma(A(i, l), B(l, j), s);
+    C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * s;
+  }
+  __syncthreads();
+}
+
+__device__ void wg_copy(int m, int n, MV src, MV dst) {
+  const int mn = m * n;
+  for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) {
+    const int i = idx % m, j = idx / m;
+    dst(i, j) = src(i, j);
+  }
+  __syncthreads();
+}
+
+__device__ void wg_fill(int m, int n, MV dst, double v) {
+  const int mn = m * n;
+  for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) dst(idx % m, idx / m) = v;
+  __syncthreads();
+}
+
+// Householder QR of A (m x n) in place (LAPACK dlarfg convention).  On exit
+// the upper triangle of the first min(m,n) rows holds R, the strictly lower
+// part holds the Householder vectors (unit first entry implied) and tau[j]
+// (if tau != nullptr) the scalar factors.  red: >= 4 doubles of scratch.
+__device__ void wg_qr(int m, int n, MV A, double *tau, double *red) {
+  const int kmax = m < n ? m : n;
+  const int lane = lane_id(), wave = wave_id(), nw = num_waves();
+  for (int j = 0; j < kmax; ++j) {
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const double v = A(i, j);
+        s = fma(v, v, s);
+      }
+      s = wave_sum(s);
+      if (lane == 0) {
+        const double alpha = A(j, j);
+        double t = 0.0, beta = alpha, scale = 0.0;
+        if (s > 0.0) {
+          const double nrm = sqrt(fma(alpha, alpha, s));
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          t = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        red[0] = t; red[1] = beta; red[2] = scale;
+      }
+    }
+    __syncthreads();
+    const double t = red[0], beta = red[1], scale = red[2];
+    if (t != 0.0) {
+      for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) A(i, j) *= scale;
+      __syncthreads();
+      for (int c = j + 1 + wave; c < n; c += nw) {
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w = fma(A(i, j), A(i, c), w);
+        w = wave_sum(w);
+        w = t * (w + A(j, c));
+        for (int i = j + 1 + lane; i < m; i += 64) A(i, c) = fma(-w, A(i, j), A(i, c));
+        if (lane == 0) A(j, c) -= w;
+      }
+      if (threadIdx.x == 0) A(j, j) = beta;
+    } else {
+      for (int i = j + 1 + threadIdx.x; i < m; i += blockDim.x) A(i, j) = 0.0;
+    }
+    if (tau != nullptr && threadIdx.x == 0) tau[j] = t;
+    __syncthreads();
+  }
+}
+
+// Copy R (rows min(m,n), upper triangular/trapezoidal) of a factorised A to R.
+__device__ void wg_extract_r(int m, int n, MV A, MV R) {
+  const int kmax = m < n ? m : n;
+  const int tot = kmax * n;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int i = idx % kmax, j = idx / kmax;
+    R(i, j) = (j >= i) ? A(i, j) : 0.0;
+  }
+  __syncthreads();
+}
+
+// Zero the strictly lower part of the first min(m,n) rows (turn a factorised
+// A into [R; junk] with R clean).
+__device__ void wg_clean_r(int m, int n, MV A) {
+  const int kmax = m < n ? m : n;
+  const int tot = kmax * kmax;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int i = idx % kmax, j = idx / kmax;
+    if (i > j) A(i, j) = 0.0;
+  }
+  __syncthreads();
+}
+
+// Explicit Q (m x q, q = min(m,n)) of a factorised A: Q = H_0 ... H_{q-1} [I; 0].
+__device__ void wg_form_q(int m, int n, MV A, const double *tau, MV Q) {
+  const int q = m < n ? m : n;
+  const int lane = lane_id(), wave = wave_id(), nw = num_waves();
+  const int tot = m * q;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int i = idx % m, j = idx / m;
+    Q(i, j) = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = q - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t != 0.0) {
+      for (int c = j + wave; c < q; c += nw) {
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w = fma(A(i, j), Q(i, c), w);
+        w = wave_sum(w);
+        w = t * (w + Q(j, c));
+        for (int i = j + 1 + lane; i < m; i += 64) Q(i, c) = fma(-w, A(i, j), Q(i, c));
+        if (lane == 0) Q(j, c) -= w;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One-sided (Hestenes) Jacobi: rotate the columns of G (m x n) until they are
+// mutually orthogonal; the same rotations are applied to J (n x n, if not
+// null), which then holds the right singular vectors (G_in J = G_out).
+// Pairs are visited in round-robin order, n/2 disjoint pairs per round, one
+// wave per pair.
+__device__ void wg_jacobi(int m, int n, MV G, MV *J, int *sflag) {
+  if (n < 2) { __syncthreads(); return; }
+  const int lane = lane_id(), wave = wave_id(), nw = num_waves();
+  const int np = n + (n & 1);
+  const double tol = 4.0e-16 * (double)(m > 8 ? m : 8);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    __syncthreads();
+    if (threadIdx.x == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      for (int p = wave; p < np / 2; p += nw) {
+        int a, b;
+        if (p == 0) { a = np - 1; b = r; }
+        else { a = (r + p) % (np - 1); b = (r - p + np - 1) % (np - 1); }
+        if (a > b) { const int tt = a; a = b; b = tt; }
+        if (b >= n) continue;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          const double x = G(i, a), y = G(i, b);
+          al = fma(x, x, al); be = fma(y, y, be); ga = fma(x, y, ga);
+        }
+        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          double t;
+          if (fabs(zeta) > 1.0e100) t = 0.5 / zeta;
+          else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          for (int i = lane; i < m; i += 64) {
+            const double x = G(i, a), y = G(i, b);
+            G(i, a) = c * x - s * y;
+            G(i, b) = s * x + c * y;
+          }
+          if (J != nullptr) {
+            MV Jm = *J;
+            for (int i = lane; i < n; i += 64) {
+              const double x = Jm(i, a), y = Jm(i, b);
+              Jm(i, a) = c * x - s * y;
+              Jm(i, b) = s * x + c * y;
+            }
+          }
+          if (lane == 0) *sflag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (*sflag == 0) break;
+  }
+  __syncthreads();
+}
+
+// Column norms of G (m x n) into sig[0..n) and the permutation ord[0..n)
+// sorting them in descending order (stable).
+__device__ void wg_colnorms_sorted(int m, int n, MV G, double *sig, int *ord) {
+  const int lane = lane_id(), wave = wave_id(), nw = num_waves();
+  for (int c = wave; c < n; c += nw) {
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) { const double x = G(i, c); s = fma(x, x, s); }
+    s = wave_sum(s);
+    if (lane == 0) sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // stable insertion sort, descending
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    for (int i = 1; i < n; ++i) {
+      const int v = ord[i];
+      int j = i - 1;
+      while (j >= 0 && sig[ord[j]] < sig[v]) { ord[j + 1] = ord[j]; --j; }
+      ord[j + 1] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Lower Cholesky factor of A (n x n) in place using the lower triangle;
+// the strict upper triangle is zeroed.  Returns 0 or (j+1) for a
+// non-positive pivot j.
+__device__ int wg_potrf(int n, MV A, int *iflag) {
+  if (threadIdx.x == 0) *iflag = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = A(j, j);
+      if (!(d > 0.0)) { if (*iflag == 0) *iflag = j + 1; A(j, j) = 1.0; }
+      else A(j, j) = sqrt(d);
+    }
+    __syncthreads();
+    const double djj = A(j, j);
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, j) /= djj;
+    __syncthreads();
+    const int rem = n - j - 1;
+    for (int idx = threadIdx.x; idx < rem * rem; idx += blockDim.x) {
+      const int i = j + 1 + idx % rem, c = j + 1 + idx / rem;
+      if (c <= i) A(i, c) = fma(-A(i, j), A(c, j), A(i, c));
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, c = idx / n;
+    if (c > i) A(i, c) = 0.0;
+  }
+  __syncthreads();
+  const int r = *iflag;
+  __syncthreads();
+  return r;
+}
+
+// X (m x n) <- X L^{-T} for lower triangular L (n x n): row-wise forward
+// substitution, one thread per row.
+__device__ void wg_trsm_right_lt(int m, int n, MV L, MV X) {
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    for (int j = 0; j < n; ++j) {
+      double s = X(i, j);
+      for (int l = 0; l < j; ++l) s = fma(-L(j, l), X(i, l), s);
+      X(i, j) = s / L(j, j);
+    }
+  }
+  __syncthreads();
+}
+
+// B (n x m) <- L^{-1} B (trans = 0) or L^{-T} B (trans = 1) for lower
+// triangular L (n x n); one thread per column of B.
+__device__ void wg_trsv_lower(int n, int m, MV L, MV B, int trans) {
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    if (!trans) {
+      for (int i = 0; i < n; ++i) {
+        double s = B(i, c);
+        for (int l = 0; l < i; ++l) s = fma(-L(i, l), B(l, c), s);
+        B(i, c) = s / L(i, i);
+      }
+    } else {
+      for (int i = n - 1; i >= 0; --i) {
+        double s = B(i, c);
+        for (int l = i + 1; l < n; ++l) s = fma(-L(l, i), B(l, c), s);
+        B(i, c) = s / L(i, i);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace h2

@@ -1,0 +1,302 @@
+"""Thin ctypes binding of the h2lr C ABI (include/h2lr.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions keep the C names; handles are opaque integers wrapped in small
+classes that free them.  Device buffers are torch tensors on a ROCm device
+(passed by ``data_ptr()``); host arrays are numpy arrays.  A non-zero status
+raises :class:`H2Error`.  Importing this module fails loudly if the library
+has not been built; there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import sys
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2lr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"h2lr library not built: {LIB_PATH} missing (run paper_1402_5056_amd/build.py)")
+_lib = C.CDLL(LIB_PATH)
+
+H2_OK = 0
+STATUS = {0: "H2_OK", -1: "H2_ERR_ARG", -2: "H2_ERR_NOMEM", -3: "H2_ERR_HIP", -4: "H2_ERR_NOT_SPD",
+          -5: "H2_ERR_RANK_CAP", -6: "H2_ERR_NONZERO_FARFIELD", -7: "H2_ERR_NOT_CONVERGED",
+          -8: "H2_ERR_STATE"}
+MAX_RANK = 32
+MAX_LEAF = 32
+MAX_COLS = 64
+MAX_UPDATE_RANK = 32
+MODES = {"block_rel": 0, "const_rel": 1, "none": 2}
+
+
+class H2Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class h2_trunc(C.Structure):
+    _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32)]
+
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_d = C.c_double
+_P = C.POINTER
+
+_SIG = {
+    "h2_ctx_create": [C.c_int, _vp, _P(_vp)],
+    "h2_ctx_destroy": [_vp],
+    "h2_ctx_synchronize": [_vp],
+    "h2_ctree_build": [_vp, _i32, _i64, _vp, _i32, _P(_vp)],
+    "h2_ctree_info": [_vp, _P(_i64), _P(_i64), _P(_i32)],
+    "h2_ctree_export": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "h2_ctree_destroy": [_vp],
+    "h2_btree_build": [_vp, _vp, _d, _P(_vp)],
+    "h2_btree_info": [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i32)],
+    "h2_btree_export": [_vp, _vp, _vp, _vp, _vp],
+    "h2_btree_find": [_vp, _i64, _i64, _P(_i64)],
+    "h2_btree_destroy": [_vp],
+    "h2_mat_from_csr": [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _P(_vp)],
+    "h2_mat_copy": [_vp, _P(_vp)],
+    "h2_mat_destroy": [_vp],
+    "h2_mat_stats": [_vp, _P(_i64), _P(_i32), _P(_i32)],
+    "h2_lowrank_update": [_vp, _i64, _i32, _vp, _i64, _vp, _i64, _P(h2_trunc)],
+    "h2_matvec": [_vp, _i32, _d, _vp, _d, _vp, _i32],
+    "h2_cholesky": [_vp, _P(h2_trunc)],
+    "h2_precond": [_vp, _vp, _vp, _i32],
+    "h2_csr_create": [_vp, _i64, _vp, _vp, _vp, _P(_vp)],
+    "h2_csr_destroy": [_vp],
+    "h2_spmv": [_vp, _vp, _vp],
+    "h2_pcg": [_vp, _vp, _vp, _vp, _d, _i32, _P(_i32), _P(_d)],
+}
+for _name, _args in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.h2_last_error.argtypes = []
+_lib.h2_last_error.restype = C.c_char_p
+
+EXPORTED = tuple(_SIG) + ("h2_last_error",)
+
+
+def _check(status: int):
+    if status != H2_OK:
+        raise H2Error(status, (_lib.h2_last_error() or b"").decode())
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (must be contiguous float64/int)."""
+    return t.data_ptr()
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def trunc(eps: float = 1e-4, mode: str = "block_rel", rank_cap: int = MAX_RANK) -> h2_trunc:
+    return h2_trunc(float(eps), MODES[mode] if isinstance(mode, str) else int(mode), int(rank_cap))
+
+
+_LIVE = weakref.WeakSet()
+
+
+class _Handle:
+    _destroy = None
+    _order = 0          # destruction order at exit: matrices first, context last
+
+    def __init__(self, h, keep=()):
+        self.h = h
+        self._keep = keep   # keep referenced objects alive
+        _LIVE.add(self)
+
+    def close(self):
+        if self.h is not None and self._destroy is not None:
+            getattr(_lib, self._destroy)(self.h)
+            self.h = None
+
+    def __del__(self):
+        # Never call into the HIP runtime while the interpreter shuts down:
+        # the runtime may already be torn down; _close_all ran before that.
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@atexit.register
+def _close_all():
+    """Free every live handle in dependency order before the HIP runtime
+    and torch are torn down."""
+    for h in sorted(list(_LIVE), key=lambda x: x._order):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+class Ctx(_Handle):
+    _destroy = "h2_ctx_destroy"
+    _order = 4
+
+
+class CTree(_Handle):
+    _destroy = "h2_ctree_destroy"
+    _order = 3
+
+
+class BTree(_Handle):
+    _destroy = "h2_btree_destroy"
+    _order = 2
+
+
+class Mat(_Handle):
+    _destroy = "h2_mat_destroy"
+    _order = 0
+
+
+class Csr(_Handle):
+    _destroy = "h2_csr_destroy"
+    _order = 1
+
+
+def h2_ctx_create(device: int = 0, stream: int | None = None) -> Ctx:
+    h = _vp()
+    _check(_lib.h2_ctx_create(int(device), _vp(stream or 0), C.byref(h)))
+    return Ctx(h.value)
+
+
+def h2_ctx_synchronize(ctx: Ctx):
+    _check(_lib.h2_ctx_synchronize(ctx.h))
+
+
+def h2_ctree_build(ctx: Ctx, coords: np.ndarray, leaf_size: int = 32) -> CTree:
+    c = _np(coords, np.int32)
+    h = _vp()
+    _check(_lib.h2_ctree_build(ctx.h, c.shape[1], c.shape[0], c.ctypes.data, int(leaf_size), C.byref(h)))
+    return CTree(h.value, keep=(ctx,))
+
+
+def h2_ctree_info(ct: CTree):
+    n, nc, depth = _i64(), _i64(), _i32()
+    _check(_lib.h2_ctree_info(ct.h, C.byref(n), C.byref(nc), C.byref(depth)))
+    return n.value, nc.value, depth.value
+
+
+def h2_ctree_export(ct: CTree) -> dict:
+    n, nc, _ = h2_ctree_info(ct)
+    out = {"perm": np.zeros(n, np.int64)}
+    for k in ("offset", "size", "level", "son0", "son1", "parent"):
+        out[k] = np.zeros(nc, np.int32)
+    _check(_lib.h2_ctree_export(ct.h, out["perm"].ctypes.data, out["offset"].ctypes.data,
+                                out["size"].ctypes.data, out["level"].ctypes.data,
+                                out["son0"].ctypes.data, out["son1"].ctypes.data,
+                                out["parent"].ctypes.data))
+    return out
+
+
+def h2_btree_build(ctx: Ctx, ct: CTree, eta: float = 2.0) -> BTree:
+    h = _vp()
+    _check(_lib.h2_btree_build(ctx.h, ct.h, float(eta), C.byref(h)))
+    return BTree(h.value, keep=(ctx, ct))
+
+
+def h2_btree_info(bt: BTree):
+    nb, na, nn, csp = _i64(), _i64(), _i64(), _i32()
+    _check(_lib.h2_btree_info(bt.h, C.byref(nb), C.byref(na), C.byref(nn), C.byref(csp)))
+    return nb.value, na.value, nn.value, csp.value
+
+
+def h2_btree_export(bt: BTree) -> dict:
+    nb = h2_btree_info(bt)[0]
+    out = {k: np.zeros(nb, np.int32) for k in ("row", "col", "kind", "parent")}
+    _check(_lib.h2_btree_export(bt.h, out["row"].ctypes.data, out["col"].ctypes.data,
+                                out["kind"].ctypes.data, out["parent"].ctypes.data))
+    return out
+
+
+def h2_btree_find(bt: BTree, t: int, s: int) -> int:
+    b = _i64()
+    _check(_lib.h2_btree_find(bt.h, int(t), int(s), C.byref(b)))
+    return b.value
+
+
+def _csr_arrays(A):
+    import scipy.sparse as sp
+    A = sp.csr_matrix(A)
+    return A.shape[0], _np(A.indptr, np.int64), _np(A.indices, np.int32), _np(A.data, np.float64)
+
+
+def h2_mat_from_csr(ctx: Ctx, bt: BTree, A, lower: bool = False) -> Mat:
+    n, rp, ci, v = _csr_arrays(A)
+    h = _vp()
+    _check(_lib.h2_mat_from_csr(ctx.h, bt.h, n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                1 if lower else 0, C.byref(h)))
+    return Mat(h.value, keep=(ctx, bt))
+
+
+def h2_mat_copy(m: Mat) -> Mat:
+    h = _vp()
+    _check(_lib.h2_mat_copy(m.h, C.byref(h)))
+    return Mat(h.value, keep=m._keep)
+
+
+def h2_mat_stats(m: Mat):
+    v, kr, kc = _i64(), _i32(), _i32()
+    _check(_lib.h2_mat_stats(m.h, C.byref(v), C.byref(kr), C.byref(kc)))
+    return v.value, kr.value, kc.value
+
+
+def h2_lowrank_update(m: Mat, block: int, X, Y, tr: h2_trunc):
+    """X (#t0 x k), Y (#s0 x k): float64 torch tensors on the device,
+    column-major (pass ``x.t().contiguous().t()`` or Fortran-ordered data)."""
+    k = X.shape[1]
+    assert Y.shape[1] == k
+    _check(_lib.h2_lowrank_update(m.h, int(block), int(k), _ptr(X), X.stride(1) if k > 1 else X.shape[0],
+                                  _ptr(Y), Y.stride(1) if k > 1 else Y.shape[0], C.byref(tr)))
+
+
+def h2_matvec(m: Mat, x, y, trans: bool = False, alpha: float = 1.0, beta: float = 0.0):
+    """x, y: (n,) or (nrhs, n) contiguous float64 device tensors (each row one
+    vector, i.e. column-major n x nrhs)."""
+    nrhs = 1 if x.dim() == 1 else x.shape[0]
+    _check(_lib.h2_matvec(m.h, 1 if trans else 0, float(alpha), _ptr(x), float(beta), _ptr(y), nrhs))
+
+
+def h2_cholesky(m: Mat, tr: h2_trunc):
+    _check(_lib.h2_cholesky(m.h, C.byref(tr)))
+
+
+def h2_precond(m: Mat, r, z):
+    nrhs = 1 if r.dim() == 1 else r.shape[0]
+    _check(_lib.h2_precond(m.h, _ptr(r), _ptr(z), nrhs))
+
+
+def h2_csr_create(ctx: Ctx, A) -> Csr:
+    n, rp, ci, v = _csr_arrays(A)
+    h = _vp()
+    _check(_lib.h2_csr_create(ctx.h, n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, C.byref(h)))
+    return Csr(h.value, keep=(ctx,))
+
+
+def h2_spmv(a: Csr, x, y):
+    _check(_lib.h2_spmv(a.h, _ptr(x), _ptr(y)))
+
+
+def h2_pcg(a: Csr, m: Mat, b, x, rtol: float = 1e-8, maxit: int = 1000):
+    it, rel = _i32(), _d()
+    st = _lib.h2_pcg(a.h, m.h, _ptr(b), _ptr(x), float(rtol), int(maxit), C.byref(it), C.byref(rel))
+    if st != H2_OK and st != -7:
+        _check(st)
+    return it.value, rel.value, st == H2_OK

@@ -1,0 +1,182 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the
+same seeded inputs.  Bar: bit-exact trees (see test_abi_cpu), represented
+operators within 1e-12 relative spectral error in FP64."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.arith import cholesky as o_cholesky, precond_apply as o_precond
+from oracle.h2 import TruncParams, from_csr as o_from_csr, to_dense as o_to_dense
+from oracle.solve import pcg as o_pcg
+from oracle.trees import ADM, build_block_tree, build_cluster_tree
+from oracle.update import addlr as o_addlr
+from tests.helpers import dense_via_matvec, gpu, rel2, to_dev_cols, to_original
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib():
+    gpu()
+    from paper_1402_5056_amd import h2lr
+    return h2lr
+
+
+def _setup(lib, N, sigma_seed=None, leaf=32, eta=2.0, lower=False):
+    p = w.problem(N, sigma_seed=sigma_seed, rhs_seed=5)
+    ctx = lib.h2_ctx_create(0)
+    ct = lib.h2_ctree_build(ctx, p["coords"], leaf)
+    bt = lib.h2_btree_build(ctx, ct, eta)
+    M = lib.h2_mat_from_csr(ctx, bt, p["A"], lower=lower)
+    oc = build_cluster_tree(p["coords"], leaf)
+    ob = build_block_tree(oc, eta)
+    return p, ctx, bt, M, oc, ob
+
+
+def test_from_csr_and_matvec(lib):
+    print("case: from_csr + matvec, N=32", flush=True)
+    torch = gpu()
+    p, ctx, bt, M, oc, ob = _setup(lib, 32, sigma_seed=3)
+    x = w.gaussian(oc.n, 3, 1)
+    X = torch.tensor(np.ascontiguousarray(x.T), device="cuda")
+    Y = torch.zeros_like(X)
+    lib.h2_matvec(M, X, Y)
+    ref = (p["A"] @ x).T
+    assert np.allclose(Y.cpu().numpy(), ref, rtol=1e-14, atol=1e-13)
+    Y2 = torch.ones_like(X)
+    lib.h2_matvec(M, X, Y2, trans=True, alpha=2.0, beta=0.5)
+    assert np.allclose(Y2.cpu().numpy(), 2.0 * (p["A"].T @ x).T + 0.5, atol=1e-12)
+
+
+def _factors(oc, t, s, k, seed):
+    X = w.gaussian(int(oc.size[t]), k, seed)
+    Y = w.gaussian(int(oc.size[s]), k, seed + 1000)
+    return X, Y
+
+
+def test_global_update_exact(lib):
+    print("case: global update rank 8, no truncation, N=32", flush=True)
+    p, ctx, bt, M, oc, ob = _setup(lib, 32)
+    Z = o_from_csr(p["A"], oc, ob)
+    X = w.gaussian(oc.n, 8, 1)[oc.perm]
+    Y = w.gaussian(oc.n, 8, 101)[oc.perm]
+    o_addlr(Z, 0, X, Y, TruncParams(0.0, "none", 32))
+    lib.h2_lowrank_update(M, 0, to_dev_cols(X), to_dev_cols(Y), lib.trunc(0.0, "none", 32))
+    D = dense_via_matvec(lib, M, oc.n)
+    Dref = to_original(o_to_dense(Z), oc.perm)
+    assert rel2(D, Dref) < TOL
+    _, kr, kc = lib.h2_mat_stats(M)
+    assert kr == int(Z.k[0].max()) and kc == int(Z.k[1].max())
+
+
+@pytest.mark.parametrize("eps,mode", [(1e-6, "block_rel"), (1e-3, "block_rel"), (1e-8, "const_rel")])
+def test_update_sequence(lib, eps, mode):
+    """Global update then local updates on admissible leaves, subdivided and
+    diagonal blocks, each with truncation; parity after every step."""
+    print(f"case: update sequence eps={eps} mode={mode}, N=32", flush=True)
+    p, ctx, bt, M, oc, ob = _setup(lib, 32, sigma_seed=4)
+    Z = o_from_csr(p["A"], oc, ob)
+    tp = TruncParams(eps, mode, 32)
+    tr = lib.trunc(eps, mode, 32)
+    adm = [b for b in range(ob.nb) if ob.kind[b] == ADM]
+    inner = [b for b in range(ob.nb) if ob.kind[b] == 0 and ob.row[b] != ob.col[b]]
+    diag = [b for b in range(ob.nb) if ob.kind[b] == 0 and ob.row[b] == ob.col[b] and b != 0]
+    X0 = w.gaussian(oc.n, 6, 7)[oc.perm] * np.logspace(0, -5, 6)
+    seq = [(0, X0, w.gaussian(oc.n, 6, 8)[oc.perm])]
+    for i, b in enumerate([adm[5], inner[3], diag[2], adm[60], inner[10]]):
+        X, Y = _factors(oc, int(ob.row[b]), int(ob.col[b]), 2 + i, 20 + i)
+        seq.append((b, X, Y))
+    for b, X, Y in seq:
+        margins = []
+        o_addlr(Z, b, X, Y, tp, margins)
+        lib.h2_lowrank_update(M, b, to_dev_cols(X), to_dev_cols(Y), tr)
+        if mode == "block_rel" and margins:
+            assert min(margins) > 1e-8, "seed too close to the truncation threshold"
+        D = dense_via_matvec(lib, M, oc.n)
+        Dref = to_original(o_to_dense(Z), oc.perm)
+        assert rel2(D, Dref) < TOL, (b, rel2(D, Dref))
+
+
+def test_zero_update_skipped(lib):
+    torch = gpu()
+    p, ctx, bt, M, oc, ob = _setup(lib, 32)
+    X = torch.zeros((4, oc.n), dtype=torch.float64, device="cuda").t()
+    Y = to_dev_cols(w.gaussian(oc.n, 4, 1))
+    lib.h2_lowrank_update(M, 0, X, Y, lib.trunc(1e-6))
+    assert lib.h2_mat_stats(M)[1:] == (0, 0)
+
+
+def test_rank_cap_error(lib):
+    print("case: rank cap error", flush=True)
+    p, ctx, bt, M, oc, ob = _setup(lib, 32)
+    X = w.gaussian(oc.n, 8, 1)[oc.perm]
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_lowrank_update(M, 0, to_dev_cols(X), to_dev_cols(X), lib.trunc(0.0, "none", 4))
+    assert ei.value.name == "H2_ERR_RANK_CAP"
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_matvec(M, *(2 * [gpu().zeros(oc.n, dtype=gpu().float64, device="cuda")]))
+    assert ei.value.name == "H2_ERR_STATE"
+
+
+@pytest.mark.parametrize("N,sigma_seed,eps", [(32, None, 1e-6), (32, 3, 1e-4), (16, 5, 1e-6)])
+def test_cholesky_parity(lib, N, sigma_seed, eps):
+    print(f"case: cholesky N={N} sigma={sigma_seed} eps={eps}", flush=True)
+    leaf = 32 if N >= 32 else 8
+    p, ctx, bt, M, oc, ob = _setup(lib, N, sigma_seed=sigma_seed, leaf=leaf, lower=True)
+    L = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), TruncParams(eps, "block_rel", 32))
+    lib.h2_cholesky(M, lib.trunc(eps, "block_rel", 32))
+    D = dense_via_matvec(lib, M, oc.n)
+    Dref = to_original(np.tril(o_to_dense(L)), oc.perm)
+    err = rel2(D, Dref)
+    print(f"  ||L_gpu - L_oracle||_2 / ||L_oracle||_2 = {err:.3e}", flush=True)
+    assert err < TOL
+    _, kr, kc = lib.h2_mat_stats(M)
+    assert (kr, kc) == (int(L.k[0].max()), int(L.k[1].max()))
+
+
+def test_precond_and_pcg(lib):
+    print("case: precond + pcg N=32", flush=True)
+    torch = gpu()
+    p, ctx, bt, M, oc, ob = _setup(lib, 32, sigma_seed=3, lower=True)
+    tp = TruncParams(1e-4, "block_rel", 32)
+    L = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), tp)
+    lib.h2_cholesky(M, lib.trunc(1e-4, "block_rel", 32))
+    r = w.gaussian(oc.n, 2, 9)
+    R = torch.tensor(np.ascontiguousarray(r.T), device="cuda")
+    Zt = torch.zeros_like(R)
+    lib.h2_precond(M, R, Zt)
+    zref = np.stack([o_precond(L, r[:, i]) for i in range(2)])
+    assert rel2(Zt.cpu().numpy(), zref) < TOL
+    A = lib.h2_csr_create(ctx, p["A"])
+    b = torch.tensor(p["b"], device="cuda")
+    x = torch.zeros_like(b)
+    it, rel, ok = lib.h2_pcg(A, M, b, x, 1e-8, 100)
+    xo, ito, relo = o_pcg(p["A"], p["b"], lambda v: o_precond(L, v))
+    assert ok and it == ito
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-10
+    assert np.linalg.norm(p["b"] - p["A"] @ x.cpu().numpy()) / np.linalg.norm(p["b"]) < 1e-8
+
+
+def test_not_spd(lib):
+    print("case: not SPD", flush=True)
+    p = w.problem(16, rhs_seed=1)
+    A = p["A"].tolil()
+    A[5, 5] = -1.0
+    ctx = lib.h2_ctx_create(0)
+    ct = lib.h2_ctree_build(ctx, p["coords"], 8)
+    bt = lib.h2_btree_build(ctx, ct, 2.0)
+    M = lib.h2_mat_from_csr(ctx, bt, A.tocsr(), lower=True)
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_cholesky(M, lib.trunc(1e-6))
+    assert ei.value.name == "H2_ERR_NOT_SPD"
+
+
+def test_nonzero_farfield_rejected(lib):
+    p = w.problem(12, dim=3, sigma_seed=4)
+    ctx = lib.h2_ctx_create(0)
+    ct = lib.h2_ctree_build(ctx, p["coords"], 32)
+    bt = lib.h2_btree_build(ctx, ct, 2.0)
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_mat_from_csr(ctx, bt, p["A"])
+    assert ei.value.name == "H2_ERR_NONZERO_FARFIELD"
