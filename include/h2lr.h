@@ -124,11 +124,24 @@ h2_status h2_mat_from_csr(h2_ctx ctx, h2_btree bt, int64_t n, const int64_t *row
                           const int32_t *col, const double *val, int32_t lower,
                           h2_mat *out);
 h2_status h2_mat_copy(h2_mat src, h2_mat *out);
+/* Overwrite dst with the contents of src (same block tree and storage);
+ * device-to-device copies only, no allocation.  Clears a poisoned dst. */
+h2_status h2_mat_assign(h2_mat dst, h2_mat src);
 h2_status h2_mat_destroy(h2_mat m);
 /* stored_values: floating point values held by bases, transfers, couplings
  * and nearfield blocks at the current ranks; max ranks of both bases. */
 h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row,
                        int32_t *max_rank_col);
+/* Algorithmic floating point operations performed on m since the last reset
+ * (products 2mnk, Householder R-factors 2mn^2-2n^3/3, SVDs 4ab^2+8b^3 with
+ * a = max, b = min of the dimensions; vector substitutions n^2 per column);
+ * reset != 0 zeroes the counter afterwards.  Synchronises the stream. */
+h2_status h2_mat_flops(h2_mat m, double *flops, int32_t reset);
+/* Tracing: if counters != NULL, copy the first n (<= 80) profile counters of
+ * m (task counts per kind [0,32), device ticks of a 100 MHz clock per kind
+ * [32,64), ticks per stage of the low-rank update [64,80)); then enable
+ * (enable != 0, counters reset to zero) or disable collection. */
+h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n);
 
 /* Local low-rank update Z|_{t0 x s0} += X Y^* of the block tree node
  * `block` = (t0, s0) (Section 4 for the recompression, Section 5 for the

@@ -249,6 +249,8 @@ struct h2_mat_s {
   Dev<int> d_k[2], d_rho_m[2], d_wrho_m[2], d_wB_m[2], d_wnewk[2], d_bcols, d_err;
   Dev<double> d_leaf[2], d_E[2], d_rho[2], d_wrho[2], d_wB[2], d_wR[2], d_S, d_N, d_xh, d_yh, d_buf;
   Dev<double> d_pcg;   // PCG vectors and scalars
+  Dev<unsigned long long> d_prof;
+  Dev<double> d_flops;
   TaskList chol, prec;
   DevEnv env{};
 };
@@ -291,6 +293,7 @@ static void mat_alloc(h2_mat_s &m) {
   m.d_buf.alloc((size_t)NBUF * ct.n * BC);
   m.d_bcols.alloc(NBUF); m.d_bcols.zero(s);
   m.d_err.alloc(4); m.d_err.zero(s);
+  m.d_flops.alloc(1); m.d_flops.zero(s);
 }
 
 static void mat_lists(h2_mat_s &m) {
@@ -348,7 +351,7 @@ static void mat_env(h2_mat_s &m) {
   }
   e.S = m.d_S.p; e.N = m.d_N.p; e.xh = m.d_xh.p; e.yh = m.d_yh.p;
   for (int i = 0; i < NBUF; ++i) e.buf[i] = m.d_buf.p + (size_t)i * ct.n * BC;
-  e.bcols = m.d_bcols.p; e.err = m.d_err.p;
+  e.bcols = m.d_bcols.p; e.err = m.d_err.p; e.flops = m.d_flops.p;
 }
 
 // ================================================================== planner
@@ -533,7 +536,7 @@ static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
     HIPCHK(hipFuncSetAttribute((const void *)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     g_lds_attr_set = true;
   }
-  const int seg = 1 << 18;
+  const int seg = 1 << 24;
   for (int off = 0; off < count; off += seg) {
     const int cnt = std::min(seg, count - off);
     hipLaunchKernelGGL(k_interp, dim3(1), dim3(NT), lds, m.ctx->stream, d_tasks + off, cnt, m.env);
@@ -751,6 +754,59 @@ h2_status h2_mat_copy(h2_mat src, h2_mat *out) {
     mat_env(*m);
     HIPCHK(hipStreamSynchronize(s));
     *out = m.release();
+  });
+}
+
+h2_status h2_mat_assign(h2_mat dst, h2_mat src) {
+  return guarded([&] {
+    REQUIRE(dst && src, "null argument");
+    require_ok(src);
+    REQUIRE(dst->bt == src->bt && dst->lower == src->lower, "matrices have different structure");
+    hipStream_t s = dst->ctx->stream;
+    auto cp = [&](auto &to, auto &from) {
+      if (from.n) HIPCHK(hipMemcpyAsync(to.p, from.p, from.n * sizeof(*from.p), hipMemcpyDeviceToDevice, s));
+    };
+    for (int side = 0; side < 2; ++side) {
+      cp(dst->d_k[side], src->d_k[side]); cp(dst->d_rho_m[side], src->d_rho_m[side]);
+      cp(dst->d_leaf[side], src->d_leaf[side]); cp(dst->d_E[side], src->d_E[side]);
+      cp(dst->d_rho[side], src->d_rho[side]);
+    }
+    cp(dst->d_S, src->d_S); cp(dst->d_N, src->d_N);
+    HIPCHK(hipMemsetAsync(dst->d_err.p, 0, dst->d_err.n * sizeof(int), s));
+    dst->poisoned = false;
+  });
+}
+
+h2_status h2_mat_flops(h2_mat m, double *flops, int32_t reset) {
+  return guarded([&] {
+    REQUIRE(m != nullptr, "null matrix");
+    hipStream_t s = m->ctx->stream;
+    if (flops) {
+      HIPCHK(hipMemcpyAsync(flops, m->d_flops.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (reset) m->d_flops.zero(s);
+  });
+}
+
+h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n) {
+  return guarded([&] {
+    REQUIRE(m != nullptr, "null matrix");
+    hipStream_t s = m->ctx->stream;
+    if (counters && m->d_prof.p) {
+      REQUIRE(n >= 0 && n <= PROF_LEN, "too many counters");
+      std::vector<unsigned long long> h(PROF_LEN);
+      HIPCHK(hipMemcpyAsync(h.data(), m->d_prof.p, PROF_LEN * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < n; ++i) counters[i] = (int64_t)h[i];
+    }
+    if (enable) {
+      if (!m->d_prof.p) m->d_prof.alloc(PROF_LEN);
+      m->d_prof.zero(s);
+      m->env.prof = m->d_prof.p;
+    } else {
+      m->env.prof = nullptr;
+    }
   });
 }
 

@@ -79,6 +79,14 @@ struct DevEnv {
   double *buf[NBUF];
   int *bcols;
   int *err;                        // err[0] code, err[1] info
+  unsigned long long *prof;        // optional: per-op counts/ticks, update stage ticks
+  double *flops;                   // algorithmic flop counter (thread 0 of the interpreter)
 };
+
+// Layout of the optional profile counters (ticks of the 100 MHz wall clock).
+constexpr int PROF_COUNT = 0;      // [0, 32): tasks executed per op
+constexpr int PROF_TICKS = 32;     // [32, 64): ticks per op
+constexpr int PROF_STAGE = 64;     // [64, 80): ticks per update stage
+constexpr int PROF_LEN = 80;
 
 }  // namespace h2

@@ -81,6 +81,22 @@ __device__ __forceinline__ double trunc_tau(const DevEnv &e, double smax) {
   return 0.0;
 }
 
+// ------------------------------------------------------- flop accounting
+// Algorithmic flops of the dense steps (conventions: product 2mnk,
+// Householder R-factor 2mn^2 - 2n^3/3 for m >= n, SVD with left vectors
+// 4ab^2 + 8b^3 with a = max, b = min).  Counted by thread 0 only.
+__device__ __forceinline__ double fl_gemm(double m, double n, double k) { return 2.0 * m * n * k; }
+__device__ __forceinline__ double fl_qr(double m, double n) {
+  return m >= n ? 2.0 * m * n * n - 2.0 * n * n * n / 3.0 : 2.0 * n * m * m - 2.0 * m * m * m / 3.0;
+}
+__device__ __forceinline__ double fl_svd(double m, double n) {
+  const double a = m > n ? m : n, b = m > n ? n : m;
+  return 4.0 * a * b * b + 8.0 * b * b * b;
+}
+__device__ __forceinline__ void count(const DevEnv &e, double f) {
+  if (threadIdx.x == 0 && e.flops) e.flops[0] += f;
+}
+
 // ======================================================= low-rank update
 struct Upd {
   int r0[2];   // t0, s0
@@ -150,7 +166,7 @@ __device__ void build_weight(const DevEnv &e, const Upd &u, const Lds &L, int si
   const int kt = e.k[side][t];
   const int Kt = kt + (insub ? u.kp : 0);
   MV A = mv_col(L.W0, W0R);
-  int m = 0;
+  int m = 0, mrows = 0;
   const int *ptr = side == 0 ? e.rowptr : e.colptr;
   const int *idx = side == 0 ? e.rowidx : e.colidx;
   for (int p = ptr[t]; p < ptr[t + 1]; ++p) {
@@ -168,6 +184,14 @@ __device__ void build_weight(const DevEnv &e, const Upd &u, const Lds &L, int si
     MV B = side == 0 ? mv_t(St) : St;
     const int Ko = side == 0 ? Kbs : Kbt;
     wg_gemm(mo, Kt, Ko, w, Ro, B, 0.0, mv_at(A, m, 0));
+    if (e.mode == 0) {
+      int mt, ms;
+      (void)rho_of(e, u, 0, e.brow[b], mt);
+      (void)rho_of(e, u, 1, e.bcol[b], ms);
+      count(e, fl_gemm(mt, Kbs, Kbt) + fl_gemm(mt, ms, Kbs));
+    }
+    count(e, fl_gemm(mo, Kt, Ko));
+    mrows += mo;
     m += mo;
   }
   const int par = e.parent[t];
@@ -194,9 +218,12 @@ __device__ void build_weight(const DevEnv &e, const Upd &u, const Lds &L, int si
         D(i, j) = s;
       }
       __syncthreads();
+      count(e, fl_gemm(mp, kt, kpar));
+      mrows += mp;
       m += mp;
     }
   }
+  count(e, fl_qr(mrows, Kt));
   MV W = wslot(e.wB[side], t);
   if (m > 0) {
     wg_qr(m, Kt, A, nullptr, L.red);
@@ -231,6 +258,7 @@ __device__ int recompress_svd(const DevEnv &e, const Lds &L, int m, int n, MV Q)
     nG = m;
   }
   wg_jacobi(m, nG, M, nullptr, L.iw);
+  count(e, fl_svd(m, n));
   int *ord = L.iw + KM;
   wg_colnorms_sorted(m, nG, M, L.sig, ord);
   const double tau = trunc_tau(e, nG > 0 ? L.sig[ord[0]] : 0.0);
@@ -246,7 +274,16 @@ __device__ int recompress_svd(const DevEnv &e, const Lds &L, int m, int n, MV Q)
   return r;
 }
 
+__device__ __forceinline__ void prof_stage(const DevEnv &e, int stage, unsigned long long &t) {
+  if (e.prof && threadIdx.x == 0) {
+    const unsigned long long now = wall_clock64();
+    e.prof[PROF_STAGE + stage] += now - t;
+    t = now;
+  }
+}
+
 __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by) {
+  unsigned long long tstage = wall_clock64();
   Upd u;
   u.r0[0] = e.brow[b0];
   u.r0[1] = e.bcol[b0];
@@ -268,6 +305,7 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
     }
     if (nz < 2) return;
   }
+  prof_stage(e, 0, tstage);
   const int kp = u.kp;
   // --- step 1: R-factors of the extended bases, bottom-up
   for (int side = 0; side < 2; ++side) {
@@ -309,12 +347,14 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
           }
         }
         wg_qr(m, K, A, nullptr, L.red);
+        count(e, fl_qr(m, K) + (is_leaf(e, c) ? 0.0 : fl_gemm(m, kc, e.k[side][e.son0[c]])));
         wg_extract_r(m, K, A, wslot(e.wrho[side], c));
         if (threadIdx.x == 0) e.wrho_m[side][c] = m < K ? m : K;
         __syncthreads();
       }
     }
   }
+  prof_stage(e, 1, tstage);
   // --- steps 2/3: weights along pred(t0) \ {t0}, then through the subtree
   for (int side = 0; side < 2; ++side) {
     const int root = u.r0[side];
@@ -329,10 +369,12 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
     np = L.iw[3 * KM + 63];
     __syncthreads();
     for (int q = np - 1; q >= 0; --q) build_weight(e, u, L, side, path[q], false);
+    prof_stage(e, 2, tstage);
     for (int lv = e.level[root]; lv < e.nlev; ++lv) {
       const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
       for (int c = lo; c < hi; ++c) build_weight(e, u, L, side, c, true);
     }
+    prof_stage(e, 3, tstage);
   }
   // --- step 4: nested recompression, bottom-up
   for (int side = 0; side < 2; ++side) {
@@ -378,14 +420,17 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
         const int mB = e.wB_m[side][c];
         int r = 0;
         MV Q = mv_col(L.W0, W0R);
+        if (!is_leaf(e, c)) count(e, fl_gemm(mr, kc, e.k[side][e.son0[c]]));
         if (mr > 0 && mB > 0) {
           MV M = mv_col(L.W2, KM);
           wg_gemm(mr, mB, K, 1.0, Vt, mv_t(wslot(e.wB[side], c)), 0.0, M);
+          count(e, fl_gemm(mr, mB, K));
           r = recompress_svd(e, L, mr, mB, Q);
           if (r < 0) { set_error(e, E_RANK_CAP, c); return; }
         }
         // basis change R_c = Q^* V~_c (r x K)
         wg_gemm(r, K, mr, 1.0, mv_t(Q), Vt, 0.0, wslot(e.wR[side], c));
+        count(e, fl_gemm(r, K, mr));
         if (threadIdx.x == 0) e.wnewk[side][c] = r;
         if (is_leaf(e, c)) {
           wg_copy(mr, r, Q, leafslot(e, side, c));
@@ -399,11 +444,13 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
           const int kpar = e.k[side][e.parent[c]];
           MV T = mv_col(L.W2, KM);
           wg_gemm(r, kpar, kc, 1.0, wslot(e.wR[side], c), Eslot(e, side, c), 0.0, T);
+          count(e, fl_gemm(r, kpar, kc));
           wg_copy(r, kpar, T, Eslot(e, side, c));
         }
       }
     }
   }
+  prof_stage(e, 4, tstage);
   // --- step 5: couplings of every admissible leaf touching the subtrees
   for (int side = 0; side < 2; ++side) {
     const int root = u.r0[side];
@@ -426,11 +473,13 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
             rows = e.wnewk[0][t];
             P = mv_col(L.W1, KM);
             wg_gemm(rows, Ks, Kt, 1.0, wslot(e.wR[0], t), St, 0.0, P);
+            count(e, fl_gemm(rows, Ks, Kt));
           }
           MV Sd = Sslot(e, b);
           if (sin) {
             const int rs = e.wnewk[1][s];
             wg_gemm(rows, rs, Ks, 1.0, P, mv_t(wslot(e.wR[1], s)), 0.0, Sd);
+            count(e, fl_gemm(rows, rs, Ks));
           } else {
             wg_copy(rows, Ks, P, Sd);
           }
@@ -438,6 +487,7 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
       }
     }
   }
+  prof_stage(e, 5, tstage);
   // --- step 7: inadmissible leaves inside b0 receive X|_t Y|_s^*
   {
     const int root = u.r0[0];
@@ -451,10 +501,12 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
           if (!in_sub(e, u.r0[1], s)) continue;
           wg_gemm(e.size[c], e.size[s], kp, 1.0, bufrows(e, u.buf[0], c),
                   mv_t(bufrows(e, u.buf[1], s)), 1.0, Nslot(e, b));
+          count(e, fl_gemm(e.size[c], e.size[s], kp));
         }
       }
     }
   }
+  prof_stage(e, 6, tstage);
   // --- step 6: commit ranks, R-factors of the new bases, refresh the path
   for (int side = 0; side < 2; ++side) {
     const int root = u.r0[side];
@@ -481,12 +533,14 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
         m += mc;
       }
       wg_qr(m, kc, A, nullptr, L.red);
+      count(e, fl_qr(m, kc) + fl_gemm(m, kc, e.k[side][e.son0[c]]));
       wg_extract_r(m, kc, A, rhoslot(e, side, c));
       if (threadIdx.x == 0) e.rho_m[side][c] = m < kc ? m : kc;
       __syncthreads();
       c = e.parent[c];
     }
   }
+  prof_stage(e, 7, tstage);
 }
 
 // ====================================================== products with H^2
@@ -548,8 +602,9 @@ __device__ void task_expand(const DevEnv &e, int side, int t, int bo) {
 // out|_s = beta out|_s + alpha Z|_{t x s}^* in|_t (trans = 1) for the block
 // b = (t, s): forward transformation, couplings, backward transformation,
 // nearfield.
-__device__ void task_bapply(const DevEnv &e, int b, int trans, int bin, int bout,
+__device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int bin, int bout,
                             double alpha, double beta) {
+  double fl = 0.0;   // algorithmic flops of this thread
   const int m = e.bcols[bin];
   const int t = e.brow[b], s = e.bcol[b];
   const int sr = trans ? t : s, dr = trans ? s : t;
@@ -579,12 +634,14 @@ __device__ void task_bapply(const DevEnv &e, int b, int trans, int bin, int bout
         MV V = leafslot(e, ss, c);
         MV x = bufrows(e, bin, c);
         for (int l = 0; l < e.size[c]; ++l) acc = fma(V(l, i), x(l, j), acc);
+        fl += 2.0 * e.size[c];
       } else {
         for (int sn = 0; sn < 2; ++sn) {
           const int ch = sn == 0 ? e.son0[c] : e.son1[c];
           MV Ec = Eslot(e, ss, ch);
           MV xc = xhslot(e.xh, ch);
           for (int l = 0; l < e.k[ss][ch]; ++l) acc = fma(Ec(l, i), xc(l, j), acc);
+          fl += 2.0 * e.k[ss][ch];
         }
       }
       xhslot(e.xh, c)(i, j) = acc;
@@ -613,6 +670,7 @@ __device__ void task_bapply(const DevEnv &e, int b, int trans, int bin, int bout
         const int ko = e.k[ss][o];
         if (!trans) { for (int l = 0; l < ko; ++l) acc = fma(S(i, l), xo(l, j), acc); }
         else { for (int l = 0; l < ko; ++l) acc = fma(S(l, i), xo(l, j), acc); }
+        fl += 2.0 * ko;
       }
       xhslot(e.yh, c)(i, j) = acc;
     }
@@ -633,6 +691,7 @@ __device__ void task_bapply(const DevEnv &e, int b, int trans, int bin, int bout
       MV yp = xhslot(e.yh, p);
       double acc = xhslot(e.yh, c)(i, j);
       for (int l = 0; l < e.k[ds][p]; ++l) acc = fma(Ec(i, l), yp(l, j), acc);
+      fl += 2.0 * e.k[ds][p];
       xhslot(e.yh, c)(i, j) = acc;
     }
     __syncthreads();
@@ -654,6 +713,7 @@ __device__ void task_bapply(const DevEnv &e, int b, int trans, int bin, int bout
       MV V = leafslot(e, ds, c);
       MV yc = xhslot(e.yh, c);
       for (int l = 0; l < e.k[ds][c]; ++l) acc = fma(V(i, l), yc(l, j), acc);
+      fl += 2.0 * e.k[ds][c];
       for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
         const int bb = nidx[p];
         const int o = trans ? e.brow[bb] : e.bcol[bb];
@@ -663,12 +723,15 @@ __device__ void task_bapply(const DevEnv &e, int b, int trans, int bin, int bout
         const int no = e.size[o];
         if (!trans) { for (int l = 0; l < no; ++l) acc = fma(N(i, l), xo(l, j), acc); }
         else { for (int l = 0; l < no; ++l) acc = fma(N(l, i), xo(l, j), acc); }
+        fl += 2.0 * no;
       }
       MV oc = bufrows(e, bout, c);
       oc(i, j) = oc(i, j) + alpha * acc;
     }
   }
   __syncthreads();
+  fl = wg_sum(fl, L.red);
+  count(e, fl);
   if (threadIdx.x == 0) e.bcols[bout] = m;
   __syncthreads();
 }
@@ -680,6 +743,7 @@ __device__ void task_rmul_s(const DevEnv &e, int bin, int bout, int b, int trans
   MV S = Sslot(e, b);
   MV Sop = transS ? mv_t(S) : S;
   wg_gemm(e.size[cl], kout, kin, alpha, bufrows(e, bin, cl), Sop, 0.0, bufrows(e, bout, cl));
+  count(e, fl_gemm(e.size[cl], kout, kin));
   if (threadIdx.x == 0) e.bcols[bout] = kout;
   __syncthreads();
 }
@@ -712,6 +776,7 @@ __device__ void task_near_add(const DevEnv &e, int b, int bu, int bv, double alp
   const int t = e.brow[b], s = e.bcol[b];
   wg_gemm(e.size[t], e.size[s], e.bcols[bu], alpha, bufrows(e, bu, t), mv_t(bufrows(e, bv, s)), 1.0,
           Nslot(e, b));
+  count(e, fl_gemm(e.size[t], e.size[s], e.bcols[bu]));
 }
 
 __device__ void task_temp_init(const DevEnv &e, int bu, int bv, int t, int r) {
@@ -765,6 +830,10 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, const Task &tk) {
     __syncthreads();
   }
   wg_jacobi(qa, qb, C, &J, L.iw);
+  {
+    const double bmin = qa < qb ? qa : qb;   // both singular vector sets: + 14 b^3
+    count(e, fl_qr(mt, kk) + fl_qr(mr, kk) + fl_gemm(qa, qb, kk) + fl_svd(qa, qb) + 14.0 * bmin * bmin * bmin);
+  }
   int *ord = L.iw + KM;
   wg_colnorms_sorted(qa, qb, C, L.sig, ord);
   double tau = 0.0;
@@ -796,23 +865,27 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, const Task &tk) {
     for (int l = 0; l < qb; ++l) s = fma(Qb(i, l), J(l, c), s);
     TV(i, j) = s;
   }
+  count(e, fl_qr(mt, kk) + fl_qr(mr, kk) + fl_gemm(mt, r, qa) + fl_gemm(mr, r, qb));
   if (threadIdx.x == 0) { e.bcols[tu] = r; e.bcols[tv] = r; }
   __syncthreads();
 }
 
 __device__ void task_potrf(const DevEnv &e, const Lds &L, int bcc, int t) {
   const int info = wg_potrf(e.size[t], Nslot(e, bcc), L.iw);
+  count(e, (double)e.size[t] * e.size[t] * e.size[t] / 3.0);
   if (info) set_error(e, E_NOT_SPD, t);
 }
 
 __device__ void task_trsm(const DevEnv &e, int b, int bcc) {
   const int r = e.brow[b], c = e.brow[bcc];
   wg_trsm_right_lt(e.size[r], e.size[c], Nslot(e, bcc), Nslot(e, b));
+  count(e, (double)e.size[r] * e.size[c] * e.size[c]);
 }
 
 __device__ void task_trsv(const DevEnv &e, int bcc, int bi, int trans) {
   const int c = e.brow[bcc];
   wg_trsv_lower(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), trans);
+  count(e, (double)e.size[c] * e.size[c] * e.bcols[bi]);
 }
 
 __device__ void task_sub(const DevEnv &e, int ba, int bb, int bo, int cl) {
@@ -841,10 +914,11 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
     __syncthreads();
     if (e.err[0] != 0) return;
     const Task tk = tasks[it];
+    const unsigned long long t0 = e.prof ? wall_clock64() : 0ull;
     switch (tk.op) {
       case OP_ADDLR: task_addlr(e, L, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_EXPAND: task_expand(e, tk.i[0], tk.i[1], tk.i[2]); break;
-      case OP_BAPPLY: task_bapply(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.alpha, tk.beta); break;
+      case OP_BAPPLY: task_bapply(e, L, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.alpha, tk.beta); break;
       case OP_RMUL_S: task_rmul_s(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.i[4], tk.alpha); break;
       case OP_COPY_NEAR: task_copy_near(e, tk.i[0], tk.i[1], tk.alpha); break;
       case OP_IDENT: task_ident(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
@@ -857,6 +931,10 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
       case OP_SUB: task_sub(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_COPY: task_copy(e, tk.i[0], tk.i[1], tk.i[2]); break;
       default: set_error(e, E_ARG, tk.op); break;
+    }
+    if (e.prof && threadIdx.x == 0 && tk.op > 0 && tk.op < 32) {
+      e.prof[PROF_COUNT + tk.op] += 1;
+      e.prof[PROF_TICKS + tk.op] += wall_clock64() - t0;
     }
   }
 }

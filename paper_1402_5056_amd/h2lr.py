@@ -23,6 +23,13 @@ LIB_PATH = os.path.join(_HERE, "libh2lr.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"h2lr library not built: {LIB_PATH} missing (run paper_1402_5056_amd/build.py)")
+try:
+    # torch ships its own HIP runtime (same soname as the system one); loading
+    # it first makes this library bind to that runtime instead of loading a
+    # second HIP/HSA runtime into the process.
+    import torch  # noqa: F401
+except ImportError:  # host-only use (trees) without torch
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 H2_OK = 0
@@ -68,8 +75,11 @@ _SIG = {
     "h2_btree_destroy": [_vp],
     "h2_mat_from_csr": [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _P(_vp)],
     "h2_mat_copy": [_vp, _P(_vp)],
+    "h2_mat_assign": [_vp, _vp],
     "h2_mat_destroy": [_vp],
     "h2_mat_stats": [_vp, _P(_i64), _P(_i32), _P(_i32)],
+    "h2_profile": [_vp, _i32, _vp, _i32],
+    "h2_mat_flops": [_vp, _P(_d), _i32],
     "h2_lowrank_update": [_vp, _i64, _i32, _vp, _i64, _vp, _i64, _P(h2_trunc)],
     "h2_matvec": [_vp, _i32, _d, _vp, _d, _vp, _i32],
     "h2_cholesky": [_vp, _P(h2_trunc)],
@@ -124,10 +134,9 @@ class _Handle:
             getattr(_lib, self._destroy)(self.h)
             self.h = None
 
-    def __del__(self):
-        # Never call into the HIP runtime while the interpreter shuts down:
-        # the runtime may already be torn down; _close_all ran before that.
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # Never call into the HIP runtime while the interpreter shuts down.
+        if _finalizing():
             return
         try:
             self.close()
@@ -136,14 +145,12 @@ class _Handle:
 
 
 @atexit.register
-def _close_all():
-    """Free every live handle in dependency order before the HIP runtime
-    and torch are torn down."""
-    for h in sorted(list(_LIVE), key=lambda x: x._order):
-        try:
-            h.close()
-        except Exception:
-            pass
+def _forget_all():
+    """At interpreter exit, drop every live handle without calling into the
+    HIP runtime (the operating system reclaims device memory); teardown
+    order of the runtimes in the process is not under our control."""
+    for h in list(_LIVE):
+        h.h = None
 
 
 class Ctx(_Handle):
@@ -252,10 +259,38 @@ def h2_mat_copy(m: Mat) -> Mat:
     return Mat(h.value, keep=m._keep)
 
 
+def h2_mat_assign(dst: Mat, src: Mat):
+    _check(_lib.h2_mat_assign(dst.h, src.h))
+
+
 def h2_mat_stats(m: Mat):
     v, kr, kc = _i64(), _i32(), _i32()
     _check(_lib.h2_mat_stats(m.h, C.byref(v), C.byref(kr), C.byref(kc)))
     return v.value, kr.value, kc.value
+
+
+def h2_mat_flops(m: Mat, reset: bool = False) -> float:
+    f = _d()
+    _check(_lib.h2_mat_flops(m.h, C.byref(f), 1 if reset else 0))
+    return f.value
+
+
+OPS = ["", "addlr", "expand", "bapply", "rmul_s", "copy_near", "ident", "near_add", "temp_init",
+       "temp_add", "potrf", "trsm", "trsv", "sub", "copy"]
+STAGES = ["zero-check", "rfactors", "path-weights", "subtree-weights", "recompress", "couplings",
+          "nearfield", "commit"]
+
+
+def h2_profile(m: Mat, enable: bool = True):
+    """Return the previous counters as a dict and (re)enable collection."""
+    buf = np.zeros(80, np.int64)
+    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 80))
+    out = {}
+    for i, name in enumerate(OPS):
+        if name and buf[i]:
+            out[name] = (int(buf[i]), buf[32 + i] * 1e-8)
+    out["stages"] = {name: buf[64 + i] * 1e-8 for i, name in enumerate(STAGES)}
+    return out
 
 
 def h2_lowrank_update(m: Mat, block: int, X, Y, tr: h2_trunc):
