@@ -238,6 +238,7 @@ struct TaskList {
 
 struct h2_mat_s {
   h2_ctx ctx;
+  hipStream_t stream = nullptr;   // own copy: destroy must not touch ctx (may be gone)
   h2_btree bt;
   bool lower = false;
   bool poisoned = false;
@@ -251,6 +252,9 @@ struct h2_mat_s {
   Dev<double> d_pcg;   // PCG vectors and scalars
   Dev<unsigned long long> d_prof;
   Dev<double> d_flops;
+  Dev<DevEnv> d_env;          // device copy of env read by the interpreter
+  DevEnv env_uploaded{};
+  bool env_valid = false;
   TaskList chol, prec;
   DevEnv env{};
 };
@@ -530,8 +534,20 @@ static void set_trunc(h2_mat_s &m, const h2_trunc *tr) {
 
 static bool g_lds_attr_set = false;
 
+// Upload env when it changed since the last upload (blocking copy, so the
+// host struct may change afterwards).
+static void sync_env(h2_mat_s &m) {
+  if (!m.d_env.p) m.d_env.alloc(1);
+  if (!m.env_valid || std::memcmp(&m.env_uploaded, &m.env, sizeof(DevEnv)) != 0) {
+    HIPCHK(hipMemcpy(m.d_env.p, &m.env, sizeof(DevEnv), hipMemcpyHostToDevice));
+    m.env_uploaded = m.env;
+    m.env_valid = true;
+  }
+}
+
 static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
   const size_t lds = LDS_DOUBLES * sizeof(double);
+  sync_env(m);
   if (!g_lds_attr_set) {
     HIPCHK(hipFuncSetAttribute((const void *)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     g_lds_attr_set = true;
@@ -539,7 +555,8 @@ static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
   const int seg = 1 << 24;
   for (int off = 0; off < count; off += seg) {
     const int cnt = std::min(seg, count - off);
-    hipLaunchKernelGGL(k_interp, dim3(1), dim3(NT), lds, m.ctx->stream, d_tasks + off, cnt, m.env);
+    hipLaunchKernelGGL(k_interp, dim3(1), dim3(NT), lds, m.ctx->stream, d_tasks + off, cnt,
+                       (const DevEnv *)m.d_env.p);
     HIPCHK(hipGetLastError());
   }
 }
@@ -699,7 +716,7 @@ h2_status h2_mat_from_csr(h2_ctx ctx, h2_btree bt, int64_t n, const int64_t *row
     REQUIRE(ctx->device >= 0, "a host-only context cannot hold matrices");
     trees_to_device(*bt, ctx->stream);
     auto m = std::make_unique<h2_mat_s>();
-    m->ctx = ctx; m->bt = bt; m->lower = lower != 0;
+    m->ctx = ctx; m->stream = ctx->stream; m->bt = bt; m->lower = lower != 0;
     mat_lists(*m);
     // cluster-order position and leaf of every index
     std::vector<int> pos(n), leafof(n);
@@ -738,7 +755,7 @@ h2_status h2_mat_copy(h2_mat src, h2_mat *out) {
     REQUIRE(src && out, "null argument");
     require_ok(src);
     auto m = std::make_unique<h2_mat_s>();
-    m->ctx = src->ctx; m->bt = src->bt; m->lower = src->lower;
+    m->ctx = src->ctx; m->stream = src->stream; m->bt = src->bt; m->lower = src->lower;
     mat_lists(*m);
     mat_alloc(*m);
     hipStream_t s = src->ctx->stream;
@@ -811,7 +828,8 @@ h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n) {
 }
 
 h2_status h2_mat_destroy(h2_mat m) {
-  if (m) (void)hipStreamSynchronize(m->ctx->stream);
+  // Touches no other object: handles may be destroyed in any order.
+  if (m) (void)hipStreamSynchronize(m->stream);
   delete m;
   return H2_OK;
 }

@@ -59,13 +59,20 @@ __device__ __forceinline__ int wg_or(int v, int *ired) {
 }
 
 // C (m x n) = alpha * A (m x k) * B (k x n) + beta * C.  C must not alias A/B.
+// Thread t computes the entries t, t + NT, ... in column-major order; the
+// row/column of the next entry is advanced without integer division.
 __device__ void wg_gemm(int m, int n, int k, double alpha, MV A, MV B, double beta, MV C) {
-  const int mn = m * n;
-  for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) {
-    const int i = idx % m, j = idx / m;
-    double s = 0.0;
-    for (int l = 0; l < k; ++l) s = fma(A(i, l), B(l, j), s);
-    C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * s;
+  if (m > 0 && n > 0) {
+    const int nt = blockDim.x;
+    int i = threadIdx.x % m, j = threadIdx.x / m;
+    const int di = nt % m, dj = nt / m;
+    while (j < n) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s = fma(A(i, l), B(l, j), s);
+      C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * s;
+      i += di; j += dj;
+      if (i >= m) { i -= m; ++j; }
+    }
   }
   __syncthreads();
 }
@@ -186,50 +193,58 @@ __device__ void wg_form_q(int m, int n, MV A, const double *tau, MV Q) {
 // One-sided (Hestenes) Jacobi: rotate the columns of G (m x n) until they are
 // mutually orthogonal; the same rotations are applied to J (n x n, if not
 // null), which then holds the right singular vectors (G_in J = G_out).
-// Pairs are visited in round-robin order, n/2 disjoint pairs per round, one
-// wave per pair.
+// Pairs are visited in round-robin order; all n/2 disjoint pairs of a round
+// are processed at once, each by a group of g lanes (g a power of two, the
+// groups aligned inside a wave), with one workgroup barrier per round.
 __device__ void wg_jacobi(int m, int n, MV G, MV *J, int *sflag) {
   if (n < 2) { __syncthreads(); return; }
-  const int lane = lane_id(), wave = wave_id(), nw = num_waves();
   const int np = n + (n & 1);
+  const int npairs = np / 2;
+  int g = 64;
+  while (g > 1 && npairs * g > (int)blockDim.x) g >>= 1;
+  const int gid = threadIdx.x / g, gl = threadIdx.x % g, ngroups = blockDim.x / g;
   const double tol = 4.0e-16 * (double)(m > 8 ? m : 8);
   for (int sweep = 0; sweep < 60; ++sweep) {
     __syncthreads();
     if (threadIdx.x == 0) *sflag = 0;
     __syncthreads();
     for (int r = 0; r < np - 1; ++r) {
-      for (int p = wave; p < np / 2; p += nw) {
+      for (int p = gid; p < npairs; p += ngroups) {
         int a, b;
         if (p == 0) { a = np - 1; b = r; }
         else { a = (r + p) % (np - 1); b = (r - p + np - 1) % (np - 1); }
         if (a > b) { const int tt = a; a = b; b = tt; }
         if (b >= n) continue;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += g) {
           const double x = G(i, a), y = G(i, b);
           al = fma(x, x, al); be = fma(y, y, be); ga = fma(x, y, ga);
         }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+        for (int o = g >> 1; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          ga += __shfl_xor(ga, o, 64);
+        }
         if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           double t;
           if (fabs(zeta) > 1.0e100) t = 0.5 / zeta;
           else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int i = lane; i < m; i += 64) {
+          for (int i = gl; i < m; i += g) {
             const double x = G(i, a), y = G(i, b);
             G(i, a) = c * x - s * y;
             G(i, b) = s * x + c * y;
           }
           if (J != nullptr) {
             MV Jm = *J;
-            for (int i = lane; i < n; i += 64) {
+            for (int i = gl; i < n; i += g) {
               const double x = Jm(i, a), y = Jm(i, b);
               Jm(i, a) = c * x - s * y;
               Jm(i, b) = s * x + c * y;
             }
           }
-          if (lane == 0) *sflag = 1;
+          if (gl == 0) *sflag = 1;
         }
       }
       __syncthreads();
@@ -296,36 +311,71 @@ __device__ int wg_potrf(int n, MV A, int *iflag) {
   return r;
 }
 
-// X (m x n) <- X L^{-T} for lower triangular L (n x n): row-wise forward
-// substitution, one thread per row.
-__device__ void wg_trsm_right_lt(int m, int n, MV L, MV X) {
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    for (int j = 0; j < n; ++j) {
-      double s = X(i, j);
-      for (int l = 0; l < j; ++l) s = fma(-L(j, l), X(i, l), s);
-      X(i, j) = s / L(j, j);
+// One wave solves L x = b (trans = 0) or L^T x = b (trans = 1) for lower
+// triangular L (n <= 64): lane i keeps row i (or column i) of L in
+// registers and the solution is propagated with shuffles.
+template <int NMAX>
+__device__ __forceinline__ void wave_load_tri(int n, MV L, int trans, double (&row)[NMAX]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int l = 0; l < NMAX; ++l) {
+    double v = 0.0;
+    if (lane < n && l < n) v = trans ? L(l, lane) : L(lane, l);
+    row[l] = v;
+  }
+}
+
+template <int NMAX>
+__device__ __forceinline__ double wave_tri_solve(int n, const double (&row)[NMAX], int trans, double b) {
+  const int lane = lane_id();
+  // fully unrolled with static indices into row[] (no dynamic register
+  // indexing); steps j >= n are skipped by a uniform predicate
+  if (!trans) {
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+      if (j < n) {
+        const double xj = __shfl(b, j, 64) / __shfl(row[j], j, 64);
+        if (lane == j) b = xj;
+        else if (lane > j) b = fma(-row[j], xj, b);
+      }
     }
+  } else {
+#pragma unroll
+    for (int j = NMAX - 1; j >= 0; --j) {
+      if (j < n) {
+        const double xj = __shfl(b, j, 64) / __shfl(row[j], j, 64);
+        if (lane == j) b = xj;
+        else if (lane < j) b = fma(-row[j], xj, b);
+      }
+    }
+  }
+  return b;
+}
+
+// X (m x n) <- X L^{-T} for lower triangular L (n x n, n <= LS): every row x
+// of X solves L x^T = row^T; one wave per row.
+__device__ void wg_trsm_right_lt(int m, int n, MV L, MV X) {
+  double row[LS];
+  wave_load_tri<LS>(n, L, 0, row);
+  const int lane = lane_id();
+  for (int i = wave_id(); i < m; i += num_waves()) {
+    double b = lane < n ? X(i, lane) : 0.0;
+    b = wave_tri_solve<LS>(n, row, 0, b);
+    if (lane < n) X(i, lane) = b;
   }
   __syncthreads();
 }
 
-// B (n x m) <- L^{-1} B (trans = 0) or L^{-T} B (trans = 1) for lower
-// triangular L (n x n); one thread per column of B.
+// B (n x m) <- L^{-1} B (trans = 0) or L^{-T} B (trans = 1), n <= LS; one
+// wave per column of B.
 __device__ void wg_trsv_lower(int n, int m, MV L, MV B, int trans) {
-  for (int c = threadIdx.x; c < m; c += blockDim.x) {
-    if (!trans) {
-      for (int i = 0; i < n; ++i) {
-        double s = B(i, c);
-        for (int l = 0; l < i; ++l) s = fma(-L(i, l), B(l, c), s);
-        B(i, c) = s / L(i, i);
-      }
-    } else {
-      for (int i = n - 1; i >= 0; --i) {
-        double s = B(i, c);
-        for (int l = i + 1; l < n; ++l) s = fma(-L(l, i), B(l, c), s);
-        B(i, c) = s / L(i, i);
-      }
-    }
+  double row[LS];
+  wave_load_tri<LS>(n, L, trans, row);
+  const int lane = lane_id();
+  for (int c = wave_id(); c < m; c += num_waves()) {
+    double b = lane < n ? B(lane, c) : 0.0;
+    b = wave_tri_solve<LS>(n, row, trans, b);
+    if (lane < n) B(lane, c) = b;
   }
   __syncthreads();
 }

@@ -907,8 +907,10 @@ __device__ void task_copy(const DevEnv &e, int ba, int bo, int cl) {
 }
 
 // ============================================================ interpreter
-__global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, int ntask, DevEnv e) {
+__global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, int ntask,
+                                               const DevEnv *__restrict__ env) {
   extern __shared__ double lds_raw[];
+  const DevEnv &e = *env;
   const Lds L = lds_layout(lds_raw);
   for (int it = 0; it < ntask; ++it) {
     __syncthreads();

@@ -147,8 +147,7 @@ class _Handle:
 @atexit.register
 def _forget_all():
     """At interpreter exit, drop every live handle without calling into the
-    HIP runtime (the operating system reclaims device memory); teardown
-    order of the runtimes in the process is not under our control."""
+    HIP runtime (the operating system reclaims device memory)."""
     for h in list(_LIVE):
         h.h = None
 

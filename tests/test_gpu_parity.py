@@ -180,3 +180,15 @@ def test_nonzero_farfield_rejected(lib):
     with pytest.raises(lib.H2Error) as ei:
         lib.h2_mat_from_csr(ctx, bt, p["A"])
     assert ei.value.name == "H2_ERR_NONZERO_FARFIELD"
+
+
+def test_destroy_in_any_order(lib):
+    """Regression: a matrix may be destroyed after its context and trees
+    (garbage collection finalizes reference cycles in arbitrary order)."""
+    print("case: destroy order", flush=True)
+    p, ctx, bt, M, oc, ob = _setup(lib, 16, leaf=8, lower=True)
+    M2 = lib.h2_mat_copy(M)
+    ctx.close()
+    bt.close()
+    M.close()
+    M2.close()
