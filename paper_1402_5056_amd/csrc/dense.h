@@ -14,16 +14,13 @@ namespace h2 {
 struct MV {
   double *p;
   int rs, cs;
-  __device__ __forceinline__ double &operator()(int i, int j) const {
-    return p[(long)i * rs + (long)j * cs];
-  }
+  // offsets inside one slot/buffer view stay below 2^31 (32-bit arithmetic)
+  __device__ __forceinline__ double &operator()(int i, int j) const { return p[i * rs + j * cs]; }
 };
 __device__ __forceinline__ MV mv_col(double *p, int ld) { return MV{p, 1, ld}; }
 __device__ __forceinline__ MV mv_row(double *p, int ld) { return MV{p, ld, 1}; }
 __device__ __forceinline__ MV mv_t(MV a) { return MV{a.p, a.cs, a.rs}; }
-__device__ __forceinline__ MV mv_at(MV a, int i, int j) {
-  return MV{a.p + (long)i * a.rs + (long)j * a.cs, a.rs, a.cs};
-}
+__device__ __forceinline__ MV mv_at(MV a, int i, int j) { return MV{a.p + i * a.rs + j * a.cs, a.rs, a.cs}; }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
@@ -32,6 +29,25 @@ __device__ __forceinline__ int num_waves() { return blockDim.x >> 6; }
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Register-to-register data movement between lanes (DPP) for doubles.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of g lanes (g in {1, 2, 4, 8, 16}); every lane of
+// the group receives the sum.  Butterfly: xor 1, xor 2 (quad_perm), then
+// half-row and row mirrors.
+__device__ __forceinline__ double group_sum(double v, int g) {
+  if (g >= 2) v += dpp_d<0xB1>(v);     // quad_perm [1,0,3,2]
+  if (g >= 4) v += dpp_d<0x4E>(v);     // quad_perm [2,3,0,1]
+  if (g >= 8) v += dpp_d<0x141>(v);    // row_half_mirror
+  if (g >= 16) v += dpp_d<0x140>(v);   // row_mirror
   return v;
 }
 
@@ -190,20 +206,33 @@ __device__ void wg_form_q(int m, int n, MV A, const double *tau, MV Q) {
   }
 }
 
+// Rotation that makes columns a, b orthogonal given alpha = |a|^2,
+// beta = |b|^2, gamma = a.b: with d = beta - alpha,
+// t = 2 gamma sgn(d) / (|d| + sqrt(d^2 + 4 gamma^2)) (the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = d / (2 gamma)), c = 1/sqrt(1+t^2), s = c t.
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double &c, double &s) {
+  const double d = be - al;
+  const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(fma(d, d, 4.0 * ga * ga)));
+  c = __builtin_amdgcn_rsq(1.0 + t * t);
+  c = c * fma(-0.5 * (1.0 + t * t) * c, c, 1.5);   // one Newton step on the hardware rsqrt
+  s = c * t;
+}
+
 // One-sided (Hestenes) Jacobi: rotate the columns of G (m x n) until they are
 // mutually orthogonal; the same rotations are applied to J (n x n, if not
 // null), which then holds the right singular vectors (G_in J = G_out).
 // Pairs are visited in round-robin order; all n/2 disjoint pairs of a round
 // are processed at once, each by a group of g lanes (g a power of two, the
 // groups aligned inside a wave), with one workgroup barrier per round.
-__device__ void wg_jacobi(int m, int n, MV G, MV *J, int *sflag) {
-  if (n < 2) { __syncthreads(); return; }
+__device__ int wg_jacobi(int m, int n, MV G, MV *J, int *sflag) {
+  if (n < 2) { __syncthreads(); return 0; }
+  int sweeps = 0;
   const int np = n + (n & 1);
   const int npairs = np / 2;
   int g = 64;
   while (g > 1 && npairs * g > (int)blockDim.x) g >>= 1;
   const int gid = threadIdx.x / g, gl = threadIdx.x % g, ngroups = blockDim.x / g;
-  const double tol = 4.0e-16 * (double)(m > 8 ? m : 8);
+  const double tol = 4.0e-16 * (double)(m > 8 ? m : 8), tol2 = tol * tol;
   for (int sweep = 0; sweep < 60; ++sweep) {
     __syncthreads();
     if (threadIdx.x == 0) *sflag = 0;
@@ -225,12 +254,9 @@ __device__ void wg_jacobi(int m, int n, MV G, MV *J, int *sflag) {
           be += __shfl_xor(be, o, 64);
           ga += __shfl_xor(ga, o, 64);
         }
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          double t;
-          if (fabs(zeta) > 1.0e100) t = 0.5 / zeta;
-          else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
+          double c, s;
+          jacobi_rotation(al, be, ga, c, s);
           for (int i = gl; i < m; i += g) {
             const double x = G(i, a), y = G(i, b);
             G(i, a) = c * x - s * y;
@@ -249,31 +275,99 @@ __device__ void wg_jacobi(int m, int n, MV G, MV *J, int *sflag) {
       }
       __syncthreads();
     }
+    ++sweeps;
     if (*sflag == 0) break;
   }
   __syncthreads();
+  return sweeps;
+}
+
+// Single-wave one-sided Jacobi (same rotations and ordering as wg_jacobi):
+// executed by the 64 lanes of one wave, no workgroup barrier.  Each of the
+// n/2 pairs of a round is handled by a group of g lanes (g = largest power
+// of two with pairs * g <= 64); the wave's LDS accesses complete in program
+// order, so rounds only need a compiler scheduling barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ int wave_jacobi(int m, int n, MV G, MV *J) {
+  if (n < 2) return 0;
+  const int lane = lane_id();
+  const int np = n + (n & 1);
+  const int npairs = np / 2;
+  int g = 16;
+  while (g > 1 && npairs * g > 64) g >>= 1;
+  const int gid = lane / g, gl = lane % g, ngroups = 64 / g;
+  const double tol = 4.0e-16 * (double)(m > 8 ? m : 8), tol2 = tol * tol;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int r = 0; r < np - 1; ++r) {
+      for (int p = gid; p < npairs; p += ngroups) {
+        int a, b;
+        if (p == 0) { a = np - 1; b = r; }
+        else {
+          a = r + p; if (a >= np - 1) a -= np - 1;
+          b = r - p + np - 1; if (b >= np - 1) b -= np - 1;
+        }
+        if (a > b) { const int tt = a; a = b; b = tt; }
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (b < n) {
+          for (int i = gl; i < m; i += g) {
+            const double x = G(i, a), y = G(i, b);
+            al = fma(x, x, al); be = fma(y, y, be); ga = fma(x, y, ga);
+          }
+        }
+        // all lanes take part in the DPP reduction (dummy pairs add zeros)
+        al = group_sum(al, g); be = group_sum(be, g); ga = group_sum(ga, g);
+        if (b < n && ga != 0.0 && ga * ga > tol2 * (al * be)) {
+          double c, s;
+          jacobi_rotation(al, be, ga, c, s);
+          for (int i = gl; i < m; i += g) {
+            const double x = G(i, a), y = G(i, b);
+            G(i, a) = c * x - s * y;
+            G(i, b) = s * x + c * y;
+          }
+          if (J != nullptr) {
+            MV Jm = *J;
+            for (int i = gl; i < n; i += g) {
+              const double x = Jm(i, a), y = Jm(i, b);
+              Jm(i, a) = c * x - s * y;
+              Jm(i, b) = s * x + c * y;
+            }
+          }
+          rotated = 1;
+        }
+      }
+      wave_sync();
+    }
+    ++sweeps;
+    if (__ballot(rotated) == 0) break;
+  }
+  return sweeps;
 }
 
 // Column norms of G (m x n) into sig[0..n) and the permutation ord[0..n)
-// sorting them in descending order (stable).
+// sorting them in descending order (ties by index).  One thread per column
+// for the norms, then every column computes its own rank.
 __device__ void wg_colnorms_sorted(int m, int n, MV G, double *sig, int *ord) {
-  const int lane = lane_id(), wave = wave_id(), nw = num_waves();
-  for (int c = wave; c < n; c += nw) {
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
     double s = 0.0;
-    for (int i = lane; i < m; i += 64) { const double x = G(i, c); s = fma(x, x, s); }
-    s = wave_sum(s);
-    if (lane == 0) sig[c] = sqrt(s);
+    for (int i = 0; i < m; ++i) { const double x = G(i, c); s = fma(x, x, s); }
+    sig[c] = sqrt(s);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // stable insertion sort, descending
-    for (int i = 0; i < n; ++i) ord[i] = i;
-    for (int i = 1; i < n; ++i) {
-      const int v = ord[i];
-      int j = i - 1;
-      while (j >= 0 && sig[ord[j]] < sig[v]) { ord[j + 1] = ord[j]; --j; }
-      ord[j + 1] = v;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const double v = sig[c];
+    int rank = 0;
+    for (int c2 = 0; c2 < n; ++c2) {
+      const double w = sig[c2];
+      rank += (w > v || (w == v && c2 < c)) ? 1 : 0;
     }
+    ord[rank] = c;
   }
   __syncthreads();
 }

@@ -237,30 +237,33 @@ __device__ void build_weight(const DevEnv &e, const Upd &u, const Lds &L, int si
 }
 
 // Truncated SVD of M = L.W2 (m x n): left singular vectors of the kept part
-// into Q (m x r, LDS W0), returns r (or -1 past the rank cap).
+// into Q (m x r, W0), returns r (or -1 past the rank cap).  For n <= m the
+// columns of M are orthogonalised (left vectors = normalised columns); for
+// n > m the columns of M^* are, and the accumulated rotations are the left
+// singular vectors of M.
 __device__ int recompress_svd(const DevEnv &e, const Lds &L, int m, int n, MV Q) {
   MV M = mv_col(L.W2, KM);
-  int nG = n;
-  if (n > m) {
-    // left singular vectors of M = those of R^T with M^T = Q R
-    MV T = mv_col(L.W0, W0R);
-    for (int q = threadIdx.x; q < m * n; q += blockDim.x) {
-      const int i = q % m, j = q / m;
-      T(j, i) = M(i, j);
-    }
-    __syncthreads();
-    wg_qr(n, m, T, nullptr, L.red);
-    for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
-      const int i = q % m, j = q / m;
-      M(i, j) = (i >= j) ? T(j, i) : 0.0;   // G = R^T
-    }
-    __syncthreads();
-    nG = m;
-  }
-  wg_jacobi(m, nG, M, nullptr, L.iw);
-  count(e, fl_svd(m, n));
   int *ord = L.iw + KM;
-  wg_colnorms_sorted(m, nG, M, L.sig, ord);
+  const bool trans = n > m;
+  const int nG = trans ? m : n;
+  int sweeps;
+  MV J = mv_at(mv_col(L.W0, W0R), 64, 0);      // rows 64.. of W0 (m x m)
+  if (!trans) {
+    sweeps = wg_jacobi(m, n, M, nullptr, L.iw);
+    wg_colnorms_sorted(m, n, M, L.sig, ord);
+  } else {
+    for (int q = threadIdx.x; q < m * m; q += blockDim.x) J(q % m, q / m) = (q % m == q / m) ? 1.0 : 0.0;
+    __syncthreads();
+    MV Mt = mv_t(M);
+    sweeps = wg_jacobi(n, m, Mt, &J, L.iw);
+    wg_colnorms_sorted(n, m, Mt, L.sig, ord);
+  }
+  if (e.prof && threadIdx.x == 0) {
+    e.prof[PROF_STAGE + 12] += sweeps;
+    e.prof[PROF_STAGE + 13] += 1;
+    e.prof[PROF_STAGE + 14] += nG;
+  }
+  count(e, fl_svd(m, n));
   const double tau = trunc_tau(e, nG > 0 ? L.sig[ord[0]] : 0.0);
   int r = 0;
   for (int j = 0; j < nG; ++j) r += L.sig[ord[j]] > tau ? 1 : 0;
@@ -268,7 +271,7 @@ __device__ int recompress_svd(const DevEnv &e, const Lds &L, int m, int n, MV Q)
   for (int q = threadIdx.x; q < m * r; q += blockDim.x) {
     const int i = q % m, j = q / m;
     const int c = ord[j];
-    Q(i, j) = M(i, c) / L.sig[c];
+    Q(i, j) = trans ? J(i, c) : M(i, c) / L.sig[c];
   }
   __syncthreads();
   return r;
@@ -425,7 +428,9 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
           MV M = mv_col(L.W2, KM);
           wg_gemm(mr, mB, K, 1.0, Vt, mv_t(wslot(e.wB[side], c)), 0.0, M);
           count(e, fl_gemm(mr, mB, K));
+          unsigned long long tsvd = wall_clock64();
           r = recompress_svd(e, L, mr, mB, Q);
+          if (e.prof && threadIdx.x == 0) e.prof[PROF_STAGE + 11] += wall_clock64() - tsvd;
           if (r < 0) { set_error(e, E_RANK_CAP, c); return; }
         }
         // basis change R_c = Q^* V~_c (r x K)

@@ -289,6 +289,8 @@ def h2_profile(m: Mat, enable: bool = True):
         if name and buf[i]:
             out[name] = (int(buf[i]), buf[32 + i] * 1e-8)
     out["stages"] = {name: buf[64 + i] * 1e-8 for i, name in enumerate(STAGES)}
+    out["stages"]["  of which svd"] = buf[64 + 11] * 1e-8
+    out["jacobi"] = {"calls": int(buf[64 + 13]), "sweeps": int(buf[64 + 12]), "cols": int(buf[64 + 14])}
     return out
 
 
