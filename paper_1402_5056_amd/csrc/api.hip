@@ -251,7 +251,7 @@ struct h2_mat_s {
   Dev<double> d_leaf[2], d_E[2], d_rho[2], d_wrho[2], d_wB[2], d_wR[2], d_S, d_N, d_xh, d_yh, d_buf;
   Dev<double> d_pcg;   // PCG vectors and scalars
   Dev<unsigned long long> d_prof;
-  Dev<double> d_flops;
+  Dev<double> d_flops, d_wscr;
   Dev<DevEnv> d_env;          // device copy of env read by the interpreter
   DevEnv env_uploaded{};
   bool env_valid = false;
@@ -297,7 +297,8 @@ static void mat_alloc(h2_mat_s &m) {
   m.d_buf.alloc((size_t)NBUF * ct.n * BC);
   m.d_bcols.alloc(NBUF); m.d_bcols.zero(s);
   m.d_err.alloc(4); m.d_err.zero(s);
-  m.d_flops.alloc(1); m.d_flops.zero(s);
+  m.d_flops.alloc(1 + NWAVE); m.d_flops.zero(s);
+  m.d_wscr.alloc((size_t)NWAVE * WGLOB);
 }
 
 static void mat_lists(h2_mat_s &m) {
@@ -355,7 +356,7 @@ static void mat_env(h2_mat_s &m) {
   }
   e.S = m.d_S.p; e.N = m.d_N.p; e.xh = m.d_xh.p; e.yh = m.d_yh.p;
   for (int i = 0; i < NBUF; ++i) e.buf[i] = m.d_buf.p + (size_t)i * ct.n * BC;
-  e.bcols = m.d_bcols.p; e.err = m.d_err.p; e.flops = m.d_flops.p;
+  e.bcols = m.d_bcols.p; e.err = m.d_err.p; e.flops = m.d_flops.p; e.wscr = m.d_wscr.p;
 }
 
 // ================================================================== planner
@@ -546,7 +547,7 @@ static void sync_env(h2_mat_s &m) {
 }
 
 static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
-  const size_t lds = LDS_DOUBLES * sizeof(double);
+  const size_t lds = LDS_TOTAL_DOUBLES * sizeof(double);
   sync_env(m);
   if (!g_lds_attr_set) {
     HIPCHK(hipFuncSetAttribute((const void *)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -799,8 +800,12 @@ h2_status h2_mat_flops(h2_mat m, double *flops, int32_t reset) {
     REQUIRE(m != nullptr, "null matrix");
     hipStream_t s = m->ctx->stream;
     if (flops) {
-      HIPCHK(hipMemcpyAsync(flops, m->d_flops.p, sizeof(double), hipMemcpyDeviceToHost, s));
+      std::vector<double> h(m->d_flops.n);
+      HIPCHK(hipMemcpyAsync(h.data(), m->d_flops.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      double sum = 0.0;
+      for (double v : h) sum += v;
+      *flops = sum;
     }
     if (reset) m->d_flops.zero(s);
   });

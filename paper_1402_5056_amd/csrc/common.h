@@ -80,7 +80,8 @@ struct DevEnv {
   int *bcols;
   int *err;                        // err[0] code, err[1] info
   unsigned long long *prof;        // optional: per-op counts/ticks, update stage ticks
-  double *flops;                   // algorithmic flop counter (thread 0 of the interpreter)
+  double *flops;                   // algorithmic flops: [0] workgroup code, [1 + w] wave w
+  double *wscr;                    // per-wave global overflow work areas
 };
 
 // Layout of the optional profile counters (ticks of the 100 MHz wall clock).

@@ -350,6 +350,93 @@ __device__ int wave_jacobi(int m, int n, MV G, MV *J) {
   return sweeps;
 }
 
+// ---------------------------------------------------------------------------
+// Wave-level versions: executed by the 64 lanes of one wave, no workgroup
+// barrier, so several waves can work on independent clusters at once.
+
+__device__ __forceinline__ double wave_sum64(double v) {
+  v = group_sum(v, 16);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// C (m x n) = alpha * A (m x k) * B (k x n) + beta * C (no aliasing).
+__device__ void wv_gemm(int m, int n, int k, double alpha, MV A, MV B, double beta, MV C) {
+  if (m > 0 && n > 0) {
+    const int lane = lane_id();
+    int i = lane % m, j = lane / m;
+    const int di = 64 % m, dj = 64 / m;
+    while (j < n) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s = fma(A(i, l), B(l, j), s);
+      C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * s;
+      i += di; j += dj;
+      if (i >= m) { i -= m; ++j; }
+    }
+  }
+  wave_sync();
+}
+
+// Householder QR in place (as wg_qr): the column norm is a wave reduction,
+// the update of the trailing columns runs one lane per column.
+__device__ void wv_qr(int m, int n, MV A, double *tau) {
+  const int lane = lane_id();
+  const int kmax = m < n ? m : n;
+  for (int j = 0; j < kmax; ++j) {
+    double s = 0.0;
+    for (int i = j + 1 + lane; i < m; i += 64) { const double v = A(i, j); s = fma(v, v, s); }
+    s = wave_sum64(s);
+    const double alpha = A(j, j);
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (s > 0.0) {
+      const double nrm = sqrt(fma(alpha, alpha, s));
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    wave_sync();
+    if (t != 0.0) {
+      for (int i = j + 1 + lane; i < m; i += 64) A(i, j) *= scale;
+      wave_sync();
+      for (int c = j + 1 + lane; c < n; c += 64) {
+        double w = A(j, c);
+        for (int i = j + 1; i < m; ++i) w = fma(A(i, j), A(i, c), w);
+        w *= t;
+        A(j, c) -= w;
+        for (int i = j + 1; i < m; ++i) A(i, c) = fma(-w, A(i, j), A(i, c));
+      }
+      wave_sync();
+      if (lane == 0) A(j, j) = beta;
+    } else {
+      for (int i = j + 1 + lane; i < m; i += 64) A(i, j) = 0.0;
+    }
+    if (tau != nullptr && lane == 0) tau[j] = t;
+    wave_sync();
+  }
+}
+
+// Column norms (one lane per column) and descending ranking, wave level.
+__device__ void wv_colnorms_sorted(int m, int n, MV G, double *sig, int *ord) {
+  const int lane = lane_id();
+  for (int c = lane; c < n; c += 64) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) { const double x = G(i, c); s = fma(x, x, s); }
+    sig[c] = sqrt(s);
+  }
+  wave_sync();
+  for (int c = lane; c < n; c += 64) {
+    const double v = sig[c];
+    int rank = 0;
+    for (int c2 = 0; c2 < n; ++c2) {
+      const double w = sig[c2];
+      rank += (w > v || (w == v && c2 < c)) ? 1 : 0;
+    }
+    ord[rank] = c;
+  }
+  wave_sync();
+}
+
 // Column norms of G (m x n) into sig[0..n) and the permutation ord[0..n)
 // sorting them in descending order (ties by index).  One thread per column
 // for the norms, then every column computes its own rank.

@@ -98,11 +98,61 @@ __device__ __forceinline__ void count(const DevEnv &e, double f) {
 }
 
 // ======================================================= low-rank update
+// The update runs level by level.  Inside one level the clusters of both
+// subtrees (for the weights also the predecessors of t0 and s0) depend on
+// each other only through the previous level, so they are processed
+// concurrently, one wave per cluster, with a workgroup barrier per level.
+
+constexpr int NWAVE = NT / 64;
+constexpr int WREG = 4608;      // doubles of LDS per wave for work matrices
+constexpr int WSMALL = 256;     // doubles of LDS per wave for vectors
+constexpr int WGLOB = 16384;    // doubles of global scratch per wave (overflow)
+constexpr size_t LDS_WAVE_DOUBLES = (size_t)NWAVE * (WREG + WSMALL);
+constexpr size_t LDS_TOTAL_DOUBLES = LDS_WAVE_DOUBLES > LDS_DOUBLES ? LDS_WAVE_DOUBLES : LDS_DOUBLES;
+
 struct Upd {
   int r0[2];   // t0, s0
   int buf[2];  // X, Y buffers
   int kp;
 };
+
+struct Wv {
+  double *reg;   // LDS work area
+  double *sig;   // LDS, 64 doubles
+  int *ord;      // LDS, 128 ints
+  double *glob;  // global overflow area
+  int w;
+};
+
+__device__ __forceinline__ Wv wave_areas(double *lds, const DevEnv &e) {
+  Wv W;
+  W.w = wave_id();
+  W.reg = lds + W.w * (WREG + WSMALL);
+  W.sig = W.reg + WREG;
+  W.ord = reinterpret_cast<int *>(W.sig + 64);
+  W.glob = e.wscr + (long)W.w * WGLOB;
+  return W;
+}
+
+// Bump allocation of a wave's work matrices: LDS while it fits, then the
+// wave's global overflow area.  Odd leading dimensions spread LDS banks.
+struct WvAlloc {
+  double *lds, *glob;
+  int lused, gused;
+  __device__ MV take(int m, int n) {
+    const int ld = m | 1;
+    const int need = ld * (n > 0 ? n : 1);
+    double *p;
+    if (lused + need <= WREG) { p = lds + lused; lused += need; }
+    else { p = glob + gused; gused += need; }
+    return mv_col(p, ld);
+  }
+};
+__device__ __forceinline__ WvAlloc wv_alloc(const Wv &W) { return WvAlloc{W.reg, W.glob, 0, 0}; }
+
+__device__ __forceinline__ void count_w(const DevEnv &e, const Wv &W, double f) {
+  if (lane_id() == 0 && e.flops) e.flops[1 + W.w] += f;
+}
 
 // R-factor of the (possibly extended) basis of cluster c.
 __device__ __forceinline__ MV rho_of(const DevEnv &e, const Upd &u, int side, int c, int &m) {
@@ -111,170 +161,354 @@ __device__ __forceinline__ MV rho_of(const DevEnv &e, const Upd &u, int side, in
   return rhoslot(e, side, c);
 }
 
-// Extended coupling S~_b (K_t x K_s) into dst (Section 5, three rules).
-__device__ void load_stilde(const DevEnv &e, const Upd &u, int b, MV dst, int &Kt, int &Ks) {
+// Entry (i, j) of the extended coupling S~_b (Section 5, three rules).
+struct SExt {
+  MV S;
+  int kt, ks, Kt, Ks;
+  bool tin, sin;
+  __device__ __forceinline__ double operator()(int i, int j) const {
+    if (i < kt && j < ks) return S(i, j);
+    return (tin && sin && i >= kt && j >= ks && (i - kt) == (j - ks)) ? 1.0 : 0.0;
+  }
+};
+__device__ __forceinline__ SExt sext(const DevEnv &e, const Upd &u, int b) {
+  SExt x;
   const int t = e.brow[b], s = e.bcol[b];
-  const int kt = e.k[0][t], ks = e.k[1][s];
-  const bool tin = in_sub(e, u.r0[0], t), sin = in_sub(e, u.r0[1], s);
-  Kt = kt + (tin ? u.kp : 0);
-  Ks = ks + (sin ? u.kp : 0);
-  MV S = Sslot(e, b);
-  const int tot = Kt * Ks;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int i = idx % Kt, j = idx / Kt;
-    double v;
-    if (i < kt && j < ks) v = S(i, j);
-    else v = (tin && sin && i >= kt && j >= ks && (i - kt) == (j - ks)) ? 1.0 : 0.0;
-    dst(i, j) = v;
+  x.S = Sslot(e, b);
+  x.kt = e.k[0][t]; x.ks = e.k[1][s];
+  x.tin = in_sub(e, u.r0[0], t); x.sin = in_sub(e, u.r0[1], s);
+  x.Kt = x.kt + (x.tin ? u.kp : 0);
+  x.Ks = x.ks + (x.sin ? u.kp : 0);
+  return x;
+}
+
+// Step 1: R-factor of the extended basis of cluster c (one wave).
+__device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side, int c) {
+  const int lane = lane_id();
+  const int kc = e.k[side][c], K = kc + u.kp;
+  WvAlloc al = wv_alloc(W);
+  int m;
+  MV A;
+  double fl = 0.0;
+  if (is_leaf(e, c)) {
+    m = e.size[c];
+    A = al.take(m, K);
+    MV V = leafslot(e, side, c), F = bufrows(e, u.buf[side], c);
+    for (int q = lane; q < m * K; q += 64) {
+      const int i = q % m, j = q / m;
+      A(i, j) = j < kc ? V(i, j) : F(i, j - kc);
+    }
+  } else {
+    const int c1 = e.son0[c], c2 = e.son1[c];
+    const int m1 = e.wrho_m[side][c1], m2 = e.wrho_m[side][c2];
+    m = m1 + m2;
+    A = al.take(m, K);
+    for (int sn = 0; sn < 2; ++sn) {
+      const int ch = sn == 0 ? c1 : c2, mc = sn == 0 ? m1 : m2, off = sn == 0 ? 0 : m1;
+      const int kch = e.k[side][ch];
+      MV Rc = wslot(e.wrho[side], ch), Ec = Eslot(e, side, ch);
+      for (int q = lane; q < mc * K; q += 64) {
+        const int i = q % mc, j = q / mc;
+        double sacc = 0.0;
+        if (j < kc) { for (int l = 0; l < kch; ++l) sacc = fma(Rc(i, l), Ec(l, j), sacc); }
+        else sacc = Rc(i, kch + (j - kc));
+        A(off + i, j) = sacc;
+      }
+      fl += fl_gemm(mc, kc, kch);
+    }
   }
-  __syncthreads();
-}
-
-// Block scale omega_b = 1/||R_{V,t} S~_b R_{W,s}^*||_F; leaves S~_b in L.W2.
-__device__ double block_scale(const DevEnv &e, const Upd &u, const Lds &L, int b, int &Kt, int &Ks) {
-  MV St = mv_col(L.W2, KM);
-  load_stilde(e, u, b, St, Kt, Ks);
-  if (e.mode != 0) return 1.0;
-  int mt, ms;
-  MV Rt = rho_of(e, u, 0, e.brow[b], mt);
-  MV Rs = rho_of(e, u, 1, e.bcol[b], ms);
-  MV P = mv_col(L.W1, KM);
-  wg_gemm(mt, Ks, Kt, 1.0, Rt, St, 0.0, P);
-  double acc = 0.0;
-  const int tot = mt * ms;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int i = idx % mt, j = idx / mt;
-    double s = 0.0;
-    for (int l = 0; l < Ks; ++l) s = fma(P(i, l), Rs(j, l), s);
-    acc = fma(s, s, acc);
+  wave_sync();
+  wv_qr(m, K, A, nullptr);
+  const int mr = m < K ? m : K;
+  MV R = wslot(e.wrho[side], c);
+  for (int q = lane; q < mr * K; q += 64) {
+    const int i = q % mr, j = q / mr;
+    R(i, j) = j >= i ? A(i, j) : 0.0;
   }
-  const double f2 = wg_sum(acc, L.red);
-  return f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
+  if (lane == 0) e.wrho_m[side][c] = mr;
+  count_w(e, W, fl + fl_qr(m, K));
+  wave_sync();
 }
 
-// Compress the stack rows [0, m) x K of W0 to its R-factor; returns new m.
-__device__ int stack_compress(const Lds &L, int m, int K) {
-  MV A = mv_col(L.W0, W0R);
-  wg_qr(m, K, A, nullptr, L.red);
-  wg_clean_r(m, K, A);
-  return m < K ? m : K;
-}
-
-// Weight matrix B~_t (Section 4, recursion for the weights; all blocks of
-// row(t) as required by Section 5).  insub: t lies in the updated subtree.
-__device__ void build_weight(const DevEnv &e, const Upd &u, const Lds &L, int side, int t, bool insub) {
+// Steps 2/3: weight matrix B~_t (Section 4; all blocks of row(t), Section 5),
+// built by a stack of scaled blocks compressed with QR (one wave).
+__device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, int t, bool insub) {
+  const int lane = lane_id();
   const int kt = e.k[side][t];
   const int Kt = kt + (insub ? u.kp : 0);
-  MV A = mv_col(L.W0, W0R);
+  const int cap = 2 * KM;
+  WvAlloc al = wv_alloc(W);
+  MV A = al.take(cap, Kt);
+  MV P = al.take(KM, KM);
   int m = 0, mrows = 0;
+  double fl = 0.0;
   const int *ptr = side == 0 ? e.rowptr : e.colptr;
   const int *idx = side == 0 ? e.rowidx : e.colidx;
   for (int p = ptr[t]; p < ptr[t + 1]; ++p) {
     const int b = idx[p];
-    int Kbt, Kbs;
-    const double w = block_scale(e, u, L, b, Kbt, Kbs);   // S~ in W2
-    if (w == 0.0) continue;
+    const SExt St = sext(e, u, b);
+    double wsc = 1.0;
+    if (e.mode == 0) {
+      int mt, ms;
+      MV Rt = rho_of(e, u, 0, e.brow[b], mt);
+      MV Rs = rho_of(e, u, 1, e.bcol[b], ms);
+      for (int q = lane; q < mt * St.Ks; q += 64) {
+        const int i = q % mt, j = q / mt;
+        double acc = 0.0;
+        for (int l = 0; l < St.Kt; ++l) acc = fma(Rt(i, l), St(l, j), acc);
+        P(i, j) = acc;
+      }
+      wave_sync();
+      double f2 = 0.0;
+      for (int q = lane; q < mt * ms; q += 64) {
+        const int i = q % mt, j = q / mt;
+        double acc = 0.0;
+        for (int l = 0; l < St.Ks; ++l) acc = fma(P(i, l), Rs(j, l), acc);
+        f2 = fma(acc, acc, f2);
+      }
+      f2 = wave_sum64(f2);
+      wsc = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
+      fl += fl_gemm(mt, St.Ks, St.Kt) + fl_gemm(mt, ms, St.Ks);
+    }
+    if (wsc == 0.0) continue;
     const int other = side == 0 ? e.bcol[b] : e.brow[b];
     int mo;
     MV Ro = rho_of(e, u, 1 - side, other, mo);
     if (mo == 0) continue;
-    if (m + mo > W0R) m = stack_compress(L, m, Kt);
-    MV St = mv_col(L.W2, KM);
-    // side 0: w * R_{W,s} S~^T (mo x K_t); side 1: w * R_{V,t} S~ (mo x K_s)
-    MV B = side == 0 ? mv_t(St) : St;
-    const int Ko = side == 0 ? Kbs : Kbt;
-    wg_gemm(mo, Kt, Ko, w, Ro, B, 0.0, mv_at(A, m, 0));
-    if (e.mode == 0) {
-      int mt, ms;
-      (void)rho_of(e, u, 0, e.brow[b], mt);
-      (void)rho_of(e, u, 1, e.bcol[b], ms);
-      count(e, fl_gemm(mt, Kbs, Kbt) + fl_gemm(mt, ms, Kbs));
+    if (m + mo > cap) {
+      wv_qr(m, Kt, A, nullptr);
+      const int mc = m < Kt ? m : Kt;
+      for (int q = lane; q < mc * mc; q += 64) { const int i = q % mc, j = q / mc; if (i > j) A(i, j) = 0.0; }
+      wave_sync();
+      m = mc;
     }
-    count(e, fl_gemm(mo, Kt, Ko));
-    mrows += mo;
+    // side 0: w R_{W,s} S~^T (mo x K_t); side 1: w R_{V,t} S~ (mo x K_s)
+    const int Ko = side == 0 ? St.Ks : St.Kt;
+    for (int q = lane; q < mo * Kt; q += 64) {
+      const int i = q % mo, j = q / mo;
+      double acc = 0.0;
+      if (side == 0) { for (int l = 0; l < Ko; ++l) acc = fma(Ro(i, l), St(j, l), acc); }
+      else { for (int l = 0; l < Ko; ++l) acc = fma(Ro(i, l), St(l, j), acc); }
+      A(m + i, j) = wsc * acc;
+    }
+    wave_sync();
+    fl += fl_gemm(mo, Kt, Ko);
     m += mo;
+    mrows += mo;
   }
   const int par = e.parent[t];
   if (par >= 0) {
     const bool pin = in_sub(e, u.r0[side], par);
     const int kpar = e.k[side][par];
-    const int Kp = kpar + (pin ? u.kp : 0);
     const int mp = e.wB_m[side][par];
+    (void)pin;
     if (mp > 0) {
-      if (m + mp > W0R) m = stack_compress(L, m, Kt);
-      MV Bp = wslot(e.wB[side], par);
-      MV Et = Eslot(e, side, t);
-      const bool root_of_sub = insub && t == u.r0[side];
-      MV D = mv_at(A, m, 0);
-      const int tot = mp * Kt;
-      for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-        const int i = q % mp, j = q / mp;
-        double s = 0.0;
-        if (j < kt) {
-          for (int l = 0; l < kpar; ++l) s = fma(Bp(i, l), Et(j, l), s);
-        } else if (!root_of_sub) {
-          s = Bp(i, kpar + (j - kt));   // identity part of diag(E_t, I)
-        }
-        D(i, j) = s;
+      if (m + mp > cap) {
+        wv_qr(m, Kt, A, nullptr);
+        const int mc = m < Kt ? m : Kt;
+        for (int q = lane; q < mc * mc; q += 64) { const int i = q % mc, j = q / mc; if (i > j) A(i, j) = 0.0; }
+        wave_sync();
+        m = mc;
       }
-      __syncthreads();
-      count(e, fl_gemm(mp, kt, kpar));
-      mrows += mp;
+      MV Bp = wslot(e.wB[side], par), Et = Eslot(e, side, t);
+      const bool root_of_sub = insub && t == u.r0[side];
+      for (int q = lane; q < mp * Kt; q += 64) {
+        const int i = q % mp, j = q / mp;
+        double acc = 0.0;
+        if (j < kt) { for (int l = 0; l < kpar; ++l) acc = fma(Bp(i, l), Et(j, l), acc); }
+        else if (!root_of_sub) acc = Bp(i, kpar + (j - kt));   // identity part of diag(E_t, I)
+        A(m + i, j) = acc;
+      }
+      wave_sync();
+      fl += fl_gemm(mp, kt, kpar);
       m += mp;
+      mrows += mp;
     }
   }
-  count(e, fl_qr(mrows, Kt));
-  MV W = wslot(e.wB[side], t);
+  MV Wt = wslot(e.wB[side], t);
+  int mr = 0;
   if (m > 0) {
-    wg_qr(m, Kt, A, nullptr, L.red);
-    const int mr = m < Kt ? m : Kt;
-    wg_extract_r(m, Kt, A, W);
-    if (threadIdx.x == 0) e.wB_m[side][t] = mr;
-  } else {
-    if (threadIdx.x == 0) e.wB_m[side][t] = 0;
+    wv_qr(m, Kt, A, nullptr);
+    mr = m < Kt ? m : Kt;
+    for (int q = lane; q < mr * Kt; q += 64) {
+      const int i = q % mr, j = q / mr;
+      Wt(i, j) = j >= i ? A(i, j) : 0.0;
+    }
   }
-  __syncthreads();
+  if (lane == 0) e.wB_m[side][t] = mr;
+  count_w(e, W, fl + fl_qr(mrows, Kt));
+  wave_sync();
 }
 
-// Truncated SVD of M = L.W2 (m x n): left singular vectors of the kept part
-// into Q (m x r, W0), returns r (or -1 past the rank cap).  For n <= m the
-// columns of M are orthogonalised (left vectors = normalised columns); for
-// n > m the columns of M^* are, and the accumulated rotations are the left
-// singular vectors of M.
-__device__ int recompress_svd(const DevEnv &e, const Lds &L, int m, int n, MV Q) {
-  MV M = mv_col(L.W2, KM);
-  int *ord = L.iw + KM;
-  const bool trans = n > m;
-  const int nG = trans ? m : n;
-  int sweeps;
-  MV J = mv_at(mv_col(L.W0, W0R), 64, 0);      // rows 64.. of W0 (m x m)
-  if (!trans) {
-    sweeps = wg_jacobi(m, n, M, nullptr, L.iw);
-    wg_colnorms_sorted(m, n, M, L.sig, ord);
+// Step 4: nested recompression of cluster c (Section 4, eq. (Qt_nested),
+// (hatQt_condensed)): truncated SVD of V~_t B~_t^* (leaf) or V^_t B~_t^*,
+// new basis / transfer matrices and R_t = Q_t^* V~_t.  Returns the new rank
+// or -1 past the rank cap (one wave).
+__device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int side, int c) {
+  const int lane = lane_id();
+  const int root = u.r0[side];
+  const int kc = e.k[side][c], K = kc + u.kp;
+  WvAlloc al = wv_alloc(W);
+  int mr, r1 = 0;
+  MV Vt;
+  double fl = 0.0;
+  if (is_leaf(e, c)) {
+    mr = e.size[c];
+    Vt = al.take(mr, K);
+    MV V = leafslot(e, side, c), F = bufrows(e, u.buf[side], c);
+    for (int q = lane; q < mr * K; q += 64) {
+      const int i = q % mr, j = q / mr;
+      Vt(i, j) = j < kc ? V(i, j) : F(i, j - kc);
+    }
   } else {
-    for (int q = threadIdx.x; q < m * m; q += blockDim.x) J(q % m, q / m) = (q % m == q / m) ? 1.0 : 0.0;
-    __syncthreads();
-    MV Mt = mv_t(M);
-    sweeps = wg_jacobi(n, m, Mt, &J, L.iw);
-    wg_colnorms_sorted(n, m, Mt, L.sig, ord);
+    const int c1 = e.son0[c], c2 = e.son1[c];
+    const int rc1 = e.wnewk[side][c1], rc2 = e.wnewk[side][c2];
+    r1 = rc1;
+    mr = rc1 + rc2;
+    Vt = al.take(mr, K);
+    for (int sn = 0; sn < 2; ++sn) {
+      const int ch = sn == 0 ? c1 : c2, rc = sn == 0 ? rc1 : rc2, off = sn == 0 ? 0 : rc1;
+      const int kch = e.k[side][ch];
+      MV Rc = wslot(e.wR[side], ch), Ec = Eslot(e, side, ch);
+      for (int q = lane; q < rc * K; q += 64) {
+        const int i = q % rc, j = q / rc;
+        double acc = 0.0;
+        if (j < kc) { for (int l = 0; l < kch; ++l) acc = fma(Rc(i, l), Ec(l, j), acc); }
+        else acc = Rc(i, kch + (j - kc));
+        Vt(off + i, j) = acc;
+      }
+      fl += fl_gemm(rc, kc, kch);
+    }
   }
-  if (e.prof && threadIdx.x == 0) {
-    e.prof[PROF_STAGE + 12] += sweeps;
-    e.prof[PROF_STAGE + 13] += 1;
-    e.prof[PROF_STAGE + 14] += nG;
-  }
-  count(e, fl_svd(m, n));
-  const double tau = trunc_tau(e, nG > 0 ? L.sig[ord[0]] : 0.0);
+  wave_sync();
+  const int mB = e.wB_m[side][c];
   int r = 0;
-  for (int j = 0; j < nG; ++j) r += L.sig[ord[j]] > tau ? 1 : 0;
-  if (r > e.rank_cap) return -1;
-  for (int q = threadIdx.x; q < m * r; q += blockDim.x) {
-    const int i = q % m, j = q / m;
-    const int c = ord[j];
-    Q(i, j) = trans ? J(i, c) : M(i, c) / L.sig[c];
+  bool trans = false;
+  MV M{nullptr, 0, 0}, J{nullptr, 0, 0};
+  if (mr > 0 && mB > 0) {
+    M = al.take(mr, mB);
+    wv_gemm(mr, mB, K, 1.0, Vt, mv_t(wslot(e.wB[side], c)), 0.0, M);
+    fl += fl_gemm(mr, mB, K);
+    trans = mB > mr;
+    int sweeps, nG;
+    if (!trans) {
+      sweeps = wave_jacobi(mr, mB, M, nullptr);
+      wv_colnorms_sorted(mr, mB, M, W.sig, W.ord);
+      nG = mB;
+    } else {
+      // left singular vectors of M = accumulated rotations of M^*
+      J = al.take(mr, mr);
+      for (int q = lane; q < mr * mr; q += 64) J(q % mr, q / mr) = (q % mr == q / mr) ? 1.0 : 0.0;
+      wave_sync();
+      MV Mt = mv_t(M);
+      sweeps = wave_jacobi(mB, mr, Mt, &J);
+      wv_colnorms_sorted(mB, mr, Mt, W.sig, W.ord);
+      nG = mr;
+    }
+    fl += fl_svd(mr, mB);
+    if (e.prof && lane == 0) {
+      atomicAdd(&e.prof[PROF_STAGE + 12], (unsigned long long)sweeps);
+      atomicAdd(&e.prof[PROF_STAGE + 13], 1ull);
+      atomicAdd(&e.prof[PROF_STAGE + 14], (unsigned long long)nG);
+    }
+    const double tau = trunc_tau(e, nG > 0 ? W.sig[W.ord[0]] : 0.0);
+    for (int j = 0; j < nG; ++j) r += W.sig[W.ord[j]] > tau ? 1 : 0;
+    if (r > e.rank_cap) {
+      if (lane == 0) { e.err[1] = c; e.err[0] = E_RANK_CAP; }
+      wave_sync();
+      return -1;
+    }
   }
-  __syncthreads();
+  MV Q = al.take(mr, r > 0 ? r : 1);
+  for (int q = lane; q < mr * r; q += 64) {
+    const int i = q % mr, j = q / mr;
+    const int cc = W.ord[j];
+    Q(i, j) = trans ? J(i, cc) : M(i, cc) / W.sig[cc];
+  }
+  wave_sync();
+  wv_gemm(r, K, mr, 1.0, mv_t(Q), Vt, 0.0, wslot(e.wR[side], c));   // R_c = Q^* V~_c
+  fl += fl_gemm(r, K, mr);
+  if (lane == 0) e.wnewk[side][c] = r;
+  if (is_leaf(e, c)) {
+    MV V = leafslot(e, side, c);
+    for (int q = lane; q < mr * r; q += 64) V(q % mr, q / mr) = Q(q % mr, q / mr);
+  } else {
+    MV E1 = Eslot(e, side, e.son0[c]), E2 = Eslot(e, side, e.son1[c]);
+    const int r2 = mr - r1;
+    for (int q = lane; q < r1 * r; q += 64) E1(q % r1, q / r1) = Q(q % r1, q / r1);
+    for (int q = lane; q < r2 * r; q += 64) E2(q % r2, q / r2) = Q(r1 + q % r2, q / r2);
+  }
+  wave_sync();
+  if (c == root && e.parent[c] >= 0) {
+    // E_{t0} <- R_{t0} [E_{t0}; 0]
+    const int kpar = e.k[side][e.parent[c]];
+    MV T = al.take(r, kpar);
+    MV Ec = Eslot(e, side, c);
+    wv_gemm(r, kpar, kc, 1.0, wslot(e.wR[side], c), Ec, 0.0, T);
+    for (int q = lane; q < r * kpar; q += 64) Ec(q % r, q / r) = T(q % r, q / r);
+    fl += fl_gemm(r, kpar, kc);
+  }
+  count_w(e, W, fl);
+  wave_sync();
   return r;
+}
+
+// Step 5: coupling of an admissible leaf touching the subtrees,
+// S_b <- R_t S~_b R_s^* (identity factor outside the subtrees).
+__device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
+  const int lane = lane_id();
+  const SExt St = sext(e, u, b);
+  const int t = e.brow[b], s = e.bcol[b];
+  WvAlloc al = wv_alloc(W);
+  const int rows = St.tin ? e.wnewk[0][t] : St.kt;
+  MV P = al.take(rows, St.Ks);
+  double fl = 0.0;
+  if (St.tin) {
+    MV Rt = wslot(e.wR[0], t);
+    for (int q = lane; q < rows * St.Ks; q += 64) {
+      const int i = q % rows, j = q / rows;
+      double acc = 0.0;
+      for (int l = 0; l < St.Kt; ++l) acc = fma(Rt(i, l), St(l, j), acc);
+      P(i, j) = acc;
+    }
+    fl += fl_gemm(rows, St.Ks, St.Kt);
+  } else {
+    for (int q = lane; q < rows * St.Ks; q += 64) P(q % rows, q / rows) = St(q % rows, q / rows);
+  }
+  wave_sync();
+  MV Sd = Sslot(e, b);
+  if (St.sin) {
+    const int rs = e.wnewk[1][s];
+    wv_gemm(rows, rs, St.Ks, 1.0, P, mv_t(wslot(e.wR[1], s)), 0.0, Sd);
+    fl += fl_gemm(rows, rs, St.Ks);
+  } else {
+    for (int q = lane; q < rows * St.Ks; q += 64) Sd(q % rows, q / rows) = P(q % rows, q / rows);
+  }
+  count_w(e, W, fl);
+  wave_sync();
+}
+
+// R-factor of a predecessor's basis after E_{t0} changed (one wave).
+__device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c) {
+  const int lane = lane_id();
+  const int kc = e.k[side][c];
+  const int c1 = e.son0[c], c2 = e.son1[c];
+  const int m1 = e.rho_m[side][c1], m2 = e.rho_m[side][c2];
+  WvAlloc al = wv_alloc(W);
+  MV A = al.take(m1 + m2, kc);
+  wv_gemm(m1, kc, e.k[side][c1], 1.0, rhoslot(e, side, c1), Eslot(e, side, c1), 0.0, mv_at(A, 0, 0));
+  wv_gemm(m2, kc, e.k[side][c2], 1.0, rhoslot(e, side, c2), Eslot(e, side, c2), 0.0, mv_at(A, m1, 0));
+  const int m = m1 + m2;
+  wv_qr(m, kc, A, nullptr);
+  const int mr = m < kc ? m : kc;
+  MV R = rhoslot(e, side, c);
+  for (int q = lane; q < mr * kc; q += 64) {
+    const int i = q % mr, j = q / mr;
+    R(i, j) = j >= i ? A(i, j) : 0.0;
+  }
+  if (lane == 0) e.rho_m[side][c] = mr;
+  count_w(e, W, fl_qr(m, kc) + fl_gemm(m1, kc, e.k[side][c1]) + fl_gemm(m2, kc, e.k[side][c2]));
+  wave_sync();
 }
 
 __device__ __forceinline__ void prof_stage(const DevEnv &e, int stage, unsigned long long &t) {
@@ -285,7 +519,18 @@ __device__ __forceinline__ void prof_stage(const DevEnv &e, int stage, unsigned 
   }
 }
 
-__device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by) {
+// Number of descendants of r at level lv (0 above r's level or below the leaves).
+__device__ __forceinline__ int nlevel(const DevEnv &e, int r, int lv) {
+  return lv < e.level[r] ? 0 : dhi(e, r, lv) - dlo(e, r, lv);
+}
+
+// Ancestor of c at level lv <= level(c).
+__device__ __forceinline__ int ancestor(const DevEnv &e, int c, int lv) {
+  while (e.level[c] > lv) c = e.parent[c];
+  return c;
+}
+
+__device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, int bx, int by) {
   unsigned long long tstage = wall_clock64();
   Upd u;
   u.r0[0] = e.brow[b0];
@@ -309,214 +554,96 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
     if (nz < 2) return;
   }
   prof_stage(e, 0, tstage);
-  const int kp = u.kp;
-  // --- step 1: R-factors of the extended bases, bottom-up
-  for (int side = 0; side < 2; ++side) {
-    const int root = u.r0[side];
-    for (int lv = e.nlev - 1; lv >= e.level[root]; --lv) {
-      const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
-      for (int c = lo; c < hi; ++c) {
-        const int kc = e.k[side][c];
-        const int K = kc + kp;
-        MV A = mv_col(L.W0, W0R);
-        int m;
-        if (is_leaf(e, c)) {
-          m = e.size[c];
-          MV V = leafslot(e, side, c);
-          MV F = bufrows(e, u.buf[side], c);
-          for (int q = threadIdx.x; q < m * K; q += blockDim.x) {
-            const int i = q % m, j = q / m;
-            A(i, j) = j < kc ? V(i, j) : F(i, j - kc);
-          }
-          __syncthreads();
-        } else {
-          m = 0;
-          for (int sn = 0; sn < 2; ++sn) {
-            const int ch = sn == 0 ? e.son0[c] : e.son1[c];
-            const int mc = e.wrho_m[side][ch];
-            const int kch = e.k[side][ch];
-            MV Rc = wslot(e.wrho[side], ch);
-            MV Ec = Eslot(e, side, ch);
-            MV D = mv_at(A, m, 0);
-            for (int q = threadIdx.x; q < mc * K; q += blockDim.x) {
-              const int i = q % mc, j = q / mc;
-              double s = 0.0;
-              if (j < kc) { for (int l = 0; l < kch; ++l) s = fma(Rc(i, l), Ec(l, j), s); }
-              else s = Rc(i, kch + (j - kc));
-              D(i, j) = s;
-            }
-            __syncthreads();
-            m += mc;
-          }
-        }
-        wg_qr(m, K, A, nullptr, L.red);
-        count(e, fl_qr(m, K) + (is_leaf(e, c) ? 0.0 : fl_gemm(m, kc, e.k[side][e.son0[c]])));
-        wg_extract_r(m, K, A, wslot(e.wrho[side], c));
-        if (threadIdx.x == 0) e.wrho_m[side][c] = m < K ? m : K;
-        __syncthreads();
-      }
+  const Wv W = wave_areas(lds, e);
+  const int lv0[2] = {e.level[u.r0[0]], e.level[u.r0[1]]};
+  const int lvmin = lv0[0] < lv0[1] ? lv0[0] : lv0[1];
+  // --- step 1: R-factors of the extended bases, bottom-up, clusters of a level concurrently
+  for (int lv = e.nlev - 1; lv >= lvmin; --lv) {
+    const int n0 = nlevel(e, u.r0[0], lv), n1 = nlevel(e, u.r0[1], lv);
+    for (int q = W.w; q < n0 + n1; q += NWAVE) {
+      const int side = q < n0 ? 0 : 1;
+      const int c = side == 0 ? dlo(e, u.r0[0], lv) + q : dlo(e, u.r0[1], lv) + (q - n0);
+      wv_rfactor(e, u, W, side, c);
     }
+    __syncthreads();
   }
   prof_stage(e, 1, tstage);
-  // --- steps 2/3: weights along pred(t0) \ {t0}, then through the subtree
-  for (int side = 0; side < 2; ++side) {
-    const int root = u.r0[side];
-    int *path = L.iw + 2 * KM;   // up to KM entries
-    int np = 0;
-    if (threadIdx.x == 0) {
-      int c = e.parent[root];
-      while (c >= 0) { path[np++] = c; c = e.parent[c]; }
-      L.iw[3 * KM + 63] = np;
+  // --- steps 2/3: weights top-down; above t0 / s0 the predecessors, then the subtrees
+  for (int lv = 0; lv < e.nlev; ++lv) {
+    int cnt[2];
+    for (int side = 0; side < 2; ++side) cnt[side] = lv < lv0[side] ? 1 : nlevel(e, u.r0[side], lv);
+    for (int q = W.w; q < cnt[0] + cnt[1]; q += NWAVE) {
+      const int side = q < cnt[0] ? 0 : 1;
+      const int qq = side == 0 ? q : q - cnt[0];
+      if (lv < lv0[side]) wv_weight(e, u, W, side, ancestor(e, u.r0[side], lv), false);
+      else wv_weight(e, u, W, side, dlo(e, u.r0[side], lv) + qq, true);
     }
     __syncthreads();
-    np = L.iw[3 * KM + 63];
-    __syncthreads();
-    for (int q = np - 1; q >= 0; --q) build_weight(e, u, L, side, path[q], false);
-    prof_stage(e, 2, tstage);
-    for (int lv = e.level[root]; lv < e.nlev; ++lv) {
-      const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
-      for (int c = lo; c < hi; ++c) build_weight(e, u, L, side, c, true);
-    }
-    prof_stage(e, 3, tstage);
   }
+  prof_stage(e, 3, tstage);
   // --- step 4: nested recompression, bottom-up
-  for (int side = 0; side < 2; ++side) {
-    const int root = u.r0[side];
-    for (int lv = e.nlev - 1; lv >= e.level[root]; --lv) {
-      const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
-      for (int c = lo; c < hi; ++c) {
-        const int kc = e.k[side][c];
-        const int K = kc + kp;
-        MV Vt = mv_col(L.W1, KM);
-        int mr;
-        int r1 = 0;
-        if (is_leaf(e, c)) {
-          mr = e.size[c];
-          MV V = leafslot(e, side, c);
-          MV F = bufrows(e, u.buf[side], c);
-          for (int q = threadIdx.x; q < mr * K; q += blockDim.x) {
-            const int i = q % mr, j = q / mr;
-            Vt(i, j) = j < kc ? V(i, j) : F(i, j - kc);
-          }
-          __syncthreads();
-        } else {
-          mr = 0;
-          for (int sn = 0; sn < 2; ++sn) {
-            const int ch = sn == 0 ? e.son0[c] : e.son1[c];
-            const int rc = e.wnewk[side][ch];
-            const int kch = e.k[side][ch];
-            MV Rc = wslot(e.wR[side], ch);
-            MV Ec = Eslot(e, side, ch);
-            MV D = mv_at(Vt, mr, 0);
-            for (int q = threadIdx.x; q < rc * K; q += blockDim.x) {
-              const int i = q % rc, j = q / rc;
-              double s = 0.0;
-              if (j < kc) { for (int l = 0; l < kch; ++l) s = fma(Rc(i, l), Ec(l, j), s); }
-              else s = Rc(i, kch + (j - kc));
-              D(i, j) = s;
-            }
-            __syncthreads();
-            if (sn == 0) r1 = rc;
-            mr += rc;
-          }
-        }
-        const int mB = e.wB_m[side][c];
-        int r = 0;
-        MV Q = mv_col(L.W0, W0R);
-        if (!is_leaf(e, c)) count(e, fl_gemm(mr, kc, e.k[side][e.son0[c]]));
-        if (mr > 0 && mB > 0) {
-          MV M = mv_col(L.W2, KM);
-          wg_gemm(mr, mB, K, 1.0, Vt, mv_t(wslot(e.wB[side], c)), 0.0, M);
-          count(e, fl_gemm(mr, mB, K));
-          unsigned long long tsvd = wall_clock64();
-          r = recompress_svd(e, L, mr, mB, Q);
-          if (e.prof && threadIdx.x == 0) e.prof[PROF_STAGE + 11] += wall_clock64() - tsvd;
-          if (r < 0) { set_error(e, E_RANK_CAP, c); return; }
-        }
-        // basis change R_c = Q^* V~_c (r x K)
-        wg_gemm(r, K, mr, 1.0, mv_t(Q), Vt, 0.0, wslot(e.wR[side], c));
-        count(e, fl_gemm(r, K, mr));
-        if (threadIdx.x == 0) e.wnewk[side][c] = r;
-        if (is_leaf(e, c)) {
-          wg_copy(mr, r, Q, leafslot(e, side, c));
-        } else {
-          const int c1 = e.son0[c], c2 = e.son1[c];
-          wg_copy(r1, r, Q, Eslot(e, side, c1));
-          wg_copy(mr - r1, r, mv_at(Q, r1, 0), Eslot(e, side, c2));
-        }
-        if (c == root && e.parent[c] >= 0) {
-          // E_{t0} <- R_{t0} [E_{t0}; 0]
-          const int kpar = e.k[side][e.parent[c]];
-          MV T = mv_col(L.W2, KM);
-          wg_gemm(r, kpar, kc, 1.0, wslot(e.wR[side], c), Eslot(e, side, c), 0.0, T);
-          count(e, fl_gemm(r, kpar, kc));
-          wg_copy(r, kpar, T, Eslot(e, side, c));
-        }
-      }
+  for (int lv = e.nlev - 1; lv >= lvmin; --lv) {
+    const int n0 = nlevel(e, u.r0[0], lv), n1 = nlevel(e, u.r0[1], lv);
+    for (int q = W.w; q < n0 + n1; q += NWAVE) {
+      const int side = q < n0 ? 0 : 1;
+      const int c = side == 0 ? dlo(e, u.r0[0], lv) + q : dlo(e, u.r0[1], lv) + (q - n0);
+      wv_recompress(e, u, W, side, c);
     }
+    __syncthreads();
+    if (e.err[0] != 0) return;
   }
   prof_stage(e, 4, tstage);
   // --- step 5: couplings of every admissible leaf touching the subtrees
-  for (int side = 0; side < 2; ++side) {
-    const int root = u.r0[side];
-    const int *ptr = side == 0 ? e.rowptr : e.colptr;
-    const int *idx = side == 0 ? e.rowidx : e.colidx;
-    for (int lv = e.level[root]; lv < e.nlev; ++lv) {
-      const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
-      for (int c = lo; c < hi; ++c) {
-        for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
-          const int b = idx[p];
-          const int t = e.brow[b], s = e.bcol[b];
-          if (side == 1 && in_sub(e, u.r0[0], t)) continue;
-          const bool tin = in_sub(e, u.r0[0], t), sin = in_sub(e, u.r0[1], s);
-          int Kt, Ks;
-          MV St = mv_col(L.W2, KM);
-          load_stilde(e, u, b, St, Kt, Ks);
-          MV P = St;
-          int rows = Kt;
-          if (tin) {
-            rows = e.wnewk[0][t];
-            P = mv_col(L.W1, KM);
-            wg_gemm(rows, Ks, Kt, 1.0, wslot(e.wR[0], t), St, 0.0, P);
-            count(e, fl_gemm(rows, Ks, Kt));
-          }
-          MV Sd = Sslot(e, b);
-          if (sin) {
-            const int rs = e.wnewk[1][s];
-            wg_gemm(rows, rs, Ks, 1.0, P, mv_t(wslot(e.wR[1], s)), 0.0, Sd);
-            count(e, fl_gemm(rows, rs, Ks));
-          } else {
-            wg_copy(rows, Ks, P, Sd);
+  {
+    int q = 0;
+    for (int side = 0; side < 2; ++side) {
+      const int root = u.r0[side];
+      const int *ptr = side == 0 ? e.rowptr : e.colptr;
+      const int *idx = side == 0 ? e.rowidx : e.colidx;
+      for (int lv = lv0[side]; lv < e.nlev; ++lv) {
+        const int lo = dlo(e, root, lv), hi = lo + nlevel(e, root, lv);
+        for (int c = lo; c < hi; ++c) {
+          for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
+            const int b = idx[p];
+            if (side == 1 && in_sub(e, u.r0[0], e.brow[b])) continue;
+            if (q % NWAVE == W.w) wv_coupling(e, u, W, b);
+            ++q;
           }
         }
       }
     }
+    __syncthreads();
   }
   prof_stage(e, 5, tstage);
   // --- step 7: inadmissible leaves inside b0 receive X|_t Y|_s^*
   {
+    int q = 0;
     const int root = u.r0[0];
-    for (int lv = e.level[root]; lv < e.nlev; ++lv) {
-      const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
+    for (int lv = lv0[0]; lv < e.nlev; ++lv) {
+      const int lo = dlo(e, root, lv), hi = lo + nlevel(e, root, lv);
       for (int c = lo; c < hi; ++c) {
         if (!is_leaf(e, c)) continue;
         for (int p = e.nrowptr[c]; p < e.nrowptr[c + 1]; ++p) {
           const int b = e.nrowidx[p];
           const int s = e.bcol[b];
           if (!in_sub(e, u.r0[1], s)) continue;
-          wg_gemm(e.size[c], e.size[s], kp, 1.0, bufrows(e, u.buf[0], c),
-                  mv_t(bufrows(e, u.buf[1], s)), 1.0, Nslot(e, b));
-          count(e, fl_gemm(e.size[c], e.size[s], kp));
+          if (q % NWAVE == W.w) {
+            wv_gemm(e.size[c], e.size[s], u.kp, 1.0, bufrows(e, u.buf[0], c), mv_t(bufrows(e, u.buf[1], s)),
+                    1.0, Nslot(e, b));
+            count_w(e, W, fl_gemm(e.size[c], e.size[s], u.kp));
+          }
+          ++q;
         }
       }
     }
+    __syncthreads();
   }
   prof_stage(e, 6, tstage);
-  // --- step 6: commit ranks, R-factors of the new bases, refresh the path
+  // --- step 6: commit ranks, identity R-factors of the new bases, refresh the paths
   for (int side = 0; side < 2; ++side) {
     const int root = u.r0[side];
-    for (int lv = e.level[root]; lv < e.nlev; ++lv) {
-      const int lo = dlo(e, root, lv), hi = dhi(e, root, lv);
+    for (int lv = lv0[side]; lv < e.nlev; ++lv) {
+      const int lo = dlo(e, root, lv), hi = lo + nlevel(e, root, lv);
       for (int c = lo; c < hi; ++c) {
         const int r = e.wnewk[side][c];
         MV R = rhoslot(e, side, c);
@@ -524,27 +651,13 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, int b0, int bx, int by
         if (threadIdx.x == 0) { e.k[side][c] = r; e.rho_m[side][c] = r; }
       }
     }
-    __syncthreads();
-    int c = e.parent[root];
-    while (c >= 0) {
-      const int kc = e.k[side][c];
-      MV A = mv_col(L.W0, W0R);
-      int m = 0;
-      for (int sn = 0; sn < 2; ++sn) {
-        const int ch = sn == 0 ? e.son0[c] : e.son1[c];
-        const int mc = e.rho_m[side][ch];
-        wg_gemm(mc, kc, e.k[side][ch], 1.0, rhoslot(e, side, ch), Eslot(e, side, ch), 0.0,
-                mv_at(A, m, 0));
-        m += mc;
-      }
-      wg_qr(m, kc, A, nullptr, L.red);
-      count(e, fl_qr(m, kc) + fl_gemm(m, kc, e.k[side][e.son0[c]]));
-      wg_extract_r(m, kc, A, rhoslot(e, side, c));
-      if (threadIdx.x == 0) e.rho_m[side][c] = m < kc ? m : kc;
-      __syncthreads();
-      c = e.parent[c];
-    }
   }
+  __syncthreads();
+  if (W.w < 2) {
+    const int side = W.w;
+    for (int c = e.parent[u.r0[side]]; c >= 0; c = e.parent[c]) wv_refresh_rho(e, W, side, c);
+  }
+  __syncthreads();
   prof_stage(e, 7, tstage);
 }
 
@@ -923,7 +1036,7 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
     const Task tk = tasks[it];
     const unsigned long long t0 = e.prof ? wall_clock64() : 0ull;
     switch (tk.op) {
-      case OP_ADDLR: task_addlr(e, L, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_ADDLR: task_addlr(e, L, lds_raw, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_EXPAND: task_expand(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_BAPPLY: task_bapply(e, L, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.alpha, tk.beta); break;
       case OP_RMUL_S: task_rmul_s(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.i[4], tk.alpha); break;
