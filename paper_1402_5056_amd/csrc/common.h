@@ -88,6 +88,7 @@ struct DevEnv {
 constexpr int PROF_COUNT = 0;      // [0, 32): tasks executed per op
 constexpr int PROF_TICKS = 32;     // [32, 64): ticks per op
 constexpr int PROF_STAGE = 64;     // [64, 80): ticks per update stage
-constexpr int PROF_LEN = 80;
+constexpr int PROF_BAPPLY = 80;   // [80, 88): ticks of sub-block products by size class, [88, 96): counts
+constexpr int PROF_LEN = 96;
 
 }  // namespace h2

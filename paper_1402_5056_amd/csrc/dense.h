@@ -93,18 +93,25 @@ __device__ void wg_gemm(int m, int n, int k, double alpha, MV A, MV B, double be
   __syncthreads();
 }
 
-__device__ void wg_copy(int m, int n, MV src, MV dst) {
-  const int mn = m * n;
-  for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) {
-    const int i = idx % m, j = idx / m;
-    dst(i, j) = src(i, j);
+// Division-free walk over the entries of an m x n matrix: a thread starts at
+// entry `start` (column-major) and advances by `step` entries.
+struct Walk2 {
+  int i, j, di, dj, m;
+  __device__ __forceinline__ Walk2(int start, int step, int m_) : m(m_) {
+    i = start % m; j = start / m; di = step % m; dj = step / m;
   }
+  __device__ __forceinline__ void next() { i += di; j += dj; if (i >= m) { i -= m; ++j; } }
+};
+
+__device__ void wg_copy(int m, int n, MV src, MV dst) {
+  if (m > 0 && n > 0)
+    for (Walk2 w(threadIdx.x, blockDim.x, m); w.j < n; w.next()) dst(w.i, w.j) = src(w.i, w.j);
   __syncthreads();
 }
 
 __device__ void wg_fill(int m, int n, MV dst, double v) {
-  const int mn = m * n;
-  for (int idx = threadIdx.x; idx < mn; idx += blockDim.x) dst(idx % m, idx / m) = v;
+  if (m > 0 && n > 0)
+    for (Walk2 w(threadIdx.x, blockDim.x, m); w.j < n; w.next()) dst(w.i, w.j) = v;
   __syncthreads();
 }
 

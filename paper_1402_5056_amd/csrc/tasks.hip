@@ -718,51 +718,114 @@ __device__ void task_expand(const DevEnv &e, int side, int t, int bo) {
 
 // out|_t = beta out|_t + alpha Z|_{t x s} in|_s (trans = 0) or
 // out|_s = beta out|_s + alpha Z|_{t x s}^* in|_t (trans = 1) for the block
-// b = (t, s): forward transformation, couplings, backward transformation,
-// nearfield.
+// b = (t, s).  A leaf block of two leaf clusters is staged into LDS and
+// evaluated there; other blocks use the forward transformation, couplings,
+// backward transformation and nearfield products, one wave per cluster.
+__device__ void bapply_leaf(const DevEnv &e, const Lds &L, int b, int trans, int bin, int bout,
+                            double alpha, double beta, int m) {
+  const int t = e.brow[b], s = e.bcol[b];
+  const int nt = e.size[t], ns = e.size[s];
+  const int nsrc = trans ? nt : ns, ndst = trans ? ns : nt;
+  const int src = trans ? t : s, dst = trans ? s : t;
+  MV x = mv_col(L.W0, LS);                 // nsrc x m
+  MV in = bufrows(e, bin, src), out = bufrows(e, bout, dst);
+  double fl;
+  if (e.bkind[b] == 2) {
+    MV N = mv_col(L.W1, LS);               // nt x ns
+    MV Ns = Nslot(e, b);
+    for (Walk2 w(threadIdx.x, blockDim.x, nsrc); w.j < m; w.next()) x(w.i, w.j) = in(w.i, w.j);
+    for (Walk2 w(threadIdx.x, blockDim.x, nt); w.j < ns; w.next()) N(w.i, w.j) = Ns(w.i, w.j);
+    __syncthreads();
+    for (Walk2 w(threadIdx.x, blockDim.x, ndst); w.j < m; w.next()) {
+      double acc = 0.0;
+      if (!trans) { for (int l = 0; l < ns; ++l) acc = fma(N(w.i, l), x(l, w.j), acc); }
+      else { for (int l = 0; l < nt; ++l) acc = fma(N(l, w.i), x(l, w.j), acc); }
+      out(w.i, w.j) = (beta == 0.0 ? 0.0 : beta * out(w.i, w.j)) + alpha * acc;
+    }
+    fl = 2.0 * nt * ns * m;
+  } else {
+    const int kt = e.k[0][t], ks = e.k[1][s];
+    const int ksrc = trans ? kt : ks, kdst = trans ? ks : kt;
+    MV Vs = mv_col(L.W1, LS), Vd = mv_col(L.W1 + LS * KC, LS);   // source / destination bases
+    MV S = mv_col(L.W2, KC);
+    MV xh = mv_col(L.W2 + KC * KC, KC), yh = mv_col(L.W0 + LS * BC, KC);   // k x m (m <= BC)
+    MV Bs = leafslot(e, trans ? 0 : 1, src), Bd = leafslot(e, trans ? 1 : 0, dst), Sg = Sslot(e, b);
+    for (Walk2 w(threadIdx.x, blockDim.x, nsrc); w.j < m; w.next()) x(w.i, w.j) = in(w.i, w.j);
+    if (ksrc > 0) for (Walk2 w(threadIdx.x, blockDim.x, nsrc); w.j < ksrc; w.next()) Vs(w.i, w.j) = Bs(w.i, w.j);
+    if (kdst > 0) for (Walk2 w(threadIdx.x, blockDim.x, ndst); w.j < kdst; w.next()) Vd(w.i, w.j) = Bd(w.i, w.j);
+    if (kt > 0) for (Walk2 w(threadIdx.x, blockDim.x, kt); w.j < ks; w.next()) S(w.i, w.j) = Sg(w.i, w.j);
+    __syncthreads();
+    if (ksrc > 0) for (Walk2 w(threadIdx.x, blockDim.x, ksrc); w.j < m; w.next()) {
+      double acc = 0.0;
+      for (int l = 0; l < nsrc; ++l) acc = fma(Vs(l, w.i), x(l, w.j), acc);
+      xh(w.i, w.j) = acc;
+    }
+    __syncthreads();
+    if (kdst > 0) for (Walk2 w(threadIdx.x, blockDim.x, kdst); w.j < m; w.next()) {
+      double acc = 0.0;
+      if (!trans) { for (int l = 0; l < ks; ++l) acc = fma(S(w.i, l), xh(l, w.j), acc); }
+      else { for (int l = 0; l < kt; ++l) acc = fma(S(l, w.i), xh(l, w.j), acc); }
+      yh(w.i, w.j) = acc;
+    }
+    __syncthreads();
+    for (Walk2 w(threadIdx.x, blockDim.x, ndst); w.j < m; w.next()) {
+      double acc = 0.0;
+      for (int l = 0; l < kdst; ++l) acc = fma(Vd(w.i, l), yh(l, w.j), acc);
+      out(w.i, w.j) = (beta == 0.0 ? 0.0 : beta * out(w.i, w.j)) + alpha * acc;
+    }
+    fl = 2.0 * m * ((double)nsrc * ksrc + (double)kt * ks + (double)ndst * kdst);
+  }
+  count(e, fl);
+  if (threadIdx.x == 0) e.bcols[bout] = m;
+  __syncthreads();
+}
+
 __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int bin, int bout,
                             double alpha, double beta) {
-  double fl = 0.0;   // algorithmic flops of this thread
   const int m = e.bcols[bin];
   const int t = e.brow[b], s = e.bcol[b];
+  if (e.bkind[b] != 0 && is_leaf(e, t) && is_leaf(e, s)) {
+    bapply_leaf(e, L, b, trans, bin, bout, alpha, beta, m);
+    return;
+  }
   const int sr = trans ? t : s, dr = trans ? s : t;
   const int ss = trans ? 0 : 1, ds = 1 - ss;
-  MV out = bufrows(e, bout, dr);
+  const int lane = lane_id(), wv = wave_id();
+  double fl = 0.0;   // counted by lane 0 of each wave
   {
+    MV out = bufrows(e, bout, dr);
     const int rows = e.size[dr];
-    for (int q = threadIdx.x; q < rows * m; q += blockDim.x) {
-      const int i = q / m, j = q % m;
-      out(i, j) = beta == 0.0 ? 0.0 : beta * out(i, j);
-    }
+    for (Walk2 w(threadIdx.x, blockDim.x, rows); w.j < m; w.next())
+      out(w.i, w.j) = beta == 0.0 ? 0.0 : beta * out(w.i, w.j);
   }
   __syncthreads();
   // forward transformation over the source subtree
   for (int lv = e.nlev - 1; lv >= e.level[sr]; --lv) {
-    const int lo = dlo(e, sr, lv), hi = dhi(e, sr, lv);
-    if (lo >= hi) continue;
-    const int tot = (hi - lo) * KC * m;
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-      const int c = lo + q / (KC * m);
-      const int rem = q % (KC * m);
-      const int i = rem / m, j = rem % m;
+    const int lo = dlo(e, sr, lv), hi = lo + nlevel(e, sr, lv);
+    for (int c = lo + wv; c < hi; c += NWAVE) {
       const int kc = e.k[ss][c];
-      if (i >= kc) continue;
-      double acc = 0.0;
+      MV xc = xhslot(e.xh, c);
       if (is_leaf(e, c)) {
-        MV V = leafslot(e, ss, c);
-        MV x = bufrows(e, bin, c);
-        for (int l = 0; l < e.size[c]; ++l) acc = fma(V(l, i), x(l, j), acc);
-        fl += 2.0 * e.size[c];
-      } else {
-        for (int sn = 0; sn < 2; ++sn) {
-          const int ch = sn == 0 ? e.son0[c] : e.son1[c];
-          MV Ec = Eslot(e, ss, ch);
-          MV xc = xhslot(e.xh, ch);
-          for (int l = 0; l < e.k[ss][ch]; ++l) acc = fma(Ec(l, i), xc(l, j), acc);
-          fl += 2.0 * e.k[ss][ch];
+        MV V = leafslot(e, ss, c), x = bufrows(e, bin, c);
+        const int nc = e.size[c];
+        if (kc > 0) for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
+          double acc = 0.0;
+          for (int l = 0; l < nc; ++l) acc = fma(V(l, w.i), x(l, w.j), acc);
+          xc(w.i, w.j) = acc;
         }
+        if (lane == 0) fl += 2.0 * nc * kc * m;
+      } else {
+        const int c1 = e.son0[c], c2 = e.son1[c];
+        const int k1 = e.k[ss][c1], k2 = e.k[ss][c2];
+        MV E1 = Eslot(e, ss, c1), E2 = Eslot(e, ss, c2), x1 = xhslot(e.xh, c1), x2 = xhslot(e.xh, c2);
+        if (kc > 0) for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
+          double acc = 0.0;
+          for (int l = 0; l < k1; ++l) acc = fma(E1(l, w.i), x1(l, w.j), acc);
+          for (int l = 0; l < k2; ++l) acc = fma(E2(l, w.i), x2(l, w.j), acc);
+          xc(w.i, w.j) = acc;
+        }
+        if (lane == 0) fl += 2.0 * (k1 + k2) * kc * m;
       }
-      xhslot(e.xh, c)(i, j) = acc;
     }
     __syncthreads();
   }
@@ -770,47 +833,44 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
   const int *ptr = trans ? e.colptr : e.rowptr;
   const int *idx = trans ? e.colidx : e.rowidx;
   for (int lv = e.level[dr]; lv < e.nlev; ++lv) {
-    const int lo = dlo(e, dr, lv), hi = dhi(e, dr, lv);
-    if (lo >= hi) break;
-    const int tot = (hi - lo) * KC * m;
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-      const int c = lo + q / (KC * m);
-      const int rem = q % (KC * m);
-      const int i = rem / m, j = rem % m;
-      if (i >= e.k[ds][c]) continue;
-      double acc = 0.0;
+    const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
+    for (int c = lo + wv; c < hi; c += NWAVE) {
+      const int kc = e.k[ds][c];
+      if (kc == 0) continue;
+      MV yc = xhslot(e.yh, c);
+      for (Walk2 w(lane, 64, kc); w.j < m; w.next()) yc(w.i, w.j) = 0.0;
       for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
         const int bb = idx[p];
         const int o = trans ? e.brow[bb] : e.bcol[bb];
         if (!in_sub(e, sr, o)) continue;
-        MV S = Sslot(e, bb);
-        MV xo = xhslot(e.xh, o);
+        MV S = Sslot(e, bb), xo = xhslot(e.xh, o);
         const int ko = e.k[ss][o];
-        if (!trans) { for (int l = 0; l < ko; ++l) acc = fma(S(i, l), xo(l, j), acc); }
-        else { for (int l = 0; l < ko; ++l) acc = fma(S(l, i), xo(l, j), acc); }
-        fl += 2.0 * ko;
+        for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
+          double acc = yc(w.i, w.j);
+          if (!trans) { for (int l = 0; l < ko; ++l) acc = fma(S(w.i, l), xo(l, w.j), acc); }
+          else { for (int l = 0; l < ko; ++l) acc = fma(S(l, w.i), xo(l, w.j), acc); }
+          yc(w.i, w.j) = acc;
+        }
+        if (lane == 0) fl += 2.0 * kc * ko * m;
       }
-      xhslot(e.yh, c)(i, j) = acc;
     }
     __syncthreads();
   }
   // backward transformation
   for (int lv = e.level[dr] + 1; lv < e.nlev; ++lv) {
-    const int lo = dlo(e, dr, lv), hi = dhi(e, dr, lv);
-    if (lo >= hi) break;
-    const int tot = (hi - lo) * KC * m;
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-      const int c = lo + q / (KC * m);
-      const int rem = q % (KC * m);
-      const int i = rem / m, j = rem % m;
-      if (i >= e.k[ds][c]) continue;
+    const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
+    for (int c = lo + wv; c < hi; c += NWAVE) {
+      const int kc = e.k[ds][c];
       const int p = e.parent[c];
-      MV Ec = Eslot(e, ds, c);
-      MV yp = xhslot(e.yh, p);
-      double acc = xhslot(e.yh, c)(i, j);
-      for (int l = 0; l < e.k[ds][p]; ++l) acc = fma(Ec(i, l), yp(l, j), acc);
-      fl += 2.0 * e.k[ds][p];
-      xhslot(e.yh, c)(i, j) = acc;
+      const int kp = e.k[ds][p];
+      if (kc == 0) continue;
+      MV Ec = Eslot(e, ds, c), yp = xhslot(e.yh, p), yc = xhslot(e.yh, c);
+      for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
+        double acc = yc(w.i, w.j);
+        for (int l = 0; l < kp; ++l) acc = fma(Ec(w.i, l), yp(l, w.j), acc);
+        yc(w.i, w.j) = acc;
+      }
+      if (lane == 0) fl += 2.0 * kc * kp * m;
     }
     __syncthreads();
   }
@@ -818,38 +878,36 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
   const int *nptr = trans ? e.ncolptr : e.nrowptr;
   const int *nidx = trans ? e.ncolidx : e.nrowidx;
   for (int lv = e.level[dr]; lv < e.nlev; ++lv) {
-    const int lo = dlo(e, dr, lv), hi = dhi(e, dr, lv);
-    if (lo >= hi) break;
-    const int tot = (hi - lo) * LS * m;
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-      const int c = lo + q / (LS * m);
+    const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
+    for (int c = lo + wv; c < hi; c += NWAVE) {
       if (!is_leaf(e, c)) continue;
-      const int rem = q % (LS * m);
-      const int i = rem / m, j = rem % m;
-      if (i >= e.size[c]) continue;
-      double acc = 0.0;
-      MV V = leafslot(e, ds, c);
-      MV yc = xhslot(e.yh, c);
-      for (int l = 0; l < e.k[ds][c]; ++l) acc = fma(V(i, l), yc(l, j), acc);
-      fl += 2.0 * e.k[ds][c];
-      for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
-        const int bb = nidx[p];
-        const int o = trans ? e.brow[bb] : e.bcol[bb];
-        if (!in_sub(e, sr, o)) continue;
-        MV N = Nslot(e, bb);
-        MV xo = bufrows(e, bin, o);
-        const int no = e.size[o];
-        if (!trans) { for (int l = 0; l < no; ++l) acc = fma(N(i, l), xo(l, j), acc); }
-        else { for (int l = 0; l < no; ++l) acc = fma(N(l, i), xo(l, j), acc); }
-        fl += 2.0 * no;
+      const int nc = e.size[c], kc = e.k[ds][c];
+      MV V = leafslot(e, ds, c), yc = xhslot(e.yh, c), oc = bufrows(e, bout, c);
+      for (Walk2 w(lane, 64, nc); w.j < m; w.next()) {
+        double acc = 0.0;
+        for (int l = 0; l < kc; ++l) acc = fma(V(w.i, l), yc(l, w.j), acc);
+        for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
+          const int bb = nidx[p];
+          const int o = trans ? e.brow[bb] : e.bcol[bb];
+          if (!in_sub(e, sr, o)) continue;
+          MV N = Nslot(e, bb), xo = bufrows(e, bin, o);
+          const int no = e.size[o];
+          if (!trans) { for (int l = 0; l < no; ++l) acc = fma(N(w.i, l), xo(l, w.j), acc); }
+          else { for (int l = 0; l < no; ++l) acc = fma(N(l, w.i), xo(l, w.j), acc); }
+        }
+        oc(w.i, w.j) = oc(w.i, w.j) + alpha * acc;
       }
-      MV oc = bufrows(e, bout, c);
-      oc(i, j) = oc(i, j) + alpha * acc;
+      if (lane == 0) {
+        fl += 2.0 * nc * kc * m;
+        for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
+          const int o = trans ? e.brow[nidx[p]] : e.bcol[nidx[p]];
+          if (in_sub(e, sr, o)) fl += 2.0 * nc * e.size[o] * m;
+        }
+      }
     }
   }
+  if (lane == 0 && e.flops) e.flops[1 + wv] += fl;
   __syncthreads();
-  fl = wg_sum(fl, L.red);
-  count(e, fl);
   if (threadIdx.x == 0) e.bcols[bout] = m;
   __syncthreads();
 }
@@ -1038,7 +1096,19 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
     switch (tk.op) {
       case OP_ADDLR: task_addlr(e, L, lds_raw, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_EXPAND: task_expand(e, tk.i[0], tk.i[1], tk.i[2]); break;
-      case OP_BAPPLY: task_bapply(e, L, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.alpha, tk.beta); break;
+      case OP_BAPPLY: {
+        task_bapply(e, L, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.alpha, tk.beta);
+        if (e.prof && threadIdx.x == 0) {
+          // size class by the number of clusters below the destination cluster
+          const int dr = tk.i[1] ? e.bcol[tk.i[0]] : e.brow[tk.i[0]];
+          int nclu = 0;
+          for (int lv = e.level[dr]; lv < e.nlev; ++lv) nclu += dhi(e, dr, lv) - dlo(e, dr, lv);
+          const int cls = nclu <= 1 ? 0 : nclu <= 3 ? 1 : nclu <= 15 ? 2 : nclu <= 63 ? 3 : nclu <= 255 ? 4 : 5;
+          e.prof[PROF_BAPPLY + cls] += wall_clock64() - t0;
+          e.prof[PROF_BAPPLY + 8 + cls] += 1;
+        }
+        break;
+      }
       case OP_RMUL_S: task_rmul_s(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.i[4], tk.alpha); break;
       case OP_COPY_NEAR: task_copy_near(e, tk.i[0], tk.i[1], tk.alpha); break;
       case OP_IDENT: task_ident(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;

@@ -282,8 +282,8 @@ STAGES = ["zero-check", "rfactors", "path-weights", "subtree-weights", "recompre
 
 def h2_profile(m: Mat, enable: bool = True):
     """Return the previous counters as a dict and (re)enable collection."""
-    buf = np.zeros(80, np.int64)
-    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 80))
+    buf = np.zeros(96, np.int64)
+    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 96))
     out = {}
     for i, name in enumerate(OPS):
         if name and buf[i]:
@@ -291,6 +291,8 @@ def h2_profile(m: Mat, enable: bool = True):
     out["stages"] = {name: buf[64 + i] * 1e-8 for i, name in enumerate(STAGES)}
     out["stages"]["  of which svd"] = buf[64 + 11] * 1e-8
     out["jacobi"] = {"calls": int(buf[64 + 13]), "sweeps": int(buf[64 + 12]), "cols": int(buf[64 + 14])}
+    out["bapply_classes"] = {c: (int(buf[88 + i]), buf[80 + i] * 1e-8) for i, c in
+                             enumerate(["1", "2-3", "4-15", "16-63", "64-255", "256+"])}
     return out
 
 
