@@ -577,6 +577,10 @@ static void check_device_error(h2_mat_s &m) {
       snprintf(msg, sizeof msg, "rank cap exceeded at cluster %d", err[1]);
       throw H2Error(H2_ERR_RANK_CAP, msg);
     }
+    if (err[0] == E_SCRATCH) {
+      snprintf(msg, sizeof msg, "internal: wave work area too small (%d doubles requested)", err[1]);
+      throw H2Error(H2_ERR_STATE, msg);
+    }
     snprintf(msg, sizeof msg, "device task failed (code %d, info %d)", err[0], err[1]);
     throw H2Error(H2_ERR_ARG, msg);
   }

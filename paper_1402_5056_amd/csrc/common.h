@@ -13,7 +13,7 @@ constexpr int NT = 256;    // threads of the task interpreter workgroup
 constexpr int KPMAX = KM - KC;  // largest update rank k'
 
 // Device error codes written to err[0] (mirrors h2_status).
-enum : int { E_OK = 0, E_NOT_SPD = -4, E_RANK_CAP = -5, E_ARG = -1 };
+enum : int { E_OK = 0, E_NOT_SPD = -4, E_RANK_CAP = -5, E_ARG = -1, E_SCRATCH = -100 };
 
 // Work buffers: n x BC row-major arrays indexed by cluster-order rows.
 enum Buf : int {
@@ -89,6 +89,8 @@ constexpr int PROF_COUNT = 0;      // [0, 32): tasks executed per op
 constexpr int PROF_TICKS = 32;     // [32, 64): ticks per op
 constexpr int PROF_STAGE = 64;     // [64, 80): ticks per update stage
 constexpr int PROF_BAPPLY = 80;   // [80, 88): ticks of sub-block products by size class, [88, 96): counts
-constexpr int PROF_LEN = 96;
+constexpr int PROF_WAVE = 96;     // [96, 128): per-wave ticks / counts inside update stages
+constexpr int PROF_LEVEL = 128;    // [128, 144): ticks of low-rank updates by level of t0, [144, 160): counts
+constexpr int PROF_LEN = 160;
 
 }  // namespace h2

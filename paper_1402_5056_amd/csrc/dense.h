@@ -40,6 +40,29 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Value of lane 0 in every lane (two v_readlane).
+__device__ __forceinline__ double bcast_lane0(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/x and sqrt(x) (x > 0, normal range) from the hardware approximations,
+// each refined by two Newton steps (relative error a few ulp).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+__device__ __forceinline__ double sqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  const double r = x * y;
+  return fma(0.5 * y, fma(-r, r, x), r);   // one correction of the root itself
+}
+
 // Sum over aligned groups of g lanes (g in {1, 2, 4, 8, 16}); every lane of
 // the group receives the sum.  Butterfly: xor 1, xor 2 (quad_perm), then
 // half-row and row mirrors.
@@ -49,6 +72,24 @@ __device__ __forceinline__ double group_sum(double v, int g) {
   if (g >= 8) v += dpp_d<0x141>(v);    // row_half_mirror
   if (g >= 16) v += dpp_d<0x140>(v);   // row_mirror
   return v;
+}
+
+// Compile-time group size version for three values at once (the levels of
+// the three butterflies are interleaved, no branches).
+template <int G>
+__device__ __forceinline__ void group_sum3(double &a, double &b, double &c) {
+  if (G >= 2) { const double x = dpp_d<0xB1>(a), y = dpp_d<0xB1>(b), z = dpp_d<0xB1>(c); a += x; b += y; c += z; }
+  if (G >= 4) { const double x = dpp_d<0x4E>(a), y = dpp_d<0x4E>(b), z = dpp_d<0x4E>(c); a += x; b += y; c += z; }
+  if (G >= 8) { const double x = dpp_d<0x141>(a), y = dpp_d<0x141>(b), z = dpp_d<0x141>(c); a += x; b += y; c += z; }
+  if (G >= 16) { const double x = dpp_d<0x140>(a), y = dpp_d<0x140>(b), z = dpp_d<0x140>(c); a += x; b += y; c += z; }
+}
+template <int G>
+__device__ __forceinline__ double group_sum_t(double a) {
+  if (G >= 2) a += dpp_d<0xB1>(a);
+  if (G >= 4) a += dpp_d<0x4E>(a);
+  if (G >= 8) a += dpp_d<0x141>(a);
+  if (G >= 16) a += dpp_d<0x140>(a);
+  return a;
 }
 
 // Sum of one value per thread over the workgroup; red holds >= 16 doubles.
@@ -300,7 +341,110 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ int wave_jacobi(int m, int n, MV G, MV *J) {
+// Rotation for the wave-level sweeps: t from the hardware reciprocal and
+// reciprocal square root, each refined by one Newton step; c = 1/sqrt(1+t^2)
+// refined the same way so that c^2 + s^2 = 1 to working precision (the
+// accuracy of t only affects the convergence speed).
+__device__ __forceinline__ void jacobi_rotation_fast(double al, double be, double ga, double &c,
+                                                     double &s) {
+  const double d = be - al;
+  const double h = fma(d, d, 4.0 * ga * ga);
+  double y = __builtin_amdgcn_rsq(h);
+  y = y * fma(-0.5 * h * y, y, 1.5);
+  const double den = fabs(d) + h * y;               // |d| + sqrt(h)
+  double z = __builtin_amdgcn_rcp(den);
+  z = z * fma(-den, z, 2.0);
+  const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) * z;
+  const double u = fma(t, t, 1.0);
+  c = __builtin_amdgcn_rsq(u);
+  c = c * fma(-0.5 * u * c, c, 1.5);
+  s = c * t;
+}
+
+// One-sided Jacobi on G (m x n), one wave, J (n x n) accumulating the
+// rotations when non-null.  Round-robin pairing; each lane group of g lanes
+// owns one pair of a round and keeps its RPL rows of both columns in
+// registers between the dot products and the rotation.  Row indices past the
+// end are clamped to the last row: such lanes load that row, contribute zero
+// to the dot products and store the same values as the lane that owns it, so
+// the loads and stores need no branches (a branch per row makes the compiler
+// wait for every LDS store).  Stops after a sweep without rotation, or after
+// a sweep whose largest rotated relative off-diagonal gamma^2/(alpha beta)
+// stayed below 1e-14: by quadratic convergence the next sweep would rotate
+// by angles of order 1e-14.
+template <int g, int RPL>
+__device__ int wave_jacobi_reg(int m, int n, MV G, MV *J) {
+  const int lane = lane_id();
+  const int np = n + (n & 1);
+  const int npairs = np / 2;
+  const int gid = lane / g, gl = lane % g;
+  const double tol = 4.0e-16 * (double)(m > 8 ? m : 8), tol2 = tol * tol;
+  int ri[RPL], rj[RPL];
+  bool rok[RPL];
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    const int i = gl + k * g;
+    rok[k] = i < m;
+    ri[k] = i < m ? i : m - 1;
+    rj[k] = i < n ? i : n - 1;
+  }
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0, big = 0;
+    for (int r = 0; r < np - 1; ++r) {
+      int a = 0, b = 0;
+      if (gid < npairs) {
+        if (gid == 0) { a = np - 1; b = r; }
+        else {
+          a = r + gid; if (a >= np - 1) a -= np - 1;
+          b = r - gid + np - 1; if (b >= np - 1) b -= np - 1;
+        }
+        if (a > b) { const int tt = a; a = b; b = tt; }
+      }
+      const bool act = gid < npairs && b < n;
+      const int ca = act ? a : 0, cb = act ? b : 0;
+      double x[RPL], y[RPL];
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) { x[k] = G(ri[k], ca); y[k] = G(ri[k], cb); }
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const double xk = rok[k] ? x[k] : 0.0, yk = rok[k] ? y[k] : 0.0;
+        al = fma(xk, xk, al); be = fma(yk, yk, be); ga = fma(xk, yk, ga);
+      }
+      if (!act) { al = 0.0; be = 0.0; ga = 0.0; }
+      group_sum3<g>(al, be, ga);
+      if (act && ga != 0.0 && ga * ga > tol2 * (al * be)) {
+        double c, s;
+        jacobi_rotation_fast(al, be, ga, c, s);
+        if (ga * ga > 1e-14 * (al * be)) big = 1;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          G(ri[k], ca) = c * x[k] - s * y[k];
+          G(ri[k], cb) = s * x[k] + c * y[k];
+        }
+        if (J != nullptr) {
+          const MV Jm = *J;
+          double u[RPL], v[RPL];
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) { u[k] = Jm(rj[k], ca); v[k] = Jm(rj[k], cb); }
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) {
+            Jm(rj[k], ca) = c * u[k] - s * v[k];
+            Jm(rj[k], cb) = s * u[k] + c * v[k];
+          }
+        }
+        rotated = 1;
+      }
+      wave_sync();
+    }
+    ++sweeps;
+    if (__ballot(rotated) == 0 || __ballot(big) == 0) break;
+  }
+  return sweeps;
+}
+
+__device__ int wave_jacobi_loop(int m, int n, MV G, MV *J) {
   if (n < 2) return 0;
   const int lane = lane_id();
   const int np = n + (n & 1);
@@ -311,7 +455,7 @@ __device__ int wave_jacobi(int m, int n, MV G, MV *J) {
   const double tol = 4.0e-16 * (double)(m > 8 ? m : 8), tol2 = tol * tol;
   int sweeps = 0;
   for (int sweep = 0; sweep < 60; ++sweep) {
-    int rotated = 0;
+    int rotated = 0, big = 0;
     for (int r = 0; r < np - 1; ++r) {
       for (int p = gid; p < npairs; p += ngroups) {
         int a, b;
@@ -332,7 +476,8 @@ __device__ int wave_jacobi(int m, int n, MV G, MV *J) {
         al = group_sum(al, g); be = group_sum(be, g); ga = group_sum(ga, g);
         if (b < n && ga != 0.0 && ga * ga > tol2 * (al * be)) {
           double c, s;
-          jacobi_rotation(al, be, ga, c, s);
+          jacobi_rotation_fast(al, be, ga, c, s);
+          if (ga * ga > 1e-14 * (al * be)) big = 1;
           for (int i = gl; i < m; i += g) {
             const double x = G(i, a), y = G(i, b);
             G(i, a) = c * x - s * y;
@@ -352,9 +497,29 @@ __device__ int wave_jacobi(int m, int n, MV G, MV *J) {
       wave_sync();
     }
     ++sweeps;
-    if (__ballot(rotated) == 0) break;
+    if (__ballot(rotated) == 0 || __ballot(big) == 0) break;
   }
   return sweeps;
+}
+
+__device__ int wave_jacobi(int m, int n, MV G, MV *J) {
+  if (n < 2 || m < 1) return 0;
+  const int npairs = (n + (n & 1)) / 2;
+  int g = 16;
+  while (g > 1 && npairs * g > 64) g >>= 1;
+  const int rows = (J != nullptr && n > m) ? n : m;
+  if (g == 16) {
+    if (rows <= 16) return wave_jacobi_reg<16, 1>(m, n, G, J);
+    if (rows <= 32) return wave_jacobi_reg<16, 2>(m, n, G, J);
+    if (rows <= 64) return wave_jacobi_reg<16, 4>(m, n, G, J);
+  } else if (g == 8) {
+    if (rows <= 16) return wave_jacobi_reg<8, 2>(m, n, G, J);
+    if (rows <= 32) return wave_jacobi_reg<8, 4>(m, n, G, J);
+    if (rows <= 64) return wave_jacobi_reg<8, 8>(m, n, G, J);
+  } else if (g == 4) {
+    if (rows <= 32) return wave_jacobi_reg<4, 8>(m, n, G, J);
+  }
+  return wave_jacobi_loop(m, n, G, J);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,52 +550,168 @@ __device__ void wv_gemm(int m, int n, int k, double alpha, MV A, MV B, double be
   wave_sync();
 }
 
-// Householder QR in place (as wg_qr): the column norm is a wave reduction,
-// the update of the trailing columns runs one lane per column.
+// Trailing update of Householder step j (helper of wv_qr).  The lanes form
+// column groups of RG = 2^LG adjacent lanes: lane (g, r) handles the columns
+// c = j+1+g, j+1+g+64/RG, ... on the rows j+1+r (mod RG), in chunks of RPL
+// rows whose loads are issued together (ONE: all rows fit in one chunk and
+// stay in registers between the dot product and the update).  Row indices
+// past the end are clamped to the lane's own first row of the chunk: such
+// entries contribute zero to the dot products and are stored again with the
+// value just computed for that row, so loads and stores need no branches and
+// a duplicate store never sees an already updated entry.  Returns, in every
+// lane, the squared norm of column j+1 below its diagonal after the update.
+template <int LG, int RPL, bool ONE>
+__device__ __forceinline__ double wv_qr_step(int m, int n, int j, MV A, double t, double scale) {
+  constexpr int RG = 1 << LG, CG = 64 >> LG;
+  const int lane = lane_id();
+  const int g = lane >> LG, r = lane & (RG - 1);
+  double snext = 0.0;
+  for (int c = j + 1 + g; c < n; c += CG) {
+    const double ajc = A(j, c);
+    double q = 0.0, coef;
+    if (ONE) {
+      const int i0 = j + 1 + r < m ? j + 1 + r : j + 1;
+      double vj[RPL], vc[RPL];
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int i = j + 1 + r + k * RG, ic = i < m ? i : i0;
+        vj[k] = A(ic, j);
+        vc[k] = A(ic, c);
+      }
+      double p = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) p = fma(j + 1 + r + k * RG < m ? vj[k] : 0.0, vc[k], p);
+      p = group_sum_t<RG>(p);
+      coef = t * fma(scale, p, ajc);
+      const double f = coef * scale;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int i = j + 1 + r + k * RG, ic = i < m ? i : i0;
+        const double a = fma(-f, vj[k], vc[k]);
+        A(ic, c) = a;
+        q = fma(i < m && i > j + 1 ? a : 0.0, a, q);   // rows below the next diagonal entry
+      }
+    } else {
+      double p = 0.0;
+      for (int i0 = j + 1 + r; i0 < m; i0 += RG * RPL) {
+        double vj[RPL], vc[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = i0 + k * RG, ic = i < m ? i : i0;
+          vj[k] = A(ic, j);
+          vc[k] = A(ic, c);
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) p = fma(i0 + k * RG < m ? vj[k] : 0.0, vc[k], p);
+      }
+      p = group_sum_t<RG>(p);
+      coef = t * fma(scale, p, ajc);
+      const double f = coef * scale;
+      for (int i0 = j + 1 + r; i0 < m; i0 += RG * RPL) {
+        double vj[RPL], vc[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = i0 + k * RG, ic = i < m ? i : i0;
+          vj[k] = A(ic, j);
+          vc[k] = A(ic, c);
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = i0 + k * RG, ic = i < m ? i : i0;
+          const double a = fma(-f, vj[k], vc[k]);
+          A(ic, c) = a;
+          q = fma(i < m && i > j + 1 ? a : 0.0, a, q);
+        }
+      }
+    }
+    if (r == 0) A(j, c) = ajc - coef;
+    if (c == j + 1) snext = q;
+  }
+  // the group of column j+1 is g = 0 (lanes 0 .. RG-1)
+  snext = group_sum_t<RG>(snext);
+  return bcast_lane0(snext);
+}
+
+template <int LG>
+__device__ __forceinline__ double wv_qr_step_rows(int m, int n, int j, MV A, double t, double scale) {
+  constexpr int RG = 1 << LG;
+  const int mt = m - j - 1;
+  if (mt <= 2 * RG) return wv_qr_step<LG, 2, true>(m, n, j, A, t, scale);
+  if (mt <= 4 * RG) return wv_qr_step<LG, 4, true>(m, n, j, A, t, scale);
+  if (mt <= 8 * RG) return wv_qr_step<LG, 8, true>(m, n, j, A, t, scale);
+  return wv_qr_step<LG, 8, false>(m, n, j, A, t, scale);
+}
+
+// Householder QR in place, one wave: R in the upper triangle; below it the
+// reflectors v (unit leading entry implied) and tau[j] when tau != nullptr,
+// otherwise unspecified values.  The squared norm that step j+1 needs is
+// accumulated by the trailing update of step j.  The reciprocals and the
+// square root use the hardware approximations refined by Newton steps.
 __device__ void wv_qr(int m, int n, MV A, double *tau) {
   const int lane = lane_id();
   const int kmax = m < n ? m : n;
-  for (int j = 0; j < kmax; ++j) {
-    double s = 0.0;
-    for (int i = j + 1 + lane; i < m; i += 64) { const double v = A(i, j); s = fma(v, v, s); }
+  double s = 0.0;
+  if (kmax > 0) {
+    for (int i = 1 + lane; i < m; i += 64) { const double v = A(i, 0); s = fma(v, v, s); }
     s = wave_sum64(s);
+  }
+  for (int j = 0; j < kmax; ++j) {
     const double alpha = A(j, j);
     double t = 0.0, beta = alpha, scale = 0.0;
     if (s > 0.0) {
-      const double nrm = sqrt(fma(alpha, alpha, s));
+      const double nrm = sqrt_nr(fma(alpha, alpha, s));
       beta = alpha >= 0.0 ? -nrm : nrm;
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+      const double rb = rcp_nr(beta), rd = rcp_nr(alpha - beta);
+      t = (beta - alpha) * rb;
+      scale = rd;
     }
-    wave_sync();
+    const int nt = n - j - 1, mt = m - j - 1;
+    double snext = 0.0;
     if (t != 0.0) {
-      for (int i = j + 1 + lane; i < m; i += 64) A(i, j) *= scale;
-      wave_sync();
-      for (int c = j + 1 + lane; c < n; c += 64) {
-        double w = A(j, c);
-        for (int i = j + 1; i < m; ++i) w = fma(A(i, j), A(i, c), w);
-        w *= t;
-        A(j, c) -= w;
-        for (int i = j + 1; i < m; ++i) A(i, c) = fma(-w, A(i, j), A(i, c));
+      if (nt <= 4 && mt >= 48) snext = wv_qr_step_rows<4>(m, n, j, A, t, scale);
+      else if (nt <= 8 && mt >= 24) snext = wv_qr_step_rows<3>(m, n, j, A, t, scale);
+      else snext = wv_qr_step_rows<2>(m, n, j, A, t, scale);
+      if (tau != nullptr) {
+        for (int i = j + 1 + lane; i < m; i += 64) A(i, j) *= scale;
       }
-      wave_sync();
       if (lane == 0) A(j, j) = beta;
+      wave_sync();
     } else {
       for (int i = j + 1 + lane; i < m; i += 64) A(i, j) = 0.0;
+      wave_sync();
+      for (int i = j + 2 + lane; i < m && j + 1 < n; i += 64) { const double v = A(i, j + 1); snext = fma(v, v, snext); }
+      snext = wave_sum64(snext);
     }
     if (tau != nullptr && lane == 0) tau[j] = t;
-    wave_sync();
+    s = snext;
+  }
+  wave_sync();
+}
+
+// Column norms of G (m x n) into sig, groups of 2^LG lanes per column.
+template <int LG>
+__device__ __forceinline__ void wv_colnorms(int m, int n, MV G, double *sig) {
+  constexpr int g = 1 << LG;
+  const int lane = lane_id(), gl = lane & (g - 1);
+  for (int c0 = 0; c0 < n; c0 += 64 >> LG) {
+    const int c = c0 + (lane >> LG);
+    double s = 0.0;
+    if (c < n) {
+      for (int i = gl; i < m; i += g) { const double x = G(i, c); s = fma(x, x, s); }
+    }
+    s = group_sum_t<g>(s);
+    if (c < n && gl == 0) sig[c] = sqrt(s);
   }
 }
 
-// Column norms (one lane per column) and descending ranking, wave level.
+// Column norms and descending ranking, wave level.  The norms use groups of
+// g lanes per column (rows split over the group, DPP reduction).
 __device__ void wv_colnorms_sorted(int m, int n, MV G, double *sig, int *ord) {
   const int lane = lane_id();
-  for (int c = lane; c < n; c += 64) {
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) { const double x = G(i, c); s = fma(x, x, s); }
-    sig[c] = sqrt(s);
-  }
+  if (n <= 8) wv_colnorms<3>(m, n, G, sig);
+  else if (n <= 16) wv_colnorms<2>(m, n, G, sig);
+  else if (n <= 32) wv_colnorms<1>(m, n, G, sig);
+  else wv_colnorms<0>(m, n, G, sig);
   wave_sync();
   for (int c = lane; c < n; c += 64) {
     const double v = sig[c];

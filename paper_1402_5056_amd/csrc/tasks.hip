@@ -104,7 +104,7 @@ __device__ __forceinline__ void count(const DevEnv &e, double f) {
 // concurrently, one wave per cluster, with a workgroup barrier per level.
 
 constexpr int NWAVE = NT / 64;
-constexpr int WREG = 4608;      // doubles of LDS per wave for work matrices
+constexpr int WREG = 4864;      // doubles of LDS per wave for work matrices
 constexpr int WSMALL = 256;     // doubles of LDS per wave for vectors
 constexpr int WGLOB = 16384;    // doubles of global scratch per wave (overflow)
 constexpr size_t LDS_WAVE_DOUBLES = (size_t)NWAVE * (WREG + WSMALL);
@@ -136,22 +136,58 @@ __device__ __forceinline__ Wv wave_areas(double *lds, const DevEnv &e) {
 
 // Bump allocation of a wave's work matrices: LDS while it fits, then the
 // wave's global overflow area.  Odd leading dimensions spread LDS banks.
+// A request beyond the overflow area reports E_SCRATCH and reuses the start
+// of the area, so that every access stays in bounds.
 struct WvAlloc {
   double *lds, *glob;
+  int *err;
   int lused, gused;
   __device__ MV take(int m, int n) {
     const int ld = m | 1;
     const int need = ld * (n > 0 ? n : 1);
     double *p;
     if (lused + need <= WREG) { p = lds + lused; lused += need; }
-    else { p = glob + gused; gused += need; }
+    else if (gused + need <= WGLOB) { p = glob + gused; gused += need; }
+    else {
+      if (lane_id() == 0) { err[1] = need; err[0] = E_SCRATCH; }
+      p = glob;
+    }
     return mv_col(p, ld);
   }
 };
-__device__ __forceinline__ WvAlloc wv_alloc(const Wv &W) { return WvAlloc{W.reg, W.glob, 0, 0}; }
+__device__ __forceinline__ WvAlloc wv_alloc(const DevEnv &e, const Wv &W) {
+  return WvAlloc{W.reg, W.glob, e.err, 0, 0};
+}
 
 __device__ __forceinline__ void count_w(const DevEnv &e, const Wv &W, double f) {
   if (lane_id() == 0 && e.flops) e.flops[1 + W.w] += f;
+}
+
+// Per-wave tracing: ticks spent in a sub-step (summed over waves) and event
+// counts.  No-ops unless profiling is enabled.
+enum : int {
+  WT_RF_BUILD = 0, WT_RF_QR, WT_W_OMEGA, WT_W_STACK, WT_W_QR, WT_RC_BUILD, WT_RC_M, WT_RC_SVD,
+  WT_RC_OUT, WT_CPL, WT_REFRESH, WT_NEAR,
+  WC_W_CALLS = 16, WC_W_BLOCKS, WC_W_NONEMPTY, WC_QR_CALLS, WC_QR_COLS, WC_QR_ROWS, WC_REFRESH
+};
+__device__ __forceinline__ unsigned long long wt_now(const DevEnv &e) {
+  return e.prof ? wall_clock64() : 0ull;
+}
+__device__ __forceinline__ void wt_add(const DevEnv &e, int slot, unsigned long long &t) {
+  if (e.prof) {
+    const unsigned long long now = wall_clock64();
+    if (lane_id() == 0) atomicAdd(&e.prof[PROF_WAVE + slot], now - t);
+    t = now;
+  }
+}
+__device__ __forceinline__ void wc_add(const DevEnv &e, int slot, long v) {
+  if (e.prof && lane_id() == 0) atomicAdd(&e.prof[PROF_WAVE + slot], (unsigned long long)v);
+}
+__device__ __forceinline__ void wv_qr_traced(const DevEnv &e, int m, int n, MV A) {
+  wc_add(e, WC_QR_CALLS, 1);
+  wc_add(e, WC_QR_COLS, m < n ? m : n);
+  wc_add(e, WC_QR_ROWS, m);
+  wv_qr(m, n, A, nullptr);
 }
 
 // R-factor of the (possibly extended) basis of cluster c.
@@ -185,8 +221,9 @@ __device__ __forceinline__ SExt sext(const DevEnv &e, const Upd &u, int b) {
 // Step 1: R-factor of the extended basis of cluster c (one wave).
 __device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side, int c) {
   const int lane = lane_id();
+  unsigned long long tw = wt_now(e);
   const int kc = e.k[side][c], K = kc + u.kp;
-  WvAlloc al = wv_alloc(W);
+  WvAlloc al = wv_alloc(e, W);
   int m;
   MV A;
   double fl = 0.0;
@@ -218,7 +255,9 @@ __device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side,
     }
   }
   wave_sync();
-  wv_qr(m, K, A, nullptr);
+  wt_add(e, WT_RF_BUILD, tw);
+  wv_qr_traced(e, m, K, A);
+  wt_add(e, WT_RF_QR, tw);
   const int mr = m < K ? m : K;
   MV R = wslot(e.wrho[side], c);
   for (int q = lane; q < mr * K; q += 64) {
@@ -231,68 +270,96 @@ __device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side,
 }
 
 // Steps 2/3: weight matrix B~_t (Section 4; all blocks of row(t), Section 5),
-// built by a stack of scaled blocks compressed with QR (one wave).
+// built by a stack of scaled blocks compressed with QR (one wave).  For a
+// block b the stacked rows are G_b = rho_o S~_b^* (row side, rho_o the column
+// R-factor of s) or rho_o S~_b (column side, rho_o the row R-factor of t);
+// the block-relative scale is 1 / ||rho_t S~_b rho_s^*||_F = 1 / ||G_b rho^*||_F
+// with rho the R-factor of the cluster itself.  The operands of a block are
+// staged in LDS first; blocks whose extended coupling is identically zero
+// add nothing to the R-factor and are skipped.
 __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, int t, bool insub) {
   const int lane = lane_id();
+  unsigned long long tw = wt_now(e);
+  wc_add(e, WC_W_CALLS, 1);
   const int kt = e.k[side][t];
   const int Kt = kt + (insub ? u.kp : 0);
-  const int cap = 2 * KM;
-  WvAlloc al = wv_alloc(W);
+  const int cap = Kt + KM;          // any single block fits after a compression
+  WvAlloc al = wv_alloc(e, W);
+  int mown = 0;
+  MV Rown{nullptr, 0, 0};
+  if (e.mode == 0) {
+    MV Rg = rho_of(e, u, side, t, mown);
+    Rown = al.take(mown, Kt);
+    for (int q = lane; q < mown * Kt; q += 64) Rown(q % mown, q / mown) = Rg(q % mown, q / mown);
+  }
   MV A = al.take(cap, Kt);
-  MV P = al.take(KM, KM);
+  const WvAlloc blk0 = al;          // per-block staging starts here
   int m = 0, mrows = 0;
   double fl = 0.0;
   const int *ptr = side == 0 ? e.rowptr : e.colptr;
   const int *idx = side == 0 ? e.rowidx : e.colidx;
   for (int p = ptr[t]; p < ptr[t + 1]; ++p) {
     const int b = idx[p];
-    const SExt St = sext(e, u, b);
-    double wsc = 1.0;
-    if (e.mode == 0) {
-      int mt, ms;
-      MV Rt = rho_of(e, u, 0, e.brow[b], mt);
-      MV Rs = rho_of(e, u, 1, e.bcol[b], ms);
-      for (int q = lane; q < mt * St.Ks; q += 64) {
-        const int i = q % mt, j = q / mt;
-        double acc = 0.0;
-        for (int l = 0; l < St.Kt; ++l) acc = fma(Rt(i, l), St(l, j), acc);
-        P(i, j) = acc;
-      }
-      wave_sync();
-      double f2 = 0.0;
-      for (int q = lane; q < mt * ms; q += 64) {
-        const int i = q % mt, j = q / mt;
-        double acc = 0.0;
-        for (int l = 0; l < St.Ks; ++l) acc = fma(P(i, l), Rs(j, l), acc);
-        f2 = fma(acc, acc, f2);
-      }
-      f2 = wave_sum64(f2);
-      wsc = f2 > 0.0 ? 1.0 / sqrt(f2) : 0.0;
-      fl += fl_gemm(mt, St.Ks, St.Kt) + fl_gemm(mt, ms, St.Ks);
-    }
-    if (wsc == 0.0) continue;
-    const int other = side == 0 ? e.bcol[b] : e.brow[b];
+    wc_add(e, WC_W_BLOCKS, 1);
+    const int bt = e.brow[b], bs = e.bcol[b];
+    const int kbt = e.k[0][bt], kbs = e.k[1][bs];
+    const bool tin = in_sub(e, u.r0[0], bt), sin = in_sub(e, u.r0[1], bs);
+    const bool ext = tin && sin && u.kp > 0;
+    if (!((kbt > 0 && kbs > 0) || ext)) continue;     // S~_b = 0
+    if (e.mode == 0 && mown == 0) continue;           // scale 1/0: block dropped
     int mo;
-    MV Ro = rho_of(e, u, 1 - side, other, mo);
+    MV Rog = rho_of(e, u, 1 - side, side == 0 ? bs : bt, mo);
     if (mo == 0) continue;
+    const int Kbt = kbt + (tin ? u.kp : 0), Kbs = kbs + (sin ? u.kp : 0);
+    const int Ko = side == 0 ? Kbs : Kbt;
+    // stage T = S~_b (row side) or S~_b^* (column side), Kt x Ko, and rho_o
+    WvAlloc sa = blk0;
+    MV T = sa.take(Kt, Ko), Ro = sa.take(mo, Ko);
+    const MV S = Sslot(e, b);
+    for (int q = lane; q < Kt * Ko; q += 64) {
+      const int j = q % Kt, l = q / Kt;
+      const int i0 = side == 0 ? j : l, j0 = side == 0 ? l : j;   // entry (i0, j0) of S~_b
+      double v;
+      if (i0 < kbt && j0 < kbs) v = S(i0, j0);
+      else v = (ext && i0 >= kbt && j0 >= kbs && i0 - kbt == j0 - kbs) ? 1.0 : 0.0;
+      T(j, l) = v;
+    }
+    for (int q = lane; q < mo * Ko; q += 64) Ro(q % mo, q / mo) = Rog(q % mo, q / mo);
     if (m + mo > cap) {
-      wv_qr(m, Kt, A, nullptr);
+      wt_add(e, WT_W_STACK, tw);
+      wv_qr_traced(e, m, Kt, A);    // ends with wave_sync (also for the staging)
       const int mc = m < Kt ? m : Kt;
       for (int q = lane; q < mc * mc; q += 64) { const int i = q % mc, j = q / mc; if (i > j) A(i, j) = 0.0; }
-      wave_sync();
       m = mc;
+      wt_add(e, WT_W_QR, tw);
     }
-    // side 0: w R_{W,s} S~^T (mo x K_t); side 1: w R_{V,t} S~ (mo x K_s)
-    const int Ko = side == 0 ? St.Ks : St.Kt;
+    wave_sync();
+    wc_add(e, WC_W_NONEMPTY, 1);
+    // G_b = rho_o T^* into rows m .. m+mo of the stack
     for (int q = lane; q < mo * Kt; q += 64) {
       const int i = q % mo, j = q / mo;
       double acc = 0.0;
-      if (side == 0) { for (int l = 0; l < Ko; ++l) acc = fma(Ro(i, l), St(j, l), acc); }
-      else { for (int l = 0; l < Ko; ++l) acc = fma(Ro(i, l), St(l, j), acc); }
-      A(m + i, j) = wsc * acc;
+      for (int l = 0; l < Ko; ++l) acc = fma(Ro(i, l), T(j, l), acc);
+      A(m + i, j) = acc;
     }
     wave_sync();
     fl += fl_gemm(mo, Kt, Ko);
+    if (e.mode == 0) {
+      double f2 = 0.0;
+      for (int q = lane; q < mo * mown; q += 64) {
+        const int i = q % mo, a = q / mo;
+        double acc = 0.0;
+        for (int j = 0; j < Kt; ++j) acc = fma(A(m + i, j), Rown(a, j), acc);
+        f2 = fma(acc, acc, f2);
+      }
+      f2 = wave_sum64(f2);
+      fl += fl_gemm(mo, mown, Kt);
+      if (f2 == 0.0) { wt_add(e, WT_W_OMEGA, tw); continue; }
+      const double wsc = 1.0 / sqrt(f2);
+      for (int q = lane; q < mo * Kt; q += 64) A(m + q % mo, q / mo) *= wsc;
+      wave_sync();
+    }
+    wt_add(e, WT_W_OMEGA, tw);
     m += mo;
     mrows += mo;
   }
@@ -304,7 +371,7 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
     (void)pin;
     if (mp > 0) {
       if (m + mp > cap) {
-        wv_qr(m, Kt, A, nullptr);
+        wv_qr_traced(e, m, Kt, A);
         const int mc = m < Kt ? m : Kt;
         for (int q = lane; q < mc * mc; q += 64) { const int i = q % mc, j = q / mc; if (i > j) A(i, j) = 0.0; }
         wave_sync();
@@ -327,8 +394,9 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
   }
   MV Wt = wslot(e.wB[side], t);
   int mr = 0;
+  wt_add(e, WT_W_STACK, tw);
   if (m > 0) {
-    wv_qr(m, Kt, A, nullptr);
+    wv_qr_traced(e, m, Kt, A);
     mr = m < Kt ? m : Kt;
     for (int q = lane; q < mr * Kt; q += 64) {
       const int i = q % mr, j = q / mr;
@@ -336,6 +404,7 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
     }
   }
   if (lane == 0) e.wB_m[side][t] = mr;
+  wt_add(e, WT_W_QR, tw);
   count_w(e, W, fl + fl_qr(mrows, Kt));
   wave_sync();
 }
@@ -346,9 +415,10 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
 // or -1 past the rank cap (one wave).
 __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int side, int c) {
   const int lane = lane_id();
+  unsigned long long tw = wt_now(e);
   const int root = u.r0[side];
   const int kc = e.k[side][c], K = kc + u.kp;
-  WvAlloc al = wv_alloc(W);
+  WvAlloc al = wv_alloc(e, W);
   int mr, r1 = 0;
   MV Vt;
   double fl = 0.0;
@@ -381,6 +451,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     }
   }
   wave_sync();
+  wt_add(e, WT_RC_BUILD, tw);
   const int mB = e.wB_m[side][c];
   int r = 0;
   bool trans = false;
@@ -389,6 +460,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     M = al.take(mr, mB);
     wv_gemm(mr, mB, K, 1.0, Vt, mv_t(wslot(e.wB[side], c)), 0.0, M);
     fl += fl_gemm(mr, mB, K);
+    wt_add(e, WT_RC_M, tw);
     trans = mB > mr;
     int sweeps, nG;
     if (!trans) {
@@ -406,6 +478,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
       nG = mr;
     }
     fl += fl_svd(mr, mB);
+    wt_add(e, WT_RC_SVD, tw);
     if (e.prof && lane == 0) {
       atomicAdd(&e.prof[PROF_STAGE + 12], (unsigned long long)sweeps);
       atomicAdd(&e.prof[PROF_STAGE + 13], 1ull);
@@ -450,6 +523,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
   }
   count_w(e, W, fl);
   wave_sync();
+  wt_add(e, WT_RC_OUT, tw);
   return r;
 }
 
@@ -457,9 +531,10 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
 // S_b <- R_t S~_b R_s^* (identity factor outside the subtrees).
 __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
   const int lane = lane_id();
+  unsigned long long tw = wt_now(e);
   const SExt St = sext(e, u, b);
   const int t = e.brow[b], s = e.bcol[b];
-  WvAlloc al = wv_alloc(W);
+  WvAlloc al = wv_alloc(e, W);
   const int rows = St.tin ? e.wnewk[0][t] : St.kt;
   MV P = al.take(rows, St.Ks);
   double fl = 0.0;
@@ -486,15 +561,18 @@ __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
   }
   count_w(e, W, fl);
   wave_sync();
+  wt_add(e, WT_CPL, tw);
 }
 
 // R-factor of a predecessor's basis after E_{t0} changed (one wave).
 __device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c) {
   const int lane = lane_id();
+  unsigned long long tw = wt_now(e);
+  wc_add(e, WC_REFRESH, 1);
   const int kc = e.k[side][c];
   const int c1 = e.son0[c], c2 = e.son1[c];
   const int m1 = e.rho_m[side][c1], m2 = e.rho_m[side][c2];
-  WvAlloc al = wv_alloc(W);
+  WvAlloc al = wv_alloc(e, W);
   MV A = al.take(m1 + m2, kc);
   wv_gemm(m1, kc, e.k[side][c1], 1.0, rhoslot(e, side, c1), Eslot(e, side, c1), 0.0, mv_at(A, 0, 0));
   wv_gemm(m2, kc, e.k[side][c2], 1.0, rhoslot(e, side, c2), Eslot(e, side, c2), 0.0, mv_at(A, m1, 0));
@@ -509,6 +587,7 @@ __device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c) {
   if (lane == 0) e.rho_m[side][c] = mr;
   count_w(e, W, fl_qr(m, kc) + fl_gemm(m1, kc, e.k[side][c1]) + fl_gemm(m2, kc, e.k[side][c2]));
   wave_sync();
+  wt_add(e, WT_REFRESH, tw);
 }
 
 __device__ __forceinline__ void prof_stage(const DevEnv &e, int stage, unsigned long long &t) {
@@ -532,6 +611,7 @@ __device__ __forceinline__ int ancestor(const DevEnv &e, int c, int lv) {
 
 __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, int bx, int by) {
   unsigned long long tstage = wall_clock64();
+  const unsigned long long tstart = tstage;
   Upd u;
   u.r0[0] = e.brow[b0];
   u.r0[1] = e.bcol[b0];
@@ -659,6 +739,11 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
   }
   __syncthreads();
   prof_stage(e, 7, tstage);
+  if (e.prof && threadIdx.x == 0) {
+    const int lv = lv0[0] < 15 ? lv0[0] : 15;
+    e.prof[PROF_LEVEL + lv] += wall_clock64() - tstart;
+    e.prof[PROF_LEVEL + 16 + lv] += 1;
+  }
 }
 
 // ====================================================== products with H^2

@@ -280,10 +280,18 @@ STAGES = ["zero-check", "rfactors", "path-weights", "subtree-weights", "recompre
           "nearfield", "commit"]
 
 
+# per-wave sub-steps of the low-rank update (seconds summed over waves) and counts
+WAVE_TICKS = ["rfactor build", "rfactor qr", "weight omega", "weight stack", "weight qr",
+              "recompress build", "recompress M", "recompress svd", "recompress out", "coupling",
+              "rho refresh"]
+WAVE_COUNTS = ["weight calls", "weight blocks", "weight nonempty", "qr calls", "qr cols", "qr rows",
+               "rho refresh"]
+
+
 def h2_profile(m: Mat, enable: bool = True):
     """Return the previous counters as a dict and (re)enable collection."""
-    buf = np.zeros(96, np.int64)
-    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 96))
+    buf = np.zeros(160, np.int64)
+    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 160))
     out = {}
     for i, name in enumerate(OPS):
         if name and buf[i]:
@@ -293,6 +301,9 @@ def h2_profile(m: Mat, enable: bool = True):
     out["jacobi"] = {"calls": int(buf[64 + 13]), "sweeps": int(buf[64 + 12]), "cols": int(buf[64 + 14])}
     out["bapply_classes"] = {c: (int(buf[88 + i]), buf[80 + i] * 1e-8) for i, c in
                              enumerate(["1", "2-3", "4-15", "16-63", "64-255", "256+"])}
+    out["wave_ticks"] = {name: buf[96 + i] * 1e-8 for i, name in enumerate(WAVE_TICKS)}
+    out["wave_counts"] = {name: int(buf[112 + i]) for i, name in enumerate(WAVE_COUNTS)}
+    out["update_levels"] = {lv: (int(buf[144 + lv]), buf[128 + lv] * 1e-8) for lv in range(16) if buf[144 + lv]}
     return out
 
 
