@@ -688,6 +688,87 @@ __device__ void wv_qr(int m, int n, MV A, double *tau) {
   wave_sync();
 }
 
+// Z <- H_j Z for the Householder reflector H_j = I - tau v v^* stored by
+// wv_qr in column j of A (v_j = 1, v_i = A(i, j) below), applied to the
+// columns 0..nz-1 of Z (m rows).  Same lane layout and clamping as
+// wv_qr_step.
+template <int LG, int RPL, bool ONE>
+__device__ __forceinline__ void wv_refl_apply(int m, int j, MV A, double tau, MV Z, int nz) {
+  constexpr int RG = 1 << LG, CG = 64 >> LG;
+  const int lane = lane_id();
+  const int g = lane >> LG, r = lane & (RG - 1);
+  for (int c = g; c < nz; c += CG) {
+    const double zjc = Z(j, c);
+    double p = 0.0;
+    if (ONE) {
+      const int i0 = j + 1 + r < m ? j + 1 + r : j + 1;
+      double v[RPL], z[RPL];
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int i = j + 1 + r + k * RG, ic = i < m ? i : i0;
+        v[k] = A(ic, j);
+        z[k] = Z(ic, c);
+      }
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) p = fma(j + 1 + r + k * RG < m ? v[k] : 0.0, z[k], p);
+      p = group_sum_t<RG>(p);
+      const double w = tau * (zjc + p);
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int i = j + 1 + r + k * RG, ic = i < m ? i : i0;
+        Z(ic, c) = fma(-w, v[k], z[k]);
+      }
+      if (r == 0) Z(j, c) = zjc - w;
+    } else {
+      for (int i0 = j + 1 + r; i0 < m; i0 += RG * RPL) {
+        double v[RPL], z[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = i0 + k * RG, ic = i < m ? i : i0;
+          v[k] = A(ic, j);
+          z[k] = Z(ic, c);
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) p = fma(i0 + k * RG < m ? v[k] : 0.0, z[k], p);
+      }
+      p = group_sum_t<RG>(p);
+      const double w = tau * (zjc + p);
+      for (int i0 = j + 1 + r; i0 < m; i0 += RG * RPL) {
+        double v[RPL], z[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = i0 + k * RG, ic = i < m ? i : i0;
+          v[k] = A(ic, j);
+          z[k] = Z(ic, c);
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = i0 + k * RG, ic = i < m ? i : i0;
+          Z(ic, c) = fma(-w, v[k], z[k]);
+        }
+      }
+      if (r == 0) Z(j, c) = zjc - w;
+    }
+  }
+}
+
+// Z <- Q Z with Q = H_0 H_1 ... H_{n-1} from wv_qr(m, n, A, tau) (m rows,
+// nz columns of Z), one wave.
+__device__ void wv_apply_q(int m, int n, MV A, const double *tau, MV Z, int nz) {
+  const int kmax = m < n ? m : n;
+  for (int j = kmax - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t != 0.0 && nz > 0) {
+      const int mt = m - j - 1;
+      if (mt <= 8) wv_refl_apply<2, 2, true>(m, j, A, t, Z, nz);
+      else if (mt <= 16) wv_refl_apply<2, 4, true>(m, j, A, t, Z, nz);
+      else if (mt <= 32) wv_refl_apply<2, 8, true>(m, j, A, t, Z, nz);
+      else wv_refl_apply<2, 8, false>(m, j, A, t, Z, nz);
+    }
+    wave_sync();
+  }
+}
+
 // Column norms of G (m x n) into sig, groups of 2^LG lanes per column.
 template <int LG>
 __device__ __forceinline__ void wv_colnorms(int m, int n, MV G, double *sig) {

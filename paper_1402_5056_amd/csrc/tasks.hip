@@ -107,6 +107,7 @@ constexpr int NWAVE = NT / 64;
 constexpr int WREG = 4864;      // doubles of LDS per wave for work matrices
 constexpr int WSMALL = 256;     // doubles of LDS per wave for vectors
 constexpr int WGLOB = 16384;    // doubles of global scratch per wave (overflow)
+constexpr int PRECOND_MIN = 10; // SVDs with more columns are QR-preconditioned
 constexpr size_t LDS_WAVE_DOUBLES = (size_t)NWAVE * (WREG + WSMALL);
 constexpr size_t LDS_TOTAL_DOUBLES = LDS_WAVE_DOUBLES > LDS_DOUBLES ? LDS_WAVE_DOUBLES : LDS_DOUBLES;
 
@@ -274,10 +275,23 @@ __device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side,
 // block b the stacked rows are G_b = rho_o S~_b^* (row side, rho_o the column
 // R-factor of s) or rho_o S~_b (column side, rho_o the row R-factor of t);
 // the block-relative scale is 1 / ||rho_t S~_b rho_s^*||_F = 1 / ||G_b rho^*||_F
-// with rho the R-factor of the cluster itself.  The operands of a block are
-// staged in LDS first; blocks whose extended coupling is identically zero
-// add nothing to the R-factor and are skipped.
-__device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, int t, bool insub) {
+// with rho the R-factor of the cluster itself.  The last rows are
+// B~_parent diag(E_t, I)^*.  Since only the Gram matrix of the stack matters
+// (the R-factor is determined up to a left orthogonal factor, which changes
+// neither the left singular vectors of V^_t B~_t^* nor the stacks of the
+// sons), the work can be split:
+//   W_FULL   block rows and parent rows;
+//   W_ROWS   block rows only (R-factor stored in the weight slot of t);
+//   W_CHAIN  the stored R-factor of the block rows and the parent rows.
+// The metadata of all blocks of the row is read lane-parallel; blocks whose
+// extended coupling is identically zero add nothing and are skipped; the
+// operands of a used block are staged in LDS before its rows are formed.
+enum : int { W_FULL = 0, W_ROWS = 1, W_CHAIN = 2 };
+
+__device__ __forceinline__ int rd_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, int t, bool insub,
+                          int wmode) {
   const int lane = lane_id();
   unsigned long long tw = wt_now(e);
   wc_add(e, WC_W_CALLS, 1);
@@ -285,90 +299,115 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
   const int Kt = kt + (insub ? u.kp : 0);
   const int cap = Kt + KM;          // any single block fits after a compression
   WvAlloc al = wv_alloc(e, W);
-  int mown = 0;
-  MV Rown{nullptr, 0, 0};
-  if (e.mode == 0) {
-    MV Rg = rho_of(e, u, side, t, mown);
-    Rown = al.take(mown, Kt);
-    for (int q = lane; q < mown * Kt; q += 64) Rown(q % mown, q / mown) = Rg(q % mown, q / mown);
-  }
   MV A = al.take(cap, Kt);
-  const WvAlloc blk0 = al;          // per-block staging starts here
   int m = 0, mrows = 0;
   double fl = 0.0;
-  const int *ptr = side == 0 ? e.rowptr : e.colptr;
-  const int *idx = side == 0 ? e.rowidx : e.colidx;
-  for (int p = ptr[t]; p < ptr[t + 1]; ++p) {
-    const int b = idx[p];
-    wc_add(e, WC_W_BLOCKS, 1);
-    const int bt = e.brow[b], bs = e.bcol[b];
-    const int kbt = e.k[0][bt], kbs = e.k[1][bs];
-    const bool tin = in_sub(e, u.r0[0], bt), sin = in_sub(e, u.r0[1], bs);
-    const bool ext = tin && sin && u.kp > 0;
-    if (!((kbt > 0 && kbs > 0) || ext)) continue;     // S~_b = 0
-    if (e.mode == 0 && mown == 0) continue;           // scale 1/0: block dropped
-    int mo;
-    MV Rog = rho_of(e, u, 1 - side, side == 0 ? bs : bt, mo);
-    if (mo == 0) continue;
-    const int Kbt = kbt + (tin ? u.kp : 0), Kbs = kbs + (sin ? u.kp : 0);
-    const int Ko = side == 0 ? Kbs : Kbt;
-    // stage T = S~_b (row side) or S~_b^* (column side), Kt x Ko, and rho_o
-    WvAlloc sa = blk0;
-    MV T = sa.take(Kt, Ko), Ro = sa.take(mo, Ko);
-    const MV S = Sslot(e, b);
-    for (int q = lane; q < Kt * Ko; q += 64) {
-      const int j = q % Kt, l = q / Kt;
-      const int i0 = side == 0 ? j : l, j0 = side == 0 ? l : j;   // entry (i0, j0) of S~_b
-      double v;
-      if (i0 < kbt && j0 < kbs) v = S(i0, j0);
-      else v = (ext && i0 >= kbt && j0 >= kbs && i0 - kbt == j0 - kbs) ? 1.0 : 0.0;
-      T(j, l) = v;
-    }
-    for (int q = lane; q < mo * Ko; q += 64) Ro(q % mo, q / mo) = Rog(q % mo, q / mo);
-    if (m + mo > cap) {
-      wt_add(e, WT_W_STACK, tw);
-      wv_qr_traced(e, m, Kt, A);    // ends with wave_sync (also for the staging)
-      const int mc = m < Kt ? m : Kt;
-      for (int q = lane; q < mc * mc; q += 64) { const int i = q % mc, j = q / mc; if (i > j) A(i, j) = 0.0; }
-      m = mc;
-      wt_add(e, WT_W_QR, tw);
-    }
+  MV Wt = wslot(e.wB[side], t);
+  if (wmode == W_CHAIN) {
+    m = e.wB_m[side][t];
+    for (int q = lane; q < m * Kt; q += 64) A(q % m, q / m) = Wt(q % m, q / m);
     wave_sync();
-    wc_add(e, WC_W_NONEMPTY, 1);
-    // G_b = rho_o T^* into rows m .. m+mo of the stack
-    for (int q = lane; q < mo * Kt; q += 64) {
-      const int i = q % mo, j = q / mo;
-      double acc = 0.0;
-      for (int l = 0; l < Ko; ++l) acc = fma(Ro(i, l), T(j, l), acc);
-      A(m + i, j) = acc;
-    }
-    wave_sync();
-    fl += fl_gemm(mo, Kt, Ko);
+  } else {
+    int mown = 0;
+    MV Rown{nullptr, 0, 0};
     if (e.mode == 0) {
-      double f2 = 0.0;
-      for (int q = lane; q < mo * mown; q += 64) {
-        const int i = q % mo, a = q / mo;
-        double acc = 0.0;
-        for (int j = 0; j < Kt; ++j) acc = fma(A(m + i, j), Rown(a, j), acc);
-        f2 = fma(acc, acc, f2);
-      }
-      f2 = wave_sum64(f2);
-      fl += fl_gemm(mo, mown, Kt);
-      if (f2 == 0.0) { wt_add(e, WT_W_OMEGA, tw); continue; }
-      const double wsc = 1.0 / sqrt(f2);
-      for (int q = lane; q < mo * Kt; q += 64) A(m + q % mo, q / mo) *= wsc;
-      wave_sync();
+      MV Rg = rho_of(e, u, side, t, mown);
+      Rown = al.take(mown, Kt);
+      for (int q = lane; q < mown * Kt; q += 64) Rown(q % mown, q / mown) = Rg(q % mown, q / mown);
     }
-    wt_add(e, WT_W_OMEGA, tw);
-    m += mo;
-    mrows += mo;
+    const WvAlloc blk0 = al;        // per-block staging starts here
+    const int *ptr = side == 0 ? e.rowptr : e.colptr;
+    const int *idx = side == 0 ? e.rowidx : e.colidx;
+    const int p0 = ptr[t], nb = ptr[t + 1] - p0;
+    for (int base = 0; base < nb; base += 64) {
+      // lane-parallel metadata of up to 64 blocks
+      int b = 0, mo = 0, kbt = 0, kbs = 0, fx = 0;
+      bool use = false;
+      if (base + lane < nb) {
+        b = idx[p0 + base + lane];
+        const int bt = e.brow[b], bs = e.bcol[b];
+        kbt = e.k[0][bt];
+        kbs = e.k[1][bs];
+        const bool tin = in_sub(e, u.r0[0], bt), sin = in_sub(e, u.r0[1], bs);
+        const bool ext = tin && sin && u.kp > 0;
+        fx = (tin ? 1 : 0) | (sin ? 2 : 0) | (ext ? 4 : 0);
+        use = ((kbt > 0 && kbs > 0) || ext) && !(e.mode == 0 && mown == 0);
+        if (use) {
+          const int other = side == 0 ? bs : bt;
+          mo = in_sub(e, u.r0[1 - side], other) ? e.wrho_m[1 - side][other] : e.rho_m[1 - side][other];
+          use = mo > 0;
+        }
+      }
+      wc_add(e, WC_W_BLOCKS, nb - base < 64 ? nb - base : 64);
+      unsigned long long mask = __ballot(use);
+      while (mask != 0ull) {
+        const int l = __ffsll((long long)mask) - 1;
+        mask &= mask - 1ull;
+        const int bb = rd_lane(b, l), mob = rd_lane(mo, l), kt_b = rd_lane(kbt, l), ks_b = rd_lane(kbs, l);
+        const int f = rd_lane(fx, l);
+        const bool tin = f & 1, sin = f & 2, ext = f & 4;
+        const int other = side == 0 ? e.bcol[bb] : e.brow[bb];
+        int mo2;
+        MV Rog = rho_of(e, u, 1 - side, other, mo2);
+        const int Kbt = kt_b + (tin ? u.kp : 0), Kbs = ks_b + (sin ? u.kp : 0);
+        const int Ko = side == 0 ? Kbs : Kbt;
+        // stage T = S~_b (row side) or S~_b^* (column side), Kt x Ko, and rho_o
+        WvAlloc sa = blk0;
+        MV T = sa.take(Kt, Ko), Ro = sa.take(mob, Ko);
+        const MV S = Sslot(e, bb);
+        for (int q = lane; q < Kt * Ko; q += 64) {
+          const int j = q % Kt, c = q / Kt;
+          const int i0 = side == 0 ? j : c, j0 = side == 0 ? c : j;   // entry (i0, j0) of S~_b
+          double v;
+          if (i0 < kt_b && j0 < ks_b) v = S(i0, j0);
+          else v = (ext && i0 >= kt_b && j0 >= ks_b && i0 - kt_b == j0 - ks_b) ? 1.0 : 0.0;
+          T(j, c) = v;
+        }
+        for (int q = lane; q < mob * Ko; q += 64) Ro(q % mob, q / mob) = Rog(q % mob, q / mob);
+        if (m + mob > cap) {
+          wt_add(e, WT_W_STACK, tw);
+          wv_qr_traced(e, m, Kt, A);    // ends with wave_sync (also for the staging)
+          const int mc = m < Kt ? m : Kt;
+          for (int q = lane; q < mc * mc; q += 64) { const int i = q % mc, j = q / mc; if (i > j) A(i, j) = 0.0; }
+          m = mc;
+          wt_add(e, WT_W_QR, tw);
+        }
+        wave_sync();
+        wc_add(e, WC_W_NONEMPTY, 1);
+        // G_b = rho_o T^* into rows m .. m+mo of the stack
+        for (int q = lane; q < mob * Kt; q += 64) {
+          const int i = q % mob, j = q / mob;
+          double acc = 0.0;
+          for (int c = 0; c < Ko; ++c) acc = fma(Ro(i, c), T(j, c), acc);
+          A(m + i, j) = acc;
+        }
+        wave_sync();
+        fl += fl_gemm(mob, Kt, Ko);
+        if (e.mode == 0) {
+          double f2 = 0.0;
+          for (int q = lane; q < mob * mown; q += 64) {
+            const int i = q % mob, a = q / mob;
+            double acc = 0.0;
+            for (int j = 0; j < Kt; ++j) acc = fma(A(m + i, j), Rown(a, j), acc);
+            f2 = fma(acc, acc, f2);
+          }
+          f2 = wave_sum64(f2);
+          fl += fl_gemm(mob, mown, Kt);
+          if (f2 == 0.0) { wt_add(e, WT_W_OMEGA, tw); continue; }
+          const double wsc = 1.0 / sqrt(f2);
+          for (int q = lane; q < mob * Kt; q += 64) A(m + q % mob, q / mob) *= wsc;
+          wave_sync();
+        }
+        wt_add(e, WT_W_OMEGA, tw);
+        m += mob;
+        mrows += mob;
+      }
+    }
   }
   const int par = e.parent[t];
-  if (par >= 0) {
-    const bool pin = in_sub(e, u.r0[side], par);
+  if (wmode != W_ROWS && par >= 0) {
     const int kpar = e.k[side][par];
     const int mp = e.wB_m[side][par];
-    (void)pin;
     if (mp > 0) {
       if (m + mp > cap) {
         wv_qr_traced(e, m, Kt, A);
@@ -392,7 +431,6 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
       mrows += mp;
     }
   }
-  MV Wt = wslot(e.wB[side], t);
   int mr = 0;
   wt_add(e, WT_W_STACK, tw);
   if (m > 0) {
@@ -455,7 +493,9 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
   const int mB = e.wB_m[side][c];
   int r = 0;
   bool trans = false;
-  MV M{nullptr, 0, 0}, J{nullptr, 0, 0};
+  MV M{nullptr, 0, 0}, J{nullptr, 0, 0}, Y{nullptr, 0, 0};
+  double *qtau = nullptr;
+  int qsrc = 0;   // 0: columns of M (or of J), 1: columns of Y, 2: Q times columns of Y^*
   if (mr > 0 && mB > 0) {
     M = al.take(mr, mB);
     wv_gemm(mr, mB, K, 1.0, Vt, mv_t(wslot(e.wB[side], c)), 0.0, M);
@@ -463,7 +503,43 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     wt_add(e, WT_RC_M, tw);
     trans = mB > mr;
     int sweeps, nG;
-    if (!trans) {
+    const unsigned long long tj = wt_now(e);
+    if (!trans && mB > PRECOND_MIN) {
+      // Two-stage QR preconditioning: M = Q R, R^* = Q2 R2; the left singular
+      // vectors of R2^* (its Jacobi-rotated columns, normalised) times Q are
+      // those of M, and the sweeps needed on R2^* are few.
+      qtau = al.take(mB, 1).p;
+      wv_qr(mr, mB, M, qtau);
+      Y = al.take(mB, mB);
+      for (int q = lane; q < mB * mB; q += 64) {
+        const int i = q % mB, j = q / mB;
+        Y(i, j) = i >= j ? M(j, i) : 0.0;
+      }
+      wave_sync();
+      wv_qr(mB, mB, Y, nullptr);
+      for (int q = lane; q < mB * mB; q += 64) { const int i = q % mB, j = q / mB; if (i > j) Y(i, j) = 0.0; }
+      wave_sync();
+      sweeps = wave_jacobi(mB, mB, mv_t(Y), nullptr);
+      wv_colnorms_sorted(mB, mB, mv_t(Y), W.sig, W.ord);
+      nG = mB;
+      qsrc = 2;
+      fl += 2.0 * fl_qr(mr, mB) + fl_qr(mB, mB);
+    } else if (trans && mr > PRECOND_MIN) {
+      // M^* = Q1 R1: the left singular vectors of M are those of R1^*
+      const MV Mt = mv_t(M);
+      wv_qr(mB, mr, Mt, nullptr);
+      Y = al.take(mr, mr);
+      for (int q = lane; q < mr * mr; q += 64) {
+        const int i = q % mr, j = q / mr;
+        Y(i, j) = i >= j ? Mt(j, i) : 0.0;
+      }
+      wave_sync();
+      sweeps = wave_jacobi(mr, mr, Y, nullptr);
+      wv_colnorms_sorted(mr, mr, Y, W.sig, W.ord);
+      nG = mr;
+      qsrc = 1;
+      fl += fl_qr(mB, mr);
+    } else if (!trans) {
       sweeps = wave_jacobi(mr, mB, M, nullptr);
       wv_colnorms_sorted(mr, mB, M, W.sig, W.ord);
       nG = mB;
@@ -480,6 +556,9 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     fl += fl_svd(mr, mB);
     wt_add(e, WT_RC_SVD, tw);
     if (e.prof && lane == 0) {
+      const int cls = nG <= 8 ? 0 : nG <= 16 ? 1 : nG <= 32 ? 2 : 3;
+      atomicAdd(&e.prof[PROF_LEAFSTAGE + 8 + cls], wall_clock64() - tj);
+      atomicAdd(&e.prof[PROF_LEAFSTAGE + 12 + cls], 1ull);
       atomicAdd(&e.prof[PROF_STAGE + 12], (unsigned long long)sweeps);
       atomicAdd(&e.prof[PROF_STAGE + 13], 1ull);
       atomicAdd(&e.prof[PROF_STAGE + 14], (unsigned long long)nG);
@@ -496,9 +575,17 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
   for (int q = lane; q < mr * r; q += 64) {
     const int i = q % mr, j = q / mr;
     const int cc = W.ord[j];
-    Q(i, j) = trans ? J(i, cc) : M(i, cc) / W.sig[cc];
+    double v;
+    if (qsrc == 2) v = i < mB ? Y(cc, i) / W.sig[cc] : 0.0;   // columns of R2^*, padded
+    else if (qsrc == 1) v = Y(i, cc) / W.sig[cc];
+    else v = trans ? J(i, cc) : M(i, cc) / W.sig[cc];
+    Q(i, j) = v;
   }
   wave_sync();
+  if (qsrc == 2) {
+    wv_apply_q(mr, mB, M, qtau, Q, r);
+    fl += fl_gemm(mr, r, mB);
+  }
   wv_gemm(r, K, mr, 1.0, mv_t(Q), Vt, 0.0, wslot(e.wR[side], c));   // R_c = Q^* V~_c
   fl += fl_gemm(r, K, mr);
   if (lane == 0) e.wnewk[side][c] = r;
@@ -590,10 +677,12 @@ __device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c) {
   wt_add(e, WT_REFRESH, tw);
 }
 
-__device__ __forceinline__ void prof_stage(const DevEnv &e, int stage, unsigned long long &t) {
+__device__ __forceinline__ void prof_stage(const DevEnv &e, int stage, unsigned long long &t,
+                                           bool leaf = false) {
   if (e.prof && threadIdx.x == 0) {
     const unsigned long long now = wall_clock64();
     e.prof[PROF_STAGE + stage] += now - t;
+    if (leaf) e.prof[PROF_LEAFSTAGE + stage] += now - t;
     t = now;
   }
 }
@@ -637,6 +726,15 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
   const Wv W = wave_areas(lds, e);
   const int lv0[2] = {e.level[u.r0[0]], e.level[u.r0[1]]};
   const int lvmin = lv0[0] < lv0[1] ? lv0[0] : lv0[1];
+  const bool leafupd = is_leaf(e, u.r0[0]);
+  // --- steps 2/3, first part: block rows of the weights of the predecessors
+  // above both subtrees.  They read only data outside the subtrees, so they
+  // run concurrently with each other and with step 1.
+  const int npath = lvmin;
+  for (int q = W.w; q < 2 * npath; q += NWAVE) {
+    const int side = q < npath ? 0 : 1, lv = q < npath ? q : q - npath;
+    wv_weight(e, u, W, side, ancestor(e, u.r0[side], lv), false, W_ROWS);
+  }
   // --- step 1: R-factors of the extended bases, bottom-up, clusters of a level concurrently
   for (int lv = e.nlev - 1; lv >= lvmin; --lv) {
     const int n0 = nlevel(e, u.r0[0], lv), n1 = nlevel(e, u.r0[1], lv);
@@ -647,20 +745,26 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
     }
     __syncthreads();
   }
-  prof_stage(e, 1, tstage);
-  // --- steps 2/3: weights top-down; above t0 / s0 the predecessors, then the subtrees
-  for (int lv = 0; lv < e.nlev; ++lv) {
+  prof_stage(e, 1, tstage, leafupd);
+  // --- steps 2/3, second part: the chain root -> parent(t0) adds the parent
+  // rows (one wave per side), then the remaining levels top-down
+  if (W.w < 2) {
+    const int side = W.w;
+    for (int lv = 1; lv < npath; ++lv) wv_weight(e, u, W, side, ancestor(e, u.r0[side], lv), false, W_CHAIN);
+  }
+  __syncthreads();
+  for (int lv = npath; lv < e.nlev; ++lv) {
     int cnt[2];
     for (int side = 0; side < 2; ++side) cnt[side] = lv < lv0[side] ? 1 : nlevel(e, u.r0[side], lv);
     for (int q = W.w; q < cnt[0] + cnt[1]; q += NWAVE) {
       const int side = q < cnt[0] ? 0 : 1;
       const int qq = side == 0 ? q : q - cnt[0];
-      if (lv < lv0[side]) wv_weight(e, u, W, side, ancestor(e, u.r0[side], lv), false);
-      else wv_weight(e, u, W, side, dlo(e, u.r0[side], lv) + qq, true);
+      if (lv < lv0[side]) wv_weight(e, u, W, side, ancestor(e, u.r0[side], lv), false, W_FULL);
+      else wv_weight(e, u, W, side, dlo(e, u.r0[side], lv) + qq, true, W_FULL);
     }
     __syncthreads();
   }
-  prof_stage(e, 3, tstage);
+  prof_stage(e, 3, tstage, leafupd);
   // --- step 4: nested recompression, bottom-up
   for (int lv = e.nlev - 1; lv >= lvmin; --lv) {
     const int n0 = nlevel(e, u.r0[0], lv), n1 = nlevel(e, u.r0[1], lv);
@@ -672,7 +776,7 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
     __syncthreads();
     if (e.err[0] != 0) return;
   }
-  prof_stage(e, 4, tstage);
+  prof_stage(e, 4, tstage, leafupd);
   // --- step 5: couplings of every admissible leaf touching the subtrees
   {
     int q = 0;
@@ -694,7 +798,7 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
     }
     __syncthreads();
   }
-  prof_stage(e, 5, tstage);
+  prof_stage(e, 5, tstage, leafupd);
   // --- step 7: inadmissible leaves inside b0 receive X|_t Y|_s^*
   {
     int q = 0;
@@ -718,7 +822,7 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
     }
     __syncthreads();
   }
-  prof_stage(e, 6, tstage);
+  prof_stage(e, 6, tstage, leafupd);
   // --- step 6: commit ranks, identity R-factors of the new bases, refresh the paths
   for (int side = 0; side < 2; ++side) {
     const int root = u.r0[side];
@@ -738,7 +842,7 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
     for (int c = e.parent[u.r0[side]]; c >= 0; c = e.parent[c]) wv_refresh_rho(e, W, side, c);
   }
   __syncthreads();
-  prof_stage(e, 7, tstage);
+  prof_stage(e, 7, tstage, leafupd);
   if (e.prof && threadIdx.x == 0) {
     const int lv = lv0[0] < 15 ? lv0[0] : 15;
     e.prof[PROF_LEVEL + lv] += wall_clock64() - tstart;

@@ -290,8 +290,8 @@ WAVE_COUNTS = ["weight calls", "weight blocks", "weight nonempty", "qr calls", "
 
 def h2_profile(m: Mat, enable: bool = True):
     """Return the previous counters as a dict and (re)enable collection."""
-    buf = np.zeros(160, np.int64)
-    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 160))
+    buf = np.zeros(176, np.int64)
+    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 176))
     out = {}
     for i, name in enumerate(OPS):
         if name and buf[i]:
@@ -304,6 +304,9 @@ def h2_profile(m: Mat, enable: bool = True):
     out["wave_ticks"] = {name: buf[96 + i] * 1e-8 for i, name in enumerate(WAVE_TICKS)}
     out["wave_counts"] = {name: int(buf[112 + i]) for i, name in enumerate(WAVE_COUNTS)}
     out["update_levels"] = {lv: (int(buf[144 + lv]), buf[128 + lv] * 1e-8) for lv in range(16) if buf[144 + lv]}
+    out["leaf_stages"] = {name: buf[160 + i] * 1e-8 for i, name in enumerate(STAGES)}
+    out["svd_classes"] = {c: (int(buf[172 + i]), buf[168 + i] * 1e-8) for i, c in
+                          enumerate(["<=8", "<=16", "<=32", ">32"])}
     return out
 
 
