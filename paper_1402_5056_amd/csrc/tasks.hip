@@ -1277,10 +1277,12 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
   extern __shared__ double lds_raw[];
   const DevEnv &e = *env;
   const Lds L = lds_layout(lds_raw);
+  if (e.err[0] != 0) return;
+  Task nxt = ntask > 0 ? tasks[0] : Task{};
   for (int it = 0; it < ntask; ++it) {
     __syncthreads();
-    if (e.err[0] != 0) return;
-    const Task tk = tasks[it];
+    const Task tk = nxt;
+    if (it + 1 < ntask) nxt = tasks[it + 1];   // fetched while this task runs
     const unsigned long long t0 = e.prof ? wall_clock64() : 0ull;
     switch (tk.op) {
       case OP_ADDLR: task_addlr(e, L, lds_raw, tk.i[0], tk.i[1], tk.i[2]); break;
@@ -1314,6 +1316,11 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
     if (e.prof && threadIdx.x == 0 && tk.op > 0 && tk.op < 32) {
       e.prof[PROF_COUNT + tk.op] += 1;
       e.prof[PROF_TICKS + tk.op] += wall_clock64() - t0;
+    }
+    // only these kinds can record an error (set_error ends with a barrier)
+    if (tk.op == OP_ADDLR || tk.op == OP_POTRF || tk.op == OP_TEMP_ADD || tk.op <= 0 || tk.op >= 32) {
+      __syncthreads();
+      if (e.err[0] != 0) return;
     }
   }
 }
