@@ -232,6 +232,7 @@ struct h2_csr_s {
 
 struct TaskList {
   Dev<Task> d;
+  Dev<int> aux;      // block lists referenced by tasks (offsets in the tasks)
   int count = 0;
   bool built = false;
 };
@@ -368,6 +369,7 @@ struct Planner {
   const h2_ctree_s &ct;
   const h2_btree_s &bt;
   std::vector<Task> &T;
+  std::vector<int> aux;
   Planner(const h2_mat_s &m, std::vector<Task> &t) : M(m), ct(*m.bt->ct), bt(*m.bt), T(t) {}
 
   void emit(int op, int a = 0, int b = 0, int c = 0, int d = 0, int e_ = 0, int f = 0, int g = 0,
@@ -395,6 +397,56 @@ struct Planner {
     emit(OP_BAPPLY, b, trans, bin, bout, 0, 0, 0, 0, alpha, beta);
   }
   void addlr(int b, int bu, int bv) { emit(OP_ADDLR, b, bu, bv); }
+
+  // H^2 substitution: one pass over the clusters and blocks of the subtree
+  // (forward transformations of solved clusters reused, coupling sums pushed
+  // down the unsolved part).
+  void leaves_of(int b, std::vector<int> &out) const {
+    if (bt.kind[b] != 0) { out.push_back(b); return; }
+    const int t = bt.row[b], s = bt.col[b];
+    for (int t2 : sons_plus(t))
+      for (int s2 : sons_plus(s)) leaves_of(find(t2, s2), out);
+  }
+  // Leaves of block (c2, c1) grouped by the cluster they update (row cluster
+  // for trans = 0, column cluster for trans = 1): aux holds the group start
+  // offsets, then per group {cluster, count, blocks...}.  Returns the offset
+  // of the start table; ng receives the number of groups.
+  int cross_groups(int c2, int c1, int trans, int &ng) {
+    std::vector<int> lv;
+    leaves_of(find(c2, c1), lv);
+    std::vector<int> tgt;
+    std::vector<std::vector<int>> grp;
+    std::unordered_map<int, int> where;
+    for (int b : lv) {
+      const int t = trans ? bt.col[b] : bt.row[b];
+      auto it = where.find(t);
+      if (it == where.end()) { where[t] = (int)tgt.size(); tgt.push_back(t); grp.emplace_back(); it = where.find(t); }
+      grp[it->second].push_back(b);
+    }
+    ng = (int)tgt.size();
+    const int off = (int)aux.size();
+    aux.resize(aux.size() + ng);
+    for (int g = 0; g < ng; ++g) {
+      aux[off + g] = (int)aux.size();
+      aux.push_back(tgt[g]);
+      aux.push_back((int)grp[g].size());
+      for (int b : grp[g]) aux.push_back(b);
+    }
+    return off;
+  }
+  void sv_rec(int c, int buf, int trans, bool top) {
+    if (leaf(c)) { emit(OP_SV_LEAF, find(c, c), buf, trans); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    if (!top) emit(OP_SV_PUSH, c, buf, trans);
+    sv_rec(trans ? c2 : c1, buf, trans, false);
+    int ng;
+    const int off = cross_groups(c2, c1, trans, ng);
+    emit(OP_SV_CROSS, off, ng, buf, trans);
+    sv_rec(trans ? c1 : c2, buf, trans, false);
+    if (!top) emit(OP_SV_UP, c, buf, trans);
+  }
+  void fsolve_h2(int c, int buf) { emit(OP_SV_ZERO, c, buf, 0); sv_rec(c, buf, 0, true); }
+  void bsolve_h2(int c, int buf) { emit(OP_SV_ZERO, c, buf, 1); sv_rec(c, buf, 1, true); }
 
   void fsolve(int c, int buf) {
     if (leaf(c)) { emit(OP_TRSV, find(c, c), buf, 0); return; }
@@ -517,10 +569,15 @@ struct Planner {
   }
 };
 
-static void upload_tasks(h2_mat_s &m, TaskList &tl, const std::vector<Task> &tasks) {
+static void upload_tasks(h2_mat_s &m, TaskList &tl, const std::vector<Task> &tasks,
+                         const std::vector<int> &aux) {
+  (void)m;
   tl.d.alloc(tasks.size());
   if (!tasks.empty())
     HIPCHK(hipMemcpy(tl.d.p, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
+  tl.aux.alloc(aux.size());
+  if (!aux.empty())
+    HIPCHK(hipMemcpy(tl.aux.p, aux.data(), aux.size() * sizeof(int), hipMemcpyHostToDevice));
   tl.count = (int)tasks.size();
   tl.built = true;
 }
@@ -546,7 +603,9 @@ static void sync_env(h2_mat_s &m) {
   }
 }
 
-static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
+static void run_tasks(h2_mat_s &m, const TaskList &tl) {
+  const Task *d_tasks = tl.d.p;
+  const int count = tl.count;
   const size_t lds = LDS_TOTAL_DOUBLES * sizeof(double);
   sync_env(m);
   if (!g_lds_attr_set) {
@@ -557,7 +616,7 @@ static void run_tasks(h2_mat_s &m, const Task *d_tasks, int count) {
   for (int off = 0; off < count; off += seg) {
     const int cnt = std::min(seg, count - off);
     hipLaunchKernelGGL(k_interp, dim3(1), dim3(NT), lds, m.ctx->stream, d_tasks + off, cnt,
-                       (const DevEnv *)m.d_env.p);
+                       (const DevEnv *)m.d_env.p, (const int *)tl.aux.p);
     HIPCHK(hipGetLastError());
   }
 }
@@ -892,10 +951,11 @@ h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X,
                        (int)B_Y);
     HIPCHK(hipGetLastError());
     std::vector<Task> tasks;
-    Planner(*z, tasks).addlr((int)block, B_X, B_Y);
+    Planner P(*z, tasks);
+    P.addlr((int)block, B_X, B_Y);
     TaskList tl;
-    upload_tasks(*z, tl, tasks);
-    run_tasks(*z, tl.d.p, tl.count);
+    upload_tasks(*z, tl, tasks, P.aux);
+    run_tasks(*z, tl);
     check_device_error(*z);
   });
 }
@@ -913,10 +973,11 @@ h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, doub
                        (long)ct.n, z->env.buf[B_X], z->d_bcols.p, (int)B_X);
     HIPCHK(hipGetLastError());
     std::vector<Task> tasks;
-    Planner(*z, tasks).bapply(0, trans ? 1 : 0, B_X, B_Y, 1.0, 0.0);
+    Planner P(*z, tasks);
+    P.bapply(0, trans ? 1 : 0, B_X, B_Y, 1.0, 0.0);
     TaskList tl;
-    upload_tasks(*z, tl, tasks);
-    run_tasks(*z, tl.d.p, tl.count);
+    upload_tasks(*z, tl, tasks, P.aux);
+    run_tasks(*z, tl);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
                        z->env.buf[B_Y], y, (long)ct.n, alpha, beta);
     HIPCHK(hipGetLastError());
@@ -931,10 +992,11 @@ h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
     set_trunc(*a, tr);
     if (!a->chol.built) {
       std::vector<Task> tasks;
-      Planner(*a, tasks).chol(0);
-      upload_tasks(*a, a->chol, tasks);
+      Planner P(*a, tasks);
+      P.chol(0);
+      upload_tasks(*a, a->chol, tasks, P.aux);
     }
-    run_tasks(*a, a->chol.d.p, a->chol.count);
+    run_tasks(*a, a->chol);
     check_device_error(*a);
   });
 }
@@ -945,15 +1007,15 @@ static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
   if (!l->prec.built) {
     std::vector<Task> tasks;
     Planner P(*l, tasks);
-    P.fsolve(0, B_X);
-    P.bsolve(0, B_X);
-    upload_tasks(*l, l->prec, tasks);
+    P.fsolve_h2(0, B_X);
+    P.bsolve_h2(0, B_X);
+    upload_tasks(*l, l->prec, tasks, P.aux);
   }
   const long work = (long)ct.n * nrhs;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, 0, nrhs, ct.d_perm.p, r,
                      (long)ct.n, l->env.buf[B_X], l->d_bcols.p, (int)B_X);
   HIPCHK(hipGetLastError());
-  run_tasks(*l, l->prec.d.p, l->prec.count);
+  run_tasks(*l, l->prec);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
                      l->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
   HIPCHK(hipGetLastError());

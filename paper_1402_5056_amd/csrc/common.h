@@ -37,6 +37,11 @@ enum Op : int {
   OP_TRSV,           // i0 leaf cluster, i1 buf, i2 trans
   OP_SUB,            // i0 A, i1 B, i2 out, i3 cluster
   OP_COPY,           // i0 A, i1 out, i2 cluster
+  OP_SV_ZERO,        // i0 cluster, i1 buf, i2 trans   substitution: clear the coupling sums of the subtree
+  OP_SV_PUSH,        // i0 cluster, i1 buf, i2 trans   substitution: coupling sums to the sons
+  OP_SV_LEAF,        // i0 diagonal leaf block, i1 buf, i2 trans
+  OP_SV_CROSS,       // i0 aux offset, i1 groups, i2 buf, i3 trans  leaves of (c2, c1), solved -> unsolved part
+  OP_SV_UP,          // i0 cluster, i1 buf, i2 trans   forward transformation of a solved cluster
 };
 
 struct Task {

@@ -1101,6 +1101,140 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
   __syncthreads();
 }
 
+// ------------------------------------------------------ H^2 substitution
+// Vector substitution L x = b (trans = 0) or L^* x = b (trans = 1) with the
+// factor in H^2 form, following the recursion of Section 3 (solve the first
+// son, subtract the block (c2, c1) applied to its solution, solve the second
+// son).  The block products are not formed one by one: the forward
+// transformation xh_s = W_s^* x|_s of every solved cluster is computed once
+// (leaf, then transfer matrices upwards) and reused by every block that
+// needs it, and coupling contributions S_b xh_s to an unsolved cluster t are
+// summed in yh_t and moved to the sons with the transfer matrices just before
+// they are solved.  The sums are the same as in the block-by-block form, in
+// another association order.  trans = 0: yh in the row basis (side 0), xh in
+// the column basis (side 1); trans = 1: the roles are exchanged.
+
+__device__ void task_sv_zero(const DevEnv &e, int c, int bi, int trans) {
+  const int side = trans ? 1 : 0, m = e.bcols[bi];
+  const int wv = wave_id(), lane = lane_id();
+  for (int lv = e.level[c]; lv < e.nlev; ++lv) {
+    const int lo = dlo(e, c, lv), hi = lo + nlevel(e, c, lv);
+    for (int t = lo + wv; t < hi; t += NWAVE) {
+      const int kt = e.k[side][t];
+      MV y = xhslot(e.yh, t);
+      for (Walk2 w(lane, 64, kt); w.j < m; w.next()) y(w.i, w.j) = 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void task_sv_push(const DevEnv &e, int c, int bi, int trans) {
+  const int side = trans ? 1 : 0, m = e.bcols[bi];
+  const int kc = e.k[side][c];
+  const int wv = wave_id(), lane = lane_id();
+  if (kc > 0 && wv < 2) {
+    const int s = wv == 0 ? e.son0[c] : e.son1[c];
+    const int ks = e.k[side][s];
+    MV E = Eslot(e, side, s), yp = xhslot(e.yh, c), ys = xhslot(e.yh, s);
+    for (Walk2 w(lane, 64, ks); w.j < m; w.next()) {
+      double acc = ys(w.i, w.j);
+      for (int l = 0; l < kc; ++l) acc = fma(E(w.i, l), yp(l, w.j), acc);
+      ys(w.i, w.j) = acc;
+    }
+    if (lane == 0 && e.flops) e.flops[1 + wv] += 2.0 * ks * kc * m;
+  }
+  __syncthreads();
+}
+
+__device__ void task_sv_leaf(const DevEnv &e, int bcc, int bi, int trans) {
+  const int c = e.brow[bcc];
+  const int side = trans ? 1 : 0, oside = 1 - side, m = e.bcols[bi];
+  const int nc = e.size[c], kc = e.k[side][c], ko = e.k[oside][c];
+  MV w = bufrows(e, bi, c);
+  if (kc > 0) {
+    // w -= V_c yh_c (backward transformation of the coupling sums)
+    MV V = leafslot(e, side, c), y = xhslot(e.yh, c);
+    for (Walk2 q(threadIdx.x, blockDim.x, nc); q.j < m; q.next()) {
+      double acc = 0.0;
+      for (int l = 0; l < kc; ++l) acc = fma(V(q.i, l), y(l, q.j), acc);
+      w(q.i, q.j) -= acc;
+    }
+    __syncthreads();
+  }
+  wg_trsv_lower(nc, m, Nslot(e, bcc), w, trans);
+  if (ko > 0) {
+    // xh_c = W_c^* x|_c
+    MV Wb = leafslot(e, oside, c), x = xhslot(e.xh, c);
+    for (Walk2 q(threadIdx.x, blockDim.x, ko); q.j < m; q.next()) {
+      double acc = 0.0;
+      for (int l = 0; l < nc; ++l) acc = fma(Wb(l, q.i), w(l, q.j), acc);
+      x(q.i, q.j) = acc;
+    }
+  }
+  count(e, 2.0 * nc * (kc + ko) * m + (double)nc * nc * m);
+  __syncthreads();
+}
+
+__device__ void task_sv_cross(const DevEnv &e, const int *aux, int off, int ng, int bi, int trans) {
+  const int m = e.bcols[bi];
+  const int side = trans ? 1 : 0, oside = 1 - side;
+  const int wv = wave_id(), lane = lane_id();
+  double fl = 0.0;
+  // one group per updated cluster t (so no two waves write the same data)
+  for (int g = wv; g < ng; g += NWAVE) {
+    const int *gp = aux + aux[off + g];
+    const int t = gp[0], cnt = gp[1];
+    const int kt = e.k[side][t];
+    for (int j = 0; j < cnt; ++j) {
+      const int b = gp[2 + j];
+      const int o = trans ? e.brow[b] : e.bcol[b];
+      if (e.bkind[b] == 1) {
+        const int ko = e.k[oside][o];
+        if (kt == 0 || ko == 0) continue;
+        MV S = Sslot(e, b), x = xhslot(e.xh, o), y = xhslot(e.yh, t);
+        for (Walk2 w(lane, 64, kt); w.j < m; w.next()) {
+          double acc = y(w.i, w.j);
+          if (!trans) { for (int l = 0; l < ko; ++l) acc = fma(S(w.i, l), x(l, w.j), acc); }
+          else { for (int l = 0; l < ko; ++l) acc = fma(S(l, w.i), x(l, w.j), acc); }
+          y(w.i, w.j) = acc;
+        }
+        fl += 2.0 * kt * ko * m;
+      } else {
+        const int nt = e.size[t], no = e.size[o];
+        MV N = Nslot(e, b), xo = bufrows(e, bi, o), wt = bufrows(e, bi, t);
+        for (Walk2 w(lane, 64, nt); w.j < m; w.next()) {
+          double acc = 0.0;
+          if (!trans) { for (int l = 0; l < no; ++l) acc = fma(N(w.i, l), xo(l, w.j), acc); }
+          else { for (int l = 0; l < no; ++l) acc = fma(N(l, w.i), xo(l, w.j), acc); }
+          wt(w.i, w.j) -= acc;
+        }
+        fl += 2.0 * nt * no * m;
+      }
+    }
+  }
+  if (lane == 0 && e.flops) e.flops[1 + wv] += fl;
+  __syncthreads();
+}
+
+__device__ void task_sv_up(const DevEnv &e, int c, int bi, int trans) {
+  const int oside = trans ? 0 : 1, m = e.bcols[bi];
+  const int kc = e.k[oside][c];
+  if (kc > 0) {
+    const int c1 = e.son0[c], c2 = e.son1[c];
+    const int k1 = e.k[oside][c1], k2 = e.k[oside][c2];
+    MV E1 = Eslot(e, oside, c1), E2 = Eslot(e, oside, c2);
+    MV x1 = xhslot(e.xh, c1), x2 = xhslot(e.xh, c2), xc = xhslot(e.xh, c);
+    for (Walk2 w(threadIdx.x, blockDim.x, kc); w.j < m; w.next()) {
+      double acc = 0.0;
+      for (int l = 0; l < k1; ++l) acc = fma(E1(l, w.i), x1(l, w.j), acc);
+      for (int l = 0; l < k2; ++l) acc = fma(E2(l, w.i), x2(l, w.j), acc);
+      xc(w.i, w.j) = acc;
+    }
+    count(e, 2.0 * (k1 + k2) * kc * m);
+  }
+  __syncthreads();
+}
+
 // out|_cl = alpha in|_cl op(S_b)
 __device__ void task_rmul_s(const DevEnv &e, int bin, int bout, int b, int transS, int cl, double alpha) {
   const int kt = e.k[0][e.brow[b]], ks = e.k[1][e.bcol[b]];
@@ -1273,7 +1407,7 @@ __device__ void task_copy(const DevEnv &e, int ba, int bo, int cl) {
 
 // ============================================================ interpreter
 __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, int ntask,
-                                               const DevEnv *__restrict__ env) {
+                                               const DevEnv *__restrict__ env, const int *__restrict__ aux) {
   extern __shared__ double lds_raw[];
   const DevEnv &e = *env;
   const Lds L = lds_layout(lds_raw);
@@ -1311,6 +1445,11 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
       case OP_TRSV: task_trsv(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_SUB: task_sub(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_COPY: task_copy(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_SV_ZERO: task_sv_zero(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_SV_PUSH: task_sv_push(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_SV_LEAF: task_sv_leaf(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_SV_CROSS: task_sv_cross(e, aux, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
+      case OP_SV_UP: task_sv_up(e, tk.i[0], tk.i[1], tk.i[2]); break;
       default: set_error(e, E_ARG, tk.op); break;
     }
     if (e.prof && threadIdx.x == 0 && tk.op > 0 && tk.op < 32) {

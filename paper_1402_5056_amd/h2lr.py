@@ -275,7 +275,8 @@ def h2_mat_flops(m: Mat, reset: bool = False) -> float:
 
 
 OPS = ["", "addlr", "expand", "bapply", "rmul_s", "copy_near", "ident", "near_add", "temp_init",
-       "temp_add", "potrf", "trsm", "trsv", "sub", "copy"]
+       "temp_add", "potrf", "trsm", "trsv", "sub", "copy", "sv_zero", "sv_push", "sv_leaf", "sv_cross",
+       "sv_up"]
 STAGES = ["zero-check", "rfactors", "path-weights", "subtree-weights", "recompress", "couplings",
           "nearfield", "commit"]
 
