@@ -63,6 +63,27 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   return fma(0.5 * y, fma(-r, r, x), r);   // one correction of the root itself
 }
 
+// acc + sum_{l = lo}^{hi-1} a(l) b(l), accumulated in ascending order.  The
+// loads are issued in chunks of 8 (indices past the end clamped to hi-1 and
+// their products dropped), so that a chunk costs one memory latency; a plain
+// loop with a run-time trip count waits for every load.
+template <class FA, class FB>
+__device__ __forceinline__ double dotc(int lo, int hi, FA a, FB b, double acc) {
+  constexpr int U = 8;
+  for (int l0 = lo; l0 < hi; l0 += U) {
+    double x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = l0 + u < hi ? l0 + u : hi - 1;
+      x[u] = a(l);
+      y[u] = b(l);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = fma(l0 + u < hi ? x[u] : 0.0, y[u], acc);
+  }
+  return acc;
+}
+
 // Sum over aligned groups of g lanes (g in {1, 2, 4, 8, 16}); every lane of
 // the group receives the sum.  Butterfly: xor 1, xor 2 (quad_perm), then
 // half-row and row mirrors.

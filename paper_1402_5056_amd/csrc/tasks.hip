@@ -999,7 +999,7 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
         const int nc = e.size[c];
         if (kc > 0) for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
           double acc = 0.0;
-          for (int l = 0; l < nc; ++l) acc = fma(V(l, w.i), x(l, w.j), acc);
+          acc = dotc(0, nc, [&](int l) { return V(l, w.i); }, [&](int l) { return x(l, w.j); }, acc);
           xc(w.i, w.j) = acc;
         }
         if (lane == 0) fl += 2.0 * nc * kc * m;
@@ -1009,8 +1009,8 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
         MV E1 = Eslot(e, ss, c1), E2 = Eslot(e, ss, c2), x1 = xhslot(e.xh, c1), x2 = xhslot(e.xh, c2);
         if (kc > 0) for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
           double acc = 0.0;
-          for (int l = 0; l < k1; ++l) acc = fma(E1(l, w.i), x1(l, w.j), acc);
-          for (int l = 0; l < k2; ++l) acc = fma(E2(l, w.i), x2(l, w.j), acc);
+          acc = dotc(0, k1, [&](int l) { return E1(l, w.i); }, [&](int l) { return x1(l, w.j); }, acc);
+          acc = dotc(0, k2, [&](int l) { return E2(l, w.i); }, [&](int l) { return x2(l, w.j); }, acc);
           xc(w.i, w.j) = acc;
         }
         if (lane == 0) fl += 2.0 * (k1 + k2) * kc * m;
@@ -1036,8 +1036,8 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
         const int ko = e.k[ss][o];
         for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
           double acc = yc(w.i, w.j);
-          if (!trans) { for (int l = 0; l < ko; ++l) acc = fma(S(w.i, l), xo(l, w.j), acc); }
-          else { for (int l = 0; l < ko; ++l) acc = fma(S(l, w.i), xo(l, w.j), acc); }
+          if (!trans) { acc = dotc(0, ko, [&](int l) { return S(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+          else { acc = dotc(0, ko, [&](int l) { return S(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
           yc(w.i, w.j) = acc;
         }
         if (lane == 0) fl += 2.0 * kc * ko * m;
@@ -1056,7 +1056,7 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
       MV Ec = Eslot(e, ds, c), yp = xhslot(e.yh, p), yc = xhslot(e.yh, c);
       for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
         double acc = yc(w.i, w.j);
-        for (int l = 0; l < kp; ++l) acc = fma(Ec(w.i, l), yp(l, w.j), acc);
+        acc = dotc(0, kp, [&](int l) { return Ec(w.i, l); }, [&](int l) { return yp(l, w.j); }, acc);
         yc(w.i, w.j) = acc;
       }
       if (lane == 0) fl += 2.0 * kc * kp * m;
@@ -1074,15 +1074,15 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
       MV V = leafslot(e, ds, c), yc = xhslot(e.yh, c), oc = bufrows(e, bout, c);
       for (Walk2 w(lane, 64, nc); w.j < m; w.next()) {
         double acc = 0.0;
-        for (int l = 0; l < kc; ++l) acc = fma(V(w.i, l), yc(l, w.j), acc);
+        acc = dotc(0, kc, [&](int l) { return V(w.i, l); }, [&](int l) { return yc(l, w.j); }, acc);
         for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
           const int bb = nidx[p];
           const int o = trans ? e.brow[bb] : e.bcol[bb];
           if (!in_sub(e, sr, o)) continue;
           MV N = Nslot(e, bb), xo = bufrows(e, bin, o);
           const int no = e.size[o];
-          if (!trans) { for (int l = 0; l < no; ++l) acc = fma(N(w.i, l), xo(l, w.j), acc); }
-          else { for (int l = 0; l < no; ++l) acc = fma(N(l, w.i), xo(l, w.j), acc); }
+          if (!trans) { acc = dotc(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+          else { acc = dotc(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
         }
         oc(w.i, w.j) = oc(w.i, w.j) + alpha * acc;
       }
@@ -1138,7 +1138,7 @@ __device__ void task_sv_push(const DevEnv &e, int c, int bi, int trans) {
     MV E = Eslot(e, side, s), yp = xhslot(e.yh, c), ys = xhslot(e.yh, s);
     for (Walk2 w(lane, 64, ks); w.j < m; w.next()) {
       double acc = ys(w.i, w.j);
-      for (int l = 0; l < kc; ++l) acc = fma(E(w.i, l), yp(l, w.j), acc);
+      acc = dotc(0, kc, [&](int l) { return E(w.i, l); }, [&](int l) { return yp(l, w.j); }, acc);
       ys(w.i, w.j) = acc;
     }
     if (lane == 0 && e.flops) e.flops[1 + wv] += 2.0 * ks * kc * m;
@@ -1156,7 +1156,7 @@ __device__ void task_sv_leaf(const DevEnv &e, int bcc, int bi, int trans) {
     MV V = leafslot(e, side, c), y = xhslot(e.yh, c);
     for (Walk2 q(threadIdx.x, blockDim.x, nc); q.j < m; q.next()) {
       double acc = 0.0;
-      for (int l = 0; l < kc; ++l) acc = fma(V(q.i, l), y(l, q.j), acc);
+      acc = dotc(0, kc, [&](int l) { return V(q.i, l); }, [&](int l) { return y(l, q.j); }, acc);
       w(q.i, q.j) -= acc;
     }
     __syncthreads();
@@ -1167,7 +1167,7 @@ __device__ void task_sv_leaf(const DevEnv &e, int bcc, int bi, int trans) {
     MV Wb = leafslot(e, oside, c), x = xhslot(e.xh, c);
     for (Walk2 q(threadIdx.x, blockDim.x, ko); q.j < m; q.next()) {
       double acc = 0.0;
-      for (int l = 0; l < nc; ++l) acc = fma(Wb(l, q.i), w(l, q.j), acc);
+      acc = dotc(0, nc, [&](int l) { return Wb(l, q.i); }, [&](int l) { return w(l, q.j); }, acc);
       x(q.i, q.j) = acc;
     }
   }
@@ -1194,8 +1194,8 @@ __device__ void task_sv_cross(const DevEnv &e, const int *aux, int off, int ng, 
         MV S = Sslot(e, b), x = xhslot(e.xh, o), y = xhslot(e.yh, t);
         for (Walk2 w(lane, 64, kt); w.j < m; w.next()) {
           double acc = y(w.i, w.j);
-          if (!trans) { for (int l = 0; l < ko; ++l) acc = fma(S(w.i, l), x(l, w.j), acc); }
-          else { for (int l = 0; l < ko; ++l) acc = fma(S(l, w.i), x(l, w.j), acc); }
+          if (!trans) { acc = dotc(0, ko, [&](int l) { return S(w.i, l); }, [&](int l) { return x(l, w.j); }, acc); }
+          else { acc = dotc(0, ko, [&](int l) { return S(l, w.i); }, [&](int l) { return x(l, w.j); }, acc); }
           y(w.i, w.j) = acc;
         }
         fl += 2.0 * kt * ko * m;
@@ -1204,8 +1204,8 @@ __device__ void task_sv_cross(const DevEnv &e, const int *aux, int off, int ng, 
         MV N = Nslot(e, b), xo = bufrows(e, bi, o), wt = bufrows(e, bi, t);
         for (Walk2 w(lane, 64, nt); w.j < m; w.next()) {
           double acc = 0.0;
-          if (!trans) { for (int l = 0; l < no; ++l) acc = fma(N(w.i, l), xo(l, w.j), acc); }
-          else { for (int l = 0; l < no; ++l) acc = fma(N(l, w.i), xo(l, w.j), acc); }
+          if (!trans) { acc = dotc(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+          else { acc = dotc(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
           wt(w.i, w.j) -= acc;
         }
         fl += 2.0 * nt * no * m;
@@ -1226,8 +1226,8 @@ __device__ void task_sv_up(const DevEnv &e, int c, int bi, int trans) {
     MV x1 = xhslot(e.xh, c1), x2 = xhslot(e.xh, c2), xc = xhslot(e.xh, c);
     for (Walk2 w(threadIdx.x, blockDim.x, kc); w.j < m; w.next()) {
       double acc = 0.0;
-      for (int l = 0; l < k1; ++l) acc = fma(E1(l, w.i), x1(l, w.j), acc);
-      for (int l = 0; l < k2; ++l) acc = fma(E2(l, w.i), x2(l, w.j), acc);
+      acc = dotc(0, k1, [&](int l) { return E1(l, w.i); }, [&](int l) { return x1(l, w.j); }, acc);
+      acc = dotc(0, k2, [&](int l) { return E2(l, w.i); }, [&](int l) { return x2(l, w.j); }, acc);
       xc(w.i, w.j) = acc;
     }
     count(e, 2.0 * (k1 + k2) * kc * m);
