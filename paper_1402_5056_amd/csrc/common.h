@@ -97,6 +97,7 @@ constexpr int PROF_BAPPLY = 80;   // [80, 88): ticks of sub-block products by si
 constexpr int PROF_WAVE = 96;     // [96, 128): per-wave ticks / counts inside update stages
 constexpr int PROF_LEVEL = 128;    // [128, 144): ticks of low-rank updates by level of t0, [144, 160): counts
 constexpr int PROF_LEAFSTAGE = 160; // [160, 168): ticks per update stage, updates of leaf blocks only
-constexpr int PROF_LEN = 176;
+constexpr int PROF_TEMP = 176;     // [176, 184): ticks of truncated additions by row count class, [184, 192): counts
+constexpr int PROF_LEN = 192;
 
 }  // namespace h2

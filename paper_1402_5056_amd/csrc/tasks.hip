@@ -125,6 +125,15 @@ struct Wv {
   int w;
 };
 
+__device__ __forceinline__ Wv wave_areas_of(double *lds, const DevEnv &e, int w) {
+  Wv W;
+  W.w = w;
+  W.reg = lds + W.w * (WREG + WSMALL);
+  W.sig = W.reg + WREG;
+  W.ord = reinterpret_cast<int *>(W.sig + 64);
+  W.glob = e.wscr + (long)W.w * WGLOB;
+  return W;
+}
 __device__ __forceinline__ Wv wave_areas(double *lds, const DevEnv &e) {
   Wv W;
   W.w = wave_id();
@@ -1289,7 +1298,7 @@ __device__ void task_temp_init(const DevEnv &e, int bu, int bv, int t, int r) {
 
 // Truncated addition of the zero-extended emission (U on rows t', V on rows
 // r') to the temporary low-rank matrix (tU, tV) on (tT, rT).
-__device__ void task_temp_add(const DevEnv &e, const Lds &L, const Task &tk) {
+__device__ void task_temp_add_wg(const DevEnv &e, const Lds &L, const Task &tk) {
   const int tu = tk.i[0], tv = tk.i[1], tp = tk.i[2], rp = tk.i[3], bu = tk.i[4], bv = tk.i[5];
   const int tT = tk.i[6], rT = tk.i[7];
   const int k1 = e.bcols[tu], k2 = e.bcols[bu];
@@ -1369,6 +1378,111 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, const Task &tk) {
   __syncthreads();
 }
 
+// Truncated addition of a product contribution to a low-rank temporary
+// (Section 6): [TU U] [TV V]^* = Qa (Ra Rb^*) Qb^*, SVD of the small core
+// C = Ra Rb^*, truncation, TU <- Qa U_r Sigma_r, TV <- Qb W_r.  Wave-level
+// version: the two QRs run on waves 0 and 1, the core SVD (one-sided Jacobi
+// with the rotations accumulated) on wave 0, and the reflectors are applied
+// only to the r kept columns.  Temporaries too tall for the wave work areas
+// use the workgroup version.
+__device__ void task_temp_add(const DevEnv &e, const Lds &L, double *lds, const Task &tk) {
+  const int tu = tk.i[0], tv = tk.i[1], tp = tk.i[2], rp = tk.i[3], bu = tk.i[4], bv = tk.i[5];
+  const int tT = tk.i[6], rT = tk.i[7];
+  const int k1 = e.bcols[tu], k2 = e.bcols[bu];
+  const int kk = k1 + k2;
+  if (kk == 0) return;
+  const int mt = e.size[tT], mr = e.size[rT];
+  const int qa = mt < kk ? mt : kk, qb = mr < kk ? mr : kk;
+  // capacity check against the allocations below (work areas of waves 0 and 1)
+  {
+    const long need0 = (long)(mt | 1) * kk + (kk | 1) + (long)(qa | 1) * qb + (long)(qb | 1) * qb +
+                       (long)(qa | 1) * qa + (long)(mt | 1) * (qa > qb ? qa : qb);
+    const long need1 = (long)(mr | 1) * kk + (kk | 1) + (long)(mr | 1) * (qa > qb ? qa : qb);
+    if (need0 > WGLOB || need1 > WGLOB) { task_temp_add_wg(e, L, tk); return; }
+  }
+  const int w = wave_id(), lane = lane_id();
+  const Wv W0 = wave_areas_of(lds, e, 0), W1 = wave_areas_of(lds, e, 1);
+  WvAlloc a0 = wv_alloc(e, W0), a1 = wv_alloc(e, W1);
+  const MV X0 = a0.take(mt, kk), X1 = a1.take(mr, kk);
+  double *tau0 = a0.take(kk, 1).p, *tau1 = a1.take(kk, 1).p;
+  if (w < 2) {
+    const int rows = w == 0 ? mt : mr;
+    const MV X = w == 0 ? X0 : X1;
+    const MV T = w == 0 ? bufrows(e, tu, tT) : bufrows(e, tv, rT);
+    const int cl = w == 0 ? tp : rp, clT = w == 0 ? tT : rT;
+    const int at = e.offset[cl] - e.offset[clT], nt = e.size[cl];
+    const MV U = bufrows(e, w == 0 ? bu : bv, cl);
+    for (int q = lane; q < rows * kk; q += 64) {
+      const int i = q % rows, j = q / rows;
+      X(i, j) = j < k1 ? T(i, j) : ((i >= at && i < at + nt) ? U(i - at, j - k1) : 0.0);
+    }
+    wave_sync();
+    wv_qr(rows, kk, X, w == 0 ? tau0 : tau1);
+  }
+  __syncthreads();
+  // core C = Ra Rb^* (qa x qb) and its SVD on wave 0
+  const bool tr = qa < qb;            // Jacobi on C^* when C is wide
+  const int nj = tr ? qa : qb;        // columns rotated
+  const MV C = a0.take(qa, qb), J = a0.take(nj, nj);
+  if (w == 0) {
+    for (int q = lane; q < qa * qb; q += 64) {
+      const int i = q % qa, j = q / qa;
+      double acc = 0.0;
+      for (int l = (i > j ? i : j); l < kk; ++l) acc = fma(X0(i, l), X1(j, l), acc);
+      C(i, j) = acc;
+    }
+    for (int q = lane; q < nj * nj; q += 64) J(q % nj, q / nj) = (q % nj == q / nj) ? 1.0 : 0.0;
+    wave_sync();
+    const MV G = tr ? mv_t(C) : C;    // rows x nj
+    const int grow = tr ? qb : qa;
+    MV Jv = J;
+    wave_jacobi(grow, nj, G, &Jv);
+    wv_colnorms_sorted(grow, nj, G, W0.sig, W0.ord);
+    if (lane == 0) {
+      double tau = 0.0;
+      if (e.mode == 0) {
+        double s2 = 0.0;
+        for (int j = 0; j < nj; ++j) s2 += W0.sig[j] * W0.sig[j];
+        tau = e.eps * sqrt(s2);
+      } else if (e.mode == 1) {
+        tau = e.eps * (nj > 0 ? W0.sig[W0.ord[0]] : 0.0);
+      }
+      int r = 0;
+      for (int j = 0; j < nj; ++j) r += W0.sig[W0.ord[j]] > tau ? 1 : 0;
+      W0.ord[127] = r;
+    }
+    count(e, fl_qr(mt, kk) + fl_qr(mr, kk) + fl_gemm(qa, qb, kk) + fl_svd(qa, qb) +
+             14.0 * (double)nj * nj * nj);
+  }
+  __syncthreads();
+  const int r = W0.ord[127];
+  if (r > e.rank_cap) { set_error(e, E_RANK_CAP, tT); return; }
+  // TU = Qa (U Sigma)_r on wave 0, TV = Qb W_r on wave 1
+  if (w < 2) {
+    const int rows = w == 0 ? mt : mr, qx = w == 0 ? qa : qb;
+    WvAlloc az = w == 0 ? a0 : a1;
+    const MV Z = az.take(rows, r > 0 ? r : 1);
+    const MV G = tr ? mv_t(C) : C;
+    for (int q = lane; q < rows * r; q += 64) {
+      const int i = q % rows, j = q / rows;
+      const int c = W0.ord[j];
+      double v = 0.0;
+      if (i < qx) {
+        if (w == 0) v = tr ? J(i, c) * W0.sig[c] : G(i, c);                       // U Sigma
+        else v = tr ? (W0.sig[c] > 0.0 ? G(i, c) / W0.sig[c] : 0.0) : J(i, c);    // W
+      }
+      Z(i, j) = v;
+    }
+    wave_sync();
+    wv_apply_q(rows, kk, w == 0 ? X0 : X1, w == 0 ? tau0 : tau1, Z, r);
+    const MV out = w == 0 ? bufrows(e, tu, tT) : bufrows(e, tv, rT);
+    for (int q = lane; q < rows * r; q += 64) out(q % rows, q / rows) = Z(q % rows, q / rows);
+    if (lane == 0 && e.flops) e.flops[1 + w] += 4.0 * rows * kk * r;
+  }
+  if (threadIdx.x == 0) { e.bcols[tu] = r; e.bcols[tv] = r; }
+  __syncthreads();
+}
+
 __device__ void task_potrf(const DevEnv &e, const Lds &L, int bcc, int t) {
   const int info = wg_potrf(e.size[t], Nslot(e, bcc), L.iw);
   count(e, (double)e.size[t] * e.size[t] * e.size[t] / 3.0);
@@ -1439,7 +1553,16 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
       case OP_IDENT: task_ident(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_NEAR_ADD: task_near_add(e, tk.i[0], tk.i[1], tk.i[2], tk.alpha); break;
       case OP_TEMP_INIT: task_temp_init(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
-      case OP_TEMP_ADD: task_temp_add(e, L, tk); break;
+      case OP_TEMP_ADD: {
+        task_temp_add(e, L, lds_raw, tk);
+        if (e.prof && threadIdx.x == 0) {
+          const int rows = e.size[tk.i[6]] > e.size[tk.i[7]] ? e.size[tk.i[6]] : e.size[tk.i[7]];
+          const int cls = rows <= 32 ? 0 : rows <= 128 ? 1 : rows <= 512 ? 2 : rows <= 2048 ? 3 : 4;
+          e.prof[PROF_TEMP + cls] += wall_clock64() - t0;
+          e.prof[PROF_TEMP + 8 + cls] += 1;
+        }
+        break;
+      }
       case OP_POTRF: task_potrf(e, L, tk.i[0], tk.i[1]); break;
       case OP_TRSM: task_trsm(e, tk.i[0], tk.i[1]); break;
       case OP_TRSV: task_trsv(e, tk.i[0], tk.i[1], tk.i[2]); break;

@@ -291,8 +291,8 @@ WAVE_COUNTS = ["weight calls", "weight blocks", "weight nonempty", "qr calls", "
 
 def h2_profile(m: Mat, enable: bool = True):
     """Return the previous counters as a dict and (re)enable collection."""
-    buf = np.zeros(176, np.int64)
-    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 176))
+    buf = np.zeros(192, np.int64)
+    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 192))
     out = {}
     for i, name in enumerate(OPS):
         if name and buf[i]:
@@ -308,6 +308,8 @@ def h2_profile(m: Mat, enable: bool = True):
     out["leaf_stages"] = {name: buf[160 + i] * 1e-8 for i, name in enumerate(STAGES)}
     out["svd_classes"] = {c: (int(buf[172 + i]), buf[168 + i] * 1e-8) for i, c in
                           enumerate(["<=8", "<=16", "<=32", ">32"])}
+    out["temp_classes"] = {c: (int(buf[184 + i]), buf[176 + i] * 1e-8) for i, c in
+                           enumerate(["<=32", "<=128", "<=512", "<=2048", ">2048"])}
     return out
 
 
