@@ -156,7 +156,8 @@ __device__ void wg_gemm(int m, int n, int k, double alpha, MV A, MV B, double be
 }
 
 // Division-free walk over the entries of an m x n matrix: a thread starts at
-// entry `start` (column-major) and advances by `step` entries.
+// entry `start` (column-major) and advances by `step` entries.  Needs m > 0
+// (callers skip empty row ranges).
 struct Walk2 {
   int i, j, di, dj, m;
   __device__ __forceinline__ Walk2(int start, int step, int m_) : m(m_) {

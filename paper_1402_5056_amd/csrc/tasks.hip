@@ -661,17 +661,29 @@ __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
 }
 
 // R-factor of a predecessor's basis after E_{t0} changed (one wave).
-__device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c) {
+// R-factor of the basis of c from its sons (rho_c = R of [rho_c1 E_c1;
+// rho_c2 E_c2]).  The son vs, if it is one, is the root of a subtree just
+// recompressed whose new rank vr is not committed yet: its basis is
+// orthonormal, so its block is E_vs itself.
+__device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c, int vs, int vr) {
   const int lane = lane_id();
   unsigned long long tw = wt_now(e);
   wc_add(e, WC_REFRESH, 1);
   const int kc = e.k[side][c];
   const int c1 = e.son0[c], c2 = e.son1[c];
-  const int m1 = e.rho_m[side][c1], m2 = e.rho_m[side][c2];
+  const int m1 = c1 == vs ? vr : e.rho_m[side][c1], m2 = c2 == vs ? vr : e.rho_m[side][c2];
   WvAlloc al = wv_alloc(e, W);
   MV A = al.take(m1 + m2, kc);
-  wv_gemm(m1, kc, e.k[side][c1], 1.0, rhoslot(e, side, c1), Eslot(e, side, c1), 0.0, mv_at(A, 0, 0));
-  wv_gemm(m2, kc, e.k[side][c2], 1.0, rhoslot(e, side, c2), Eslot(e, side, c2), 0.0, mv_at(A, m1, 0));
+  for (int sn = 0; sn < 2; ++sn) {
+    const int cs = sn == 0 ? c1 : c2, ms = sn == 0 ? m1 : m2, off = sn == 0 ? 0 : m1;
+    const MV Es = Eslot(e, side, cs);
+    if (cs == vs) {
+      for (int q = lane; q < ms * kc; q += 64) A(off + q % ms, q / ms) = Es(q % ms, q / ms);
+      wave_sync();
+    } else {
+      wv_gemm(ms, kc, e.k[side][cs], 1.0, rhoslot(e, side, cs), Es, 0.0, mv_at(A, off, 0));
+    }
+  }
   const int m = m1 + m2;
   wv_qr(m, kc, A, nullptr);
   const int mr = m < kc ? m : kc;
@@ -681,7 +693,8 @@ __device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c) {
     R(i, j) = j >= i ? A(i, j) : 0.0;
   }
   if (lane == 0) e.rho_m[side][c] = mr;
-  count_w(e, W, fl_qr(m, kc) + fl_gemm(m1, kc, e.k[side][c1]) + fl_gemm(m2, kc, e.k[side][c2]));
+  count_w(e, W, fl_qr(m, kc) + (c1 == vs ? 0.0 : fl_gemm(m1, kc, e.k[side][c1])) +
+                    (c2 == vs ? 0.0 : fl_gemm(m2, kc, e.k[side][c2])));
   wave_sync();
   wt_add(e, WT_REFRESH, tw);
 }
@@ -786,9 +799,20 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
     if (e.err[0] != 0) return;
   }
   prof_stage(e, 4, tstage, leafupd);
-  // --- step 5: couplings of every admissible leaf touching the subtrees
+  // --- step 6, first part: R-factors on the paths root -> parent(t0) and
+  // root -> parent(s0) (one wave per side).  They read only the recompressed
+  // subtree roots and the bases above them, so they run while the other
+  // waves (and these, afterwards) update the couplings and nearfield blocks.
+  if (W.w < 2) {
+    const int side = W.w, root = u.r0[side];
+    for (int c = e.parent[root]; c >= 0; c = e.parent[c]) wv_refresh_rho(e, W, side, c, root, e.wnewk[side][root]);
+  }
+  // --- step 5: couplings of every admissible leaf touching the subtrees,
+  // assigned greedily to the least loaded wave (waves 0 and 1 start with the
+  // path refreshes, counted as one item each)
   {
-    int q = 0;
+    int load[NWAVE];
+    for (int w = 0; w < NWAVE; ++w) load[w] = w < 2 ? lv0[w] : 0;
     for (int side = 0; side < 2; ++side) {
       const int root = u.r0[side];
       const int *ptr = side == 0 ? e.rowptr : e.colptr;
@@ -799,8 +823,10 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
           for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
             const int b = idx[p];
             if (side == 1 && in_sub(e, u.r0[0], e.brow[b])) continue;
-            if (q % NWAVE == W.w) wv_coupling(e, u, W, b);
-            ++q;
+            int wmin = 0;
+            for (int w = 1; w < NWAVE; ++w) wmin = load[w] < load[wmin] ? w : wmin;
+            ++load[wmin];
+            if (wmin == W.w) wv_coupling(e, u, W, b);
           }
         }
       }
@@ -844,11 +870,6 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
         if (threadIdx.x == 0) { e.k[side][c] = r; e.rho_m[side][c] = r; }
       }
     }
-  }
-  __syncthreads();
-  if (W.w < 2) {
-    const int side = W.w;
-    for (int c = e.parent[u.r0[side]]; c >= 0; c = e.parent[c]) wv_refresh_rho(e, W, side, c);
   }
   __syncthreads();
   prof_stage(e, 7, tstage, leafupd);
@@ -1131,7 +1152,8 @@ __device__ void task_sv_zero(const DevEnv &e, int c, int bi, int trans) {
     for (int t = lo + wv; t < hi; t += NWAVE) {
       const int kt = e.k[side][t];
       MV y = xhslot(e.yh, t);
-      for (Walk2 w(lane, 64, kt); w.j < m; w.next()) y(w.i, w.j) = 0.0;
+      if (kt > 0)   // (Walk2 needs a non-empty row range)
+        for (Walk2 w(lane, 64, kt); w.j < m; w.next()) y(w.i, w.j) = 0.0;
     }
   }
   __syncthreads();
@@ -1145,7 +1167,7 @@ __device__ void task_sv_push(const DevEnv &e, int c, int bi, int trans) {
     const int s = wv == 0 ? e.son0[c] : e.son1[c];
     const int ks = e.k[side][s];
     MV E = Eslot(e, side, s), yp = xhslot(e.yh, c), ys = xhslot(e.yh, s);
-    for (Walk2 w(lane, 64, ks); w.j < m; w.next()) {
+    if (ks > 0) for (Walk2 w(lane, 64, ks); w.j < m; w.next()) {
       double acc = ys(w.i, w.j);
       acc = dotc(0, kc, [&](int l) { return E(w.i, l); }, [&](int l) { return yp(l, w.j); }, acc);
       ys(w.i, w.j) = acc;

@@ -158,6 +158,71 @@ def test_precond_and_pcg(lib):
     assert np.linalg.norm(p["b"] - p["A"] @ x.cpu().numpy()) / np.linalg.norm(p["b"]) < 1e-8
 
 
+def test_precond_multi_rhs(lib):
+    """Preconditioner with several right-hand sides (the substitution's
+    coupling sums then have more columns than ranks of some clusters)."""
+    print("case: precond nrhs=5 N=32 leaf 16", flush=True)
+    torch = gpu()
+    p, ctx, bt, M, oc, ob = _setup(lib, 32, sigma_seed=5, leaf=16, lower=True)
+    L = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), TruncParams(1e-6, "block_rel", 32))
+    lib.h2_cholesky(M, lib.trunc(1e-6, "block_rel", 32))
+    r = w.gaussian(oc.n, 5, 17)
+    R = torch.tensor(np.ascontiguousarray(r.T), device="cuda")
+    Zt = torch.zeros_like(R)
+    lib.h2_precond(M, R, Zt)
+    zref = np.stack([o_precond(L, r[:, i]) for i in range(5)])
+    assert rel2(Zt.cpu().numpy(), zref) < TOL
+
+
+def test_full_size_properties(lib):
+    """Benchmark size (P1 FEM 256 x 256, n = 65,025, sigma on 8 x 8
+    subdomains, leaf 32, eta 2, block-relative 1e-4), where the oracle is too
+    slow for a full comparison:
+    * sampled exact output: the diagonal block of the first leaf of L is the
+      dense Cholesky factor of the same block of A (no update reaches it);
+    * the factor is a good preconditioner: power-iteration estimate of
+      ||I - (L L^*)^{-1} A||_2 (the error measure of the paper's Table 1);
+    * PCG reaches ||r|| <= 1e-8 ||b|| for the exact sparse A (host check)."""
+    print("case: full size 256x256", flush=True)
+    torch = gpu()
+    p = w.problem(256, sigma_seed=10, rhs_seed=11)
+    n = p["A"].shape[0]
+    ctx = lib.h2_ctx_create(0)
+    ct = lib.h2_ctree_build(ctx, p["coords"], 32)
+    bt = lib.h2_btree_build(ctx, ct, 2.0)
+    Lm = lib.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
+    lib.h2_cholesky(Lm, lib.trunc(1e-4, "block_rel", 32))
+    tree = lib.h2_ctree_export(ct)
+    leaf0 = int(np.flatnonzero(tree["son0"] < 0)[0])
+    idx = tree["perm"][tree["offset"][leaf0]:tree["offset"][leaf0] + tree["size"][leaf0]]
+    E = torch.zeros((len(idx), n), dtype=torch.float64, device="cuda")
+    E[torch.arange(len(idx)), torch.tensor(idx, device="cuda")] = 1.0
+    Y = torch.zeros_like(E)
+    lib.h2_matvec(Lm, E, Y)
+    Lblk = Y.cpu().numpy()[:, idx].T
+    Lref = np.linalg.cholesky(p["A"][idx][:, idx].toarray())
+    assert np.linalg.norm(Lblk - Lref) / np.linalg.norm(Lref) < 1e-13
+    A = lib.h2_csr_create(ctx, p["A"])
+    x = torch.tensor(w.gaussian(n, 1, 3)[:, 0], device="cuda")
+    x /= torch.linalg.norm(x)
+    ax, z = torch.zeros_like(x), torch.zeros_like(x)
+    err = 0.0
+    for _ in range(12):
+        lib.h2_spmv(A, x, ax)
+        lib.h2_precond(Lm, ax, z)
+        y = x - z
+        err = float(torch.linalg.norm(y))
+        x = y / err
+    print(f"  power-iteration ||I - (LL^*)^-1 A||_2 ~ {err:.3e}", flush=True)
+    assert err < 0.05
+    b = torch.tensor(p["b"], device="cuda")
+    xs = torch.zeros_like(b)
+    it, rel, ok = lib.h2_pcg(A, Lm, b, xs, 1e-8, 100)
+    assert ok and it <= 6
+    res = np.linalg.norm(p["b"] - p["A"] @ xs.cpu().numpy()) / np.linalg.norm(p["b"])
+    assert res < 1e-8
+
+
 def test_not_spd(lib):
     print("case: not SPD", flush=True)
     p = w.problem(16, rhs_seed=1)
