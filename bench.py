@@ -38,15 +38,25 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--side", type=int, default=256, help="grid side N (n = (N-1)^2)")
     ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--eta", type=float, default=2.0, help="admissibility parameter")
+    ap.add_argument("--sigma-seed", type=str, default="10",
+                    help="seed of the piecewise-constant coefficient, or 'none' for sigma = 1")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sides", type=str, default="64,128",
                     help="grid sides the oracle is timed on (bounded sample)")
+    ap.add_argument("--trace", type=str, default="",
+                    help="after the timed steps, factorise once more with the device counters on "
+                         "and write the per-task / per-stage breakdown (JSON) to this file")
     ap.add_argument("--oracle-worker", type=int, default=0, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
-def oracle_worker(side: int, eps: float, rtol: float):
+def sigma_seed(args):
+    return None if args.sigma_seed.lower() == "none" else int(args.sigma_seed)
+
+
+def oracle_worker(side: int, eps: float, rtol: float, eta: float = 2.0, sseed=10):
     """Time the CPU oracle on one full setup + solve (single thread)."""
     import numpy as np
     import workloads as w
@@ -54,9 +64,9 @@ def oracle_worker(side: int, eps: float, rtol: float):
     from oracle.h2 import TruncParams, from_csr
     from oracle.solve import pcg
     from oracle.trees import build_block_tree, build_cluster_tree
-    p = w.problem(side, sigma_seed=10, rhs_seed=11)
+    p = w.problem(side, sigma_seed=sseed, rhs_seed=11)
     ct = build_cluster_tree(p["coords"], 32)
-    bt = build_block_tree(ct, 2.0)
+    bt = build_block_tree(ct, eta)
     L = from_csr(p["A"], ct, bt, lower=True)
     t0 = time.perf_counter()
     cholesky(L, TruncParams(eps, "block_rel", 32))
@@ -75,7 +85,8 @@ def cpu_baseline(args, n_target: int):
     runs = []
     for side in [int(s) for s in args.cpu_sides.split(",") if s]:
         cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker", str(side),
-               "--eps", str(args.eps), "--rtol", str(args.rtol)]
+               "--eps", str(args.eps), "--rtol", str(args.rtol), "--eta", str(args.eta),
+               "--sigma-seed", args.sigma_seed]
         try:
             cmd = ["taskset", "-c", "0"] + cmd
             out = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
@@ -106,7 +117,7 @@ def cpu_baseline(args, n_target: int):
 def main():
     args = parse()
     if args.oracle_worker:
-        oracle_worker(args.oracle_worker, args.eps, args.rtol)
+        oracle_worker(args.oracle_worker, args.eps, args.rtol, args.eta, sigma_seed(args))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,12 +130,12 @@ def main():
     import workloads as w
     from paper_1402_5056_amd import h2lr   # fails loudly if the library is not built
 
-    p = w.problem(args.side, sigma_seed=10, rhs_seed=11)
+    p = w.problem(args.side, sigma_seed=sigma_seed(args), rhs_seed=11)
     n = p["A"].shape[0]
     stream = torch.cuda.current_stream()
     ctx = h2lr.h2_ctx_create(0, stream.cuda_stream)
     ct = h2lr.h2_ctree_build(ctx, p["coords"], 32)
-    bt = h2lr.h2_btree_build(ctx, ct, 2.0)
+    bt = h2lr.h2_btree_build(ctx, ct, args.eta)
     A0 = h2lr.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
     L = h2lr.h2_mat_copy(A0)
     csr = h2lr.h2_csr_create(ctx, p["A"])
@@ -188,8 +199,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"P1 FEM unit square {args.side}x{args.side} grid, n={n}, sigma 8x8 "
-                               f"subdomains log-uniform [1e-2,1e2] seed 10, leaf 32, eta 2, "
+        "config": {"workload": f"P1 FEM unit square {args.side}x{args.side} grid, n={n}, "
+                               + ("sigma = 1" if sigma_seed(args) is None else
+                                  f"sigma 8x8 subdomains log-uniform [1e-2,1e2] seed {args.sigma_seed}")
+                               + f", leaf 32, eta {args.eta:g}, "
                                f"block-relative eps {args.eps}, H2-Cholesky + PCG 1 Gaussian RHS "
                                f"to {args.rtol}",
                    "n": n, "precision": "fp64", "parallelism": "1 GPU"},
@@ -213,6 +226,28 @@ def main():
             "flops_per_launch": chol_flops,
         },
     }
+    if args.trace:
+        # one more factorisation with the device counters on (not part of the timed steps)
+        h2lr.h2_mat_assign(L, A0)
+        h2lr.h2_profile(L, True)
+        h2lr.h2_cholesky(L, tr)
+        r = torch.tensor(p["b"], device="cuda")
+        zz = torch.zeros_like(r)
+        prof = h2lr.h2_profile(L, True)
+        h2lr.h2_precond(L, r, zz)
+        prof_pre = h2lr.h2_profile(L, False)
+        torch.cuda.synchronize()
+
+        def plain(d):
+            if isinstance(d, dict):
+                return {str(k): plain(v) for k, v in d.items()}
+            if isinstance(d, (list, tuple)):
+                return [plain(v) for v in d]
+            return float(d) if not isinstance(d, (int, str)) else d
+        with open(args.trace, "w") as f:
+            json.dump({"factorisation": plain(prof), "preconditioner": plain(prof_pre),
+                       "units": "seconds of a 100 MHz device clock; (count, seconds) pairs"}, f, indent=1)
+        print(f"[bench] device-counter trace written to {args.trace}", file=sys.stderr, flush=True)
     if args.cpu_baseline:
         print("[bench] timing the CPU oracle (bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, n)

@@ -9,7 +9,7 @@ constexpr int KC = 32;     // rank capacity of basis / coupling slots
 constexpr int KM = 64;     // capacity of an extended rank k + k'
 constexpr int LS = 32;     // leaf capacity (rows of a leaf basis, nearfield side)
 constexpr int BC = 64;     // columns of a work buffer (row-major, ld = BC)
-constexpr int NT = 256;    // threads of the task interpreter workgroup
+constexpr int NT = 512;    // threads of the task interpreter workgroup
 constexpr int KPMAX = KM - KC;  // largest update rank k'
 
 // Device error codes written to err[0] (mirrors h2_status).

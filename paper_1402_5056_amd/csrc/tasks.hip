@@ -104,7 +104,7 @@ __device__ __forceinline__ void count(const DevEnv &e, double f) {
 // concurrently, one wave per cluster, with a workgroup barrier per level.
 
 constexpr int NWAVE = NT / 64;
-constexpr int WREG = 4864;      // doubles of LDS per wave for work matrices
+constexpr int WREG = 2304;      // doubles of LDS per wave for work matrices
 constexpr int WSMALL = 256;     // doubles of LDS per wave for vectors
 constexpr int WGLOB = 16384;    // doubles of global scratch per wave (overflow)
 constexpr int PRECOND_MIN = 10; // SVDs with more columns are QR-preconditioned
@@ -152,11 +152,12 @@ struct WvAlloc {
   double *lds, *glob;
   int *err;
   int lused, gused;
+  int lcap = WREG;   // doubles of LDS available at lds
   __device__ MV take(int m, int n) {
     const int ld = m | 1;
     const int need = ld * (n > 0 ? n : 1);
     double *p;
-    if (lused + need <= WREG) { p = lds + lused; lused += need; }
+    if (lused + need <= lcap) { p = lds + lused; lused += need; }
     else if (gused + need <= WGLOB) { p = glob + gused; gused += need; }
     else {
       if (lane_id() == 0) { err[1] = need; err[0] = E_SCRATCH; }
@@ -1418,13 +1419,17 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, double *lds, const 
   // capacity check against the allocations below (work areas of waves 0 and 1)
   {
     const long need0 = (long)(mt | 1) * kk + (kk | 1) + (long)(qa | 1) * qb + (long)(qb | 1) * qb +
-                       (long)(qa | 1) * qa + (long)(mt | 1) * (qa > qb ? qa : qb);
+                       (long)(qa | 1) * qa + (long)(mt | 1) * (qa > qb ? qa : qb) + 3L * (kk | 1) * (kk + 1);
     const long need1 = (long)(mr | 1) * kk + (kk | 1) + (long)(mr | 1) * (qa > qb ? qa : qb);
     if (need0 > WGLOB || need1 > WGLOB) { task_temp_add_wg(e, L, tk); return; }
   }
   const int w = wave_id(), lane = lane_id();
-  const Wv W0 = wave_areas_of(lds, e, 0), W1 = wave_areas_of(lds, e, 1);
-  WvAlloc a0 = wv_alloc(e, W0), a1 = wv_alloc(e, W1);
+  // only waves 0 and 1 hold matrices here: each gets the LDS of half of the
+  // waves (the small vectors of the last wave hold the ranking)
+  const Wv W0 = wave_areas_of(lds, e, NWAVE - 1);
+  constexpr int HALF = (NWAVE / 2) * (WREG + WSMALL) - WSMALL;
+  WvAlloc a0 = WvAlloc{lds, e.wscr, e.err, 0, 0, HALF};
+  WvAlloc a1 = WvAlloc{lds + (NWAVE / 2) * (WREG + WSMALL), e.wscr + WGLOB, e.err, 0, 0, HALF};
   const MV X0 = a0.take(mt, kk), X1 = a1.take(mr, kk);
   double *tau0 = a0.take(kk, 1).p, *tau1 = a1.take(kk, 1).p;
   if (w < 2) {
@@ -1442,10 +1447,20 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, double *lds, const 
     wv_qr(rows, kk, X, w == 0 ? tau0 : tau1);
   }
   __syncthreads();
-  // core C = Ra Rb^* (qa x qb) and its SVD on wave 0
-  const bool tr = qa < qb;            // Jacobi on C^* when C is wide
+  // core C = Ra Rb^* (qa x qb) and its SVD on wave 0.  G = C, or C^* when C
+  // is wide (grow >= nj).  Above PRECOND_MIN columns the SVD is
+  // QR-preconditioned: G = Qg R, R^* = Q2 R2, one-sided Jacobi on
+  // X = R2^* with the rotations J accumulated, so that
+  // G = (Qg X J) (Q2 J)^* with the columns of X J orthogonal.
+  const bool tr = qa < qb;
   const int nj = tr ? qa : qb;        // columns rotated
+  const int grow = tr ? qb : qa;
+  const bool pre = nj > PRECOND_MIN;
   const MV C = a0.take(qa, qb), J = a0.take(nj, nj);
+  const MV G = tr ? mv_t(C) : C;      // grow x nj
+  double *taug = a0.take(nj, 1).p, *tauy = a0.take(nj, 1).p;
+  const MV Y = a0.take(nj, nj), X = a0.take(nj, nj);
+  const MV Gs = pre ? X : G;          // the matrix whose columns are rotated
   if (w == 0) {
     for (int q = lane; q < qa * qb; q += 64) {
       const int i = q % qa, j = q / qa;
@@ -1455,11 +1470,24 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, double *lds, const 
     }
     for (int q = lane; q < nj * nj; q += 64) J(q % nj, q / nj) = (q % nj == q / nj) ? 1.0 : 0.0;
     wave_sync();
-    const MV G = tr ? mv_t(C) : C;    // rows x nj
-    const int grow = tr ? qb : qa;
+    if (pre) {
+      wv_qr(grow, nj, G, taug);
+      for (int q = lane; q < nj * nj; q += 64) {
+        const int i = q % nj, j = q / nj;
+        Y(i, j) = i >= j ? G(j, i) : 0.0;
+      }
+      wave_sync();
+      wv_qr(nj, nj, Y, tauy);
+      for (int q = lane; q < nj * nj; q += 64) {
+        const int i = q % nj, j = q / nj;
+        X(i, j) = i >= j ? Y(j, i) : 0.0;
+      }
+      wave_sync();
+    }
+    const int srow = pre ? nj : grow;
     MV Jv = J;
-    wave_jacobi(grow, nj, G, &Jv);
-    wv_colnorms_sorted(grow, nj, G, W0.sig, W0.ord);
+    wave_jacobi(srow, nj, Gs, &Jv);
+    wv_colnorms_sorted(srow, nj, Gs, W0.sig, W0.ord);
     if (lane == 0) {
       double tau = 0.0;
       if (e.mode == 0) {
@@ -1479,23 +1507,30 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, double *lds, const 
   __syncthreads();
   const int r = W0.ord[127];
   if (r > e.rank_cap) { set_error(e, E_RANK_CAP, tT); return; }
-  // TU = Qa (U Sigma)_r on wave 0, TV = Qb W_r on wave 1
+  // TU = Qa (U Sigma)_r on wave 0, TV = Qb W_r on wave 1.  With G = C,
+  // U Sigma = (Qg) Gs J-rotated columns and W = (Q2) J; with G = C^* the two
+  // roles are exchanged.  (Qg, Q2 only when preconditioned.)
   if (w < 2) {
-    const int rows = w == 0 ? mt : mr, qx = w == 0 ? qa : qb;
+    const int rows = w == 0 ? mt : mr;
+    const int qx = pre ? nj : (w == 0 ? qa : qb);
     WvAlloc az = w == 0 ? a0 : a1;
     const MV Z = az.take(rows, r > 0 ? r : 1);
-    const MV G = tr ? mv_t(C) : C;
+    const bool rotated = (w == 0) != tr;   // this side takes the rotated columns
     for (int q = lane; q < rows * r; q += 64) {
       const int i = q % rows, j = q / rows;
       const int c = W0.ord[j];
       double v = 0.0;
       if (i < qx) {
-        if (w == 0) v = tr ? J(i, c) * W0.sig[c] : G(i, c);                       // U Sigma
-        else v = tr ? (W0.sig[c] > 0.0 ? G(i, c) / W0.sig[c] : 0.0) : J(i, c);    // W
+        if (rotated) v = w == 0 ? Gs(i, c) : (W0.sig[c] > 0.0 ? Gs(i, c) / W0.sig[c] : 0.0);
+        else v = w == 0 ? J(i, c) * W0.sig[c] : J(i, c);
       }
       Z(i, j) = v;
     }
     wave_sync();
+    if (pre) {
+      if (rotated) wv_apply_q(grow, nj, G, taug, Z, r);   // Qg
+      else wv_apply_q(nj, nj, Y, tauy, Z, r);             // Q2
+    }
     wv_apply_q(rows, kk, w == 0 ? X0 : X1, w == 0 ? tau0 : tau1, Z, r);
     const MV out = w == 0 ? bufrows(e, tu, tT) : bufrows(e, tv, rT);
     for (int q = lane; q < rows * r; q += 64) out(q % rows, q / rows) = Z(q % rows, q / rows);
