@@ -1012,13 +1012,6 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
   const int ss = trans ? 0 : 1, ds = 1 - ss;
   const int lane = lane_id(), wv = wave_id();
   double fl = 0.0;   // counted by lane 0 of each wave
-  {
-    MV out = bufrows(e, bout, dr);
-    const int rows = e.size[dr];
-    for (Walk2 w(threadIdx.x, blockDim.x, rows); w.j < m; w.next())
-      out(w.i, w.j) = beta == 0.0 ? 0.0 : beta * out(w.i, w.j);
-  }
-  __syncthreads();
   // forward transformation over the source subtree
   for (int lv = e.nlev - 1; lv >= e.level[sr]; --lv) {
     const int lo = dlo(e, sr, lv), hi = lo + nlevel(e, sr, lv);
@@ -1049,82 +1042,75 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
     }
     __syncthreads();
   }
-  // couplings into the destination subtree
+  // destination subtree, top-down, one pass per level: the coupling sum
+  // yh_c = sum_b S_b xh_o + E_c yh_parent, and for a leaf right away the rows
+  // out_c = beta out_c + alpha (V_c yh_c + sum_near N_b x_o)  (every row of
+  // the destination belongs to exactly one leaf)
   const int *ptr = trans ? e.colptr : e.rowptr;
   const int *idx = trans ? e.colidx : e.rowidx;
-  for (int lv = e.level[dr]; lv < e.nlev; ++lv) {
-    const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
-    for (int c = lo + wv; c < hi; c += NWAVE) {
-      const int kc = e.k[ds][c];
-      if (kc == 0) continue;
-      MV yc = xhslot(e.yh, c);
-      for (Walk2 w(lane, 64, kc); w.j < m; w.next()) yc(w.i, w.j) = 0.0;
-      for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
-        const int bb = idx[p];
-        const int o = trans ? e.brow[bb] : e.bcol[bb];
-        if (!in_sub(e, sr, o)) continue;
-        MV S = Sslot(e, bb), xo = xhslot(e.xh, o);
-        const int ko = e.k[ss][o];
-        for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
-          double acc = yc(w.i, w.j);
-          if (!trans) { acc = dotc(0, ko, [&](int l) { return S(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
-          else { acc = dotc(0, ko, [&](int l) { return S(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
-          yc(w.i, w.j) = acc;
-        }
-        if (lane == 0) fl += 2.0 * kc * ko * m;
-      }
-    }
-    __syncthreads();
-  }
-  // backward transformation
-  for (int lv = e.level[dr] + 1; lv < e.nlev; ++lv) {
-    const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
-    for (int c = lo + wv; c < hi; c += NWAVE) {
-      const int kc = e.k[ds][c];
-      const int p = e.parent[c];
-      const int kp = e.k[ds][p];
-      if (kc == 0) continue;
-      MV Ec = Eslot(e, ds, c), yp = xhslot(e.yh, p), yc = xhslot(e.yh, c);
-      for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
-        double acc = yc(w.i, w.j);
-        acc = dotc(0, kp, [&](int l) { return Ec(w.i, l); }, [&](int l) { return yp(l, w.j); }, acc);
-        yc(w.i, w.j) = acc;
-      }
-      if (lane == 0) fl += 2.0 * kc * kp * m;
-    }
-    __syncthreads();
-  }
-  // leaves: basis part and nearfield
   const int *nptr = trans ? e.ncolptr : e.nrowptr;
   const int *nidx = trans ? e.ncolidx : e.nrowidx;
   for (int lv = e.level[dr]; lv < e.nlev; ++lv) {
     const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
     for (int c = lo + wv; c < hi; c += NWAVE) {
-      if (!is_leaf(e, c)) continue;
-      const int nc = e.size[c], kc = e.k[ds][c];
-      MV V = leafslot(e, ds, c), yc = xhslot(e.yh, c), oc = bufrows(e, bout, c);
-      for (Walk2 w(lane, 64, nc); w.j < m; w.next()) {
-        double acc = 0.0;
-        acc = dotc(0, kc, [&](int l) { return V(w.i, l); }, [&](int l) { return yc(l, w.j); }, acc);
-        for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
-          const int bb = nidx[p];
+      const int kc = e.k[ds][c];
+      MV yc = xhslot(e.yh, c);
+      if (kc > 0) {
+        for (Walk2 w(lane, 64, kc); w.j < m; w.next()) yc(w.i, w.j) = 0.0;
+        for (int p = ptr[c]; p < ptr[c + 1]; ++p) {
+          const int bb = idx[p];
           const int o = trans ? e.brow[bb] : e.bcol[bb];
           if (!in_sub(e, sr, o)) continue;
-          MV N = Nslot(e, bb), xo = bufrows(e, bin, o);
-          const int no = e.size[o];
-          if (!trans) { acc = dotc(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
-          else { acc = dotc(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
+          MV S = Sslot(e, bb), xo = xhslot(e.xh, o);
+          const int ko = e.k[ss][o];
+          for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
+            double acc = yc(w.i, w.j);
+            if (!trans) { acc = dotc(0, ko, [&](int l) { return S(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+            else { acc = dotc(0, ko, [&](int l) { return S(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
+            yc(w.i, w.j) = acc;
+          }
+          if (lane == 0) fl += 2.0 * kc * ko * m;
         }
-        oc(w.i, w.j) = oc(w.i, w.j) + alpha * acc;
+        if (lv > e.level[dr]) {
+          const int pc = e.parent[c];
+          const int kp = e.k[ds][pc];
+          MV Ec = Eslot(e, ds, c), yp = xhslot(e.yh, pc);
+          for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
+            double acc = yc(w.i, w.j);
+            acc = dotc(0, kp, [&](int l) { return Ec(w.i, l); }, [&](int l) { return yp(l, w.j); }, acc);
+            yc(w.i, w.j) = acc;
+          }
+          if (lane == 0) fl += 2.0 * kc * kp * m;
+        }
       }
-      if (lane == 0) {
-        fl += 2.0 * nc * kc * m;
-        for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
-          const int o = trans ? e.brow[nidx[p]] : e.bcol[nidx[p]];
-          if (in_sub(e, sr, o)) fl += 2.0 * nc * e.size[o] * m;
+      if (is_leaf(e, c)) {
+        wave_sync();
+        const int nc = e.size[c];
+        MV V = leafslot(e, ds, c), oc = bufrows(e, bout, c);
+        for (Walk2 w(lane, 64, nc); w.j < m; w.next()) {
+          double acc = 0.0;
+          acc = dotc(0, kc, [&](int l) { return V(w.i, l); }, [&](int l) { return yc(l, w.j); }, acc);
+          for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
+            const int bb = nidx[p];
+            const int o = trans ? e.brow[bb] : e.bcol[bb];
+            if (!in_sub(e, sr, o)) continue;
+            MV N = Nslot(e, bb), xo = bufrows(e, bin, o);
+            const int no = e.size[o];
+            if (!trans) { acc = dotc(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+            else { acc = dotc(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
+          }
+          oc(w.i, w.j) = (beta == 0.0 ? 0.0 : beta * oc(w.i, w.j)) + alpha * acc;
+        }
+        if (lane == 0) {
+          fl += 2.0 * nc * kc * m;
+          for (int p = nptr[c]; p < nptr[c + 1]; ++p) {
+            const int o = trans ? e.brow[nidx[p]] : e.bcol[nidx[p]];
+            if (in_sub(e, sr, o)) fl += 2.0 * nc * e.size[o] * m;
+          }
         }
       }
     }
+    __syncthreads();
   }
   if (lane == 0 && e.flops) e.flops[1 + wv] += fl;
   __syncthreads();
