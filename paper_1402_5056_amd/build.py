@@ -18,18 +18,18 @@ def hipcc_command(out=LIB, arch="gfx950"):
             *SOURCES, "-o", out]
 
 
-def build(verbose=True):
+def build(verbose=True, out=LIB):
     """Always recompiles (the build check must exercise the compiler)."""
-    cmd = hipcc_command(LIB + ".tmp")
+    cmd = hipcc_command(out + ".tmp")
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed")
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
-    build()
+    build(out=os.path.abspath(sys.argv[1]) if len(sys.argv) > 1 else LIB)

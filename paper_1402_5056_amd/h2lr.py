@@ -19,7 +19,9 @@ import weakref
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libh2lr.so")
+# H2LR_LIBRARY selects another build of the same library (side-by-side
+# comparisons of builds); by default the in-tree one.
+LIB_PATH = os.environ.get("H2LR_LIBRARY") or os.path.join(_HERE, "libh2lr.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"h2lr library not built: {LIB_PATH} missing (run paper_1402_5056_amd/build.py)")
