@@ -563,7 +563,7 @@ __device__ void wv_gemm(int m, int n, int k, double alpha, MV A, MV B, double be
     const int di = 64 % m, dj = 64 / m;
     while (j < n) {
       double s = 0.0;
-      for (int l = 0; l < k; ++l) s = fma(A(i, l), B(l, j), s);
+      s = dotc(0, k, [&](int l) { return A(i, l); }, [&](int l) { return B(l, j); }, s);
       C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * s;
       i += di; j += dj;
       if (i >= m) { i -= m; ++j; }

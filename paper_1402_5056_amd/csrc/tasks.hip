@@ -107,7 +107,7 @@ constexpr int NWAVE = NT / 64;
 constexpr int WREG = 2304;      // doubles of LDS per wave for work matrices
 constexpr int WSMALL = 256;     // doubles of LDS per wave for vectors
 constexpr int WGLOB = 16384;    // doubles of global scratch per wave (overflow)
-constexpr int PRECOND_MIN = 10; // SVDs with more columns are QR-preconditioned
+constexpr int PRECOND_MIN = 6;  // SVDs with more columns are QR-preconditioned
 constexpr size_t LDS_WAVE_DOUBLES = (size_t)NWAVE * (WREG + WSMALL);
 constexpr size_t LDS_TOTAL_DOUBLES = LDS_WAVE_DOUBLES > LDS_DOUBLES ? LDS_WAVE_DOUBLES : LDS_DOUBLES;
 
@@ -258,7 +258,7 @@ __device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side,
       for (int q = lane; q < mc * K; q += 64) {
         const int i = q % mc, j = q / mc;
         double sacc = 0.0;
-        if (j < kc) { for (int l = 0; l < kch; ++l) sacc = fma(Rc(i, l), Ec(l, j), sacc); }
+        if (j < kc) { sacc = dotc(0, kch, [&](int l) { return Rc(i, l); }, [&](int l) { return Ec(l, j); }, sacc); }
         else sacc = Rc(i, kch + (j - kc));
         A(off + i, j) = sacc;
       }
@@ -388,7 +388,7 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
         for (int q = lane; q < mob * Kt; q += 64) {
           const int i = q % mob, j = q / mob;
           double acc = 0.0;
-          for (int c = 0; c < Ko; ++c) acc = fma(Ro(i, c), T(j, c), acc);
+          acc = dotc(0, Ko, [&](int c) { return Ro(i, c); }, [&](int c) { return T(j, c); }, acc);
           A(m + i, j) = acc;
         }
         wave_sync();
@@ -398,7 +398,7 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
           for (int q = lane; q < mob * mown; q += 64) {
             const int i = q % mob, a = q / mob;
             double acc = 0.0;
-            for (int j = 0; j < Kt; ++j) acc = fma(A(m + i, j), Rown(a, j), acc);
+            acc = dotc(0, Kt, [&](int j) { return A(m + i, j); }, [&](int j) { return Rown(a, j); }, acc);
             f2 = fma(acc, acc, f2);
           }
           f2 = wave_sum64(f2);
@@ -431,7 +431,7 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
       for (int q = lane; q < mp * Kt; q += 64) {
         const int i = q % mp, j = q / mp;
         double acc = 0.0;
-        if (j < kt) { for (int l = 0; l < kpar; ++l) acc = fma(Bp(i, l), Et(j, l), acc); }
+        if (j < kt) { acc = dotc(0, kpar, [&](int l) { return Bp(i, l); }, [&](int l) { return Et(j, l); }, acc); }
         else if (!root_of_sub) acc = Bp(i, kpar + (j - kt));   // identity part of diag(E_t, I)
         A(m + i, j) = acc;
       }
@@ -491,7 +491,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
       for (int q = lane; q < rc * K; q += 64) {
         const int i = q % rc, j = q / rc;
         double acc = 0.0;
-        if (j < kc) { for (int l = 0; l < kch; ++l) acc = fma(Rc(i, l), Ec(l, j), acc); }
+        if (j < kc) { acc = dotc(0, kch, [&](int l) { return Rc(i, l); }, [&](int l) { return Ec(l, j); }, acc); }
         else acc = Rc(i, kch + (j - kc));
         Vt(off + i, j) = acc;
       }
@@ -640,7 +640,7 @@ __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
     for (int q = lane; q < rows * St.Ks; q += 64) {
       const int i = q % rows, j = q / rows;
       double acc = 0.0;
-      for (int l = 0; l < St.Kt; ++l) acc = fma(Rt(i, l), St(l, j), acc);
+      acc = dotc(0, St.Kt, [&](int l) { return Rt(i, l); }, [&](int l) { return St(l, j); }, acc);
       P(i, j) = acc;
     }
     fl += fl_gemm(rows, St.Ks, St.Kt);
