@@ -886,7 +886,9 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
 __device__ void task_expand(const DevEnv &e, int side, int t, int bo) {
   const int kt = e.k[side][t];
   MV out = bufrows(e, bo, t);
-  if (is_leaf(e, t)) {
+  if (kt == 0) {
+    // (nothing to expand)
+  } else if (is_leaf(e, t)) {
     wg_copy(e.size[t], kt, leafslot(e, side, t), out);
   } else {
     // T_c = E_c T_father (k_c x k_t) for the descendants, top-down, in xh
@@ -1004,6 +1006,11 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
                             double alpha, double beta) {
   const int m = e.bcols[bin];
   const int t = e.brow[b], s = e.bcol[b];
+  if (m == 0) {   // no columns: nothing to compute (happens while ranks are still zero)
+    if (threadIdx.x == 0) e.bcols[bout] = 0;
+    __syncthreads();
+    return;
+  }
   if (e.bkind[b] != 0 && is_leaf(e, t) && is_leaf(e, s)) {
     bapply_leaf(e, L, b, trans, bin, bout, alpha, beta, m);
     return;
@@ -1261,6 +1268,11 @@ __device__ void task_sv_up(const DevEnv &e, int c, int bi, int trans) {
 __device__ void task_rmul_s(const DevEnv &e, int bin, int bout, int b, int transS, int cl, double alpha) {
   const int kt = e.k[0][e.brow[b]], ks = e.k[1][e.bcol[b]];
   const int kin = transS ? ks : kt, kout = transS ? kt : ks;
+  if (kout == 0) {
+    if (threadIdx.x == 0) e.bcols[bout] = 0;
+    __syncthreads();
+    return;
+  }
   MV S = Sslot(e, b);
   MV Sop = transS ? mv_t(S) : S;
   wg_gemm(e.size[cl], kout, kin, alpha, bufrows(e, bin, cl), Sop, 0.0, bufrows(e, bout, cl));
@@ -1294,6 +1306,7 @@ __device__ void task_ident(const DevEnv &e, int cl, int bo, int c0, int nc) {
 }
 
 __device__ void task_near_add(const DevEnv &e, int b, int bu, int bv, double alpha) {
+  if (e.bcols[bu] == 0) return;   // rank-0 contribution
   const int t = e.brow[b], s = e.bcol[b];
   wg_gemm(e.size[t], e.size[s], e.bcols[bu], alpha, bufrows(e, bu, t), mv_t(bufrows(e, bv, s)), 1.0,
           Nslot(e, b));
@@ -1543,6 +1556,7 @@ __device__ void task_trsm(const DevEnv &e, int b, int bcc) {
 }
 
 __device__ void task_trsv(const DevEnv &e, int bcc, int bi, int trans) {
+  if (e.bcols[bi] == 0) return;   // no columns
   const int c = e.brow[bcc];
   wg_trsv_lower(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), trans);
   count(e, (double)e.size[c] * e.size[c] * e.bcols[bi]);
