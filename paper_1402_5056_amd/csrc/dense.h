@@ -64,12 +64,11 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 }
 
 // acc + sum_{l = lo}^{hi-1} a(l) b(l), accumulated in ascending order.  The
-// loads are issued in chunks of 4 (indices past the end clamped to hi-1 and
+// loads are issued in chunks of U (indices past the end clamped to hi-1 and
 // their products dropped), so that a chunk costs one memory latency; a plain
 // loop with a run-time trip count waits for every load.
-template <class FA, class FB>
+template <int U = 4, class FA, class FB>
 __device__ __forceinline__ double dotc(int lo, int hi, FA a, FB b, double acc) {
-  constexpr int U = 4;
   for (int l0 = lo; l0 < hi; l0 += U) {
     double x[U], y[U];
 #pragma unroll

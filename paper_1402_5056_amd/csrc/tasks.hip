@@ -1034,7 +1034,7 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
         const int nc = e.size[c];
         if (kc > 0) for (Walk2 w(lane, 64, kc); w.j < m; w.next()) {
           double acc = 0.0;
-          acc = dotc(0, nc, [&](int l) { return V(l, w.i); }, [&](int l) { return x(l, w.j); }, acc);
+          acc = dotc<8>(0, nc, [&](int l) { return V(l, w.i); }, [&](int l) { return x(l, w.j); }, acc);
           xc(w.i, w.j) = acc;
         }
         if (lane == 0) fl += 2.0 * nc * kc * m;
@@ -1107,8 +1107,8 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
             if (!in_sub(e, sr, o)) continue;
             MV N = Nslot(e, bb), xo = bufrows(e, bin, o);
             const int no = e.size[o];
-            if (!trans) { acc = dotc(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
-            else { acc = dotc(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
+            if (!trans) { acc = dotc<8>(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+            else { acc = dotc<8>(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
           }
           oc(w.i, w.j) = (beta == 0.0 ? 0.0 : beta * oc(w.i, w.j)) + alpha * acc;
         }
@@ -1196,7 +1196,7 @@ __device__ void task_sv_leaf(const DevEnv &e, int bcc, int bi, int trans) {
     MV Wb = leafslot(e, oside, c), x = xhslot(e.xh, c);
     for (Walk2 q(threadIdx.x, blockDim.x, ko); q.j < m; q.next()) {
       double acc = 0.0;
-      acc = dotc(0, nc, [&](int l) { return Wb(l, q.i); }, [&](int l) { return w(l, q.j); }, acc);
+      acc = dotc<8>(0, nc, [&](int l) { return Wb(l, q.i); }, [&](int l) { return w(l, q.j); }, acc);
       x(q.i, q.j) = acc;
     }
   }
@@ -1233,8 +1233,8 @@ __device__ void task_sv_cross(const DevEnv &e, const int *aux, int off, int ng, 
         MV N = Nslot(e, b), xo = bufrows(e, bi, o), wt = bufrows(e, bi, t);
         for (Walk2 w(lane, 64, nt); w.j < m; w.next()) {
           double acc = 0.0;
-          if (!trans) { acc = dotc(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
-          else { acc = dotc(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
+          if (!trans) { acc = dotc<8>(0, no, [&](int l) { return N(w.i, l); }, [&](int l) { return xo(l, w.j); }, acc); }
+          else { acc = dotc<8>(0, no, [&](int l) { return N(l, w.i); }, [&](int l) { return xo(l, w.j); }, acc); }
           wt(w.i, w.j) -= acc;
         }
         fl += 2.0 * nt * no * m;
