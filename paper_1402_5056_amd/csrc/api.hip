@@ -603,7 +603,9 @@ static void sync_env(h2_mat_s &m) {
   }
 }
 
-static void run_tasks(h2_mat_s &m, const TaskList &tl) {
+// nthreads: workgroup size of the launch (NT, or 256 for task lists whose
+// kinds distribute work by the run-time wave count).
+static void run_tasks(h2_mat_s &m, const TaskList &tl, int nthreads = NT) {
   const Task *d_tasks = tl.d.p;
   const int count = tl.count;
   const size_t lds = LDS_TOTAL_DOUBLES * sizeof(double);
@@ -615,7 +617,7 @@ static void run_tasks(h2_mat_s &m, const TaskList &tl) {
   const int seg = 1 << 24;
   for (int off = 0; off < count; off += seg) {
     const int cnt = std::min(seg, count - off);
-    hipLaunchKernelGGL(k_interp, dim3(1), dim3(NT), lds, m.ctx->stream, d_tasks + off, cnt,
+    hipLaunchKernelGGL(k_interp, dim3(1), dim3(nthreads), lds, m.ctx->stream, d_tasks + off, cnt,
                        (const DevEnv *)m.d_env.p, (const int *)tl.aux.p);
     HIPCHK(hipGetLastError());
   }
@@ -1015,7 +1017,9 @@ static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
   hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, 0, nrhs, ct.d_perm.p, r,
                      (long)ct.n, l->env.buf[B_X], l->d_bcols.p, (int)B_X);
   HIPCHK(hipGetLastError());
-  run_tasks(*l, l->prec);
+  // the substitution tasks (and the leaf solves) use the run-time wave
+  // count; four waves measured faster than eight for them
+  run_tasks(*l, l->prec, 256);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
                      l->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
   HIPCHK(hipGetLastError());

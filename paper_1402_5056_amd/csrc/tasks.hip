@@ -1147,7 +1147,7 @@ __device__ void task_sv_zero(const DevEnv &e, int c, int bi, int trans) {
   const int wv = wave_id(), lane = lane_id();
   for (int lv = e.level[c]; lv < e.nlev; ++lv) {
     const int lo = dlo(e, c, lv), hi = lo + nlevel(e, c, lv);
-    for (int t = lo + wv; t < hi; t += NWAVE) {
+    for (int t = lo + wv; t < hi; t += num_waves()) {
       const int kt = e.k[side][t];
       MV y = xhslot(e.yh, t);
       if (kt > 0)   // (Walk2 needs a non-empty row range)
@@ -1210,7 +1210,7 @@ __device__ void task_sv_cross(const DevEnv &e, const int *aux, int off, int ng, 
   const int wv = wave_id(), lane = lane_id();
   double fl = 0.0;
   // one group per updated cluster t (so no two waves write the same data)
-  for (int g = wv; g < ng; g += NWAVE) {
+  for (int g = wv; g < ng; g += num_waves()) {
     const int *gp = aux + aux[off + g];
     const int t = gp[0], cnt = gp[1];
     const int kt = e.k[side][t];
