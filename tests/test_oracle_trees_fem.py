@@ -125,7 +125,7 @@ def test_fem3d_q1_closed_form_eigenvalues():
 
 def test_fem_far_blocks_vanish():
     """A is zero on every admissible block at the experiment grids (so H^2(A)
-    has rank 0 everywhere); checked on cfg1 and a 3D grid."""
+    has rank 0 everywhere); checked on the 32 x 32 grid and a 3D grid."""
     from oracle.h2 import from_csr, to_dense
     for N, dim in ((32, 2), (16, 3)):
         pb = w.problem(N, dim=dim, sigma_seed=4)

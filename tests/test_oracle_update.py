@@ -9,8 +9,8 @@ from oracle.update import addlr
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    p = w.problem("cfg1")
+def sq32():
+    p = w.problem("p1_square_32")
     ct = build_cluster_tree(p["coords"], 32)
     bt = build_block_tree(ct, 2.0)
     return p, ct, bt
@@ -20,10 +20,10 @@ def _rel2(A, B):
     return np.linalg.norm(A - B, 2) / max(np.linalg.norm(B, 2), 1e-300)
 
 
-def test_global_update_exact(cfg1):
+def test_global_update_exact(sq32):
     """Without truncation the recompressed matrix equals Z + X Y^* (the
     rank-extended representation of eq. (tildeZ_h2) is exact)."""
-    p, ct, bt = cfg1
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     D0 = to_dense(Z)
     X = w.gaussian(ct.n, 8, 1)[ct.perm]
@@ -44,11 +44,11 @@ def _local_blocks(ct, bt):
     return [adm[3], adm[40], inner[2], inner[7], diag[1]]
 
 
-def test_local_updates_exact_sequence(cfg1):
+def test_local_updates_exact_sequence(sq32):
     """A sequence of local updates on admissible leaves, subdivided blocks and
     diagonal blocks stays exact without truncation, and the bases stay nested
     with correct R-factors (rho^* rho = V^* V)."""
-    p, ct, bt = cfg1
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     ref = to_dense(Z)
     for i, b in enumerate(_local_blocks(ct, bt)):
@@ -68,10 +68,10 @@ def test_local_updates_exact_sequence(cfg1):
             assert np.allclose(rho.T @ rho, Vt.T @ Vt, atol=1e-11 * scale)
 
 
-def test_untouched_data_bitwise(cfg1):
+def test_untouched_data_bitwise(sq32):
     """Couplings, bases and nearfield outside the subtrees / b0 are unchanged
     (Section 5: only blocks touching T_t0 or T_s0 change)."""
-    p, ct, bt = cfg1
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     X = w.gaussian(ct.n, 6, 1)[ct.perm]
     addlr(Z, 0, X, X, TruncParams(1e-8, "block_rel", 64))
@@ -132,12 +132,12 @@ def test_single_block_is_eckart_young():
         assert np.count_nonzero(sig > eps * fro) == r
 
 
-def test_truncation_error_blockwise_bound(cfg1):
+def test_truncation_error_blockwise_bound(sq32):
     """After a truncated global update every admissible block keeps the
     blockwise relative error ||(Z_new - Z~)|_b||_2 <= 2 (p+1) eps ||Z~|_b||_F
     (p = depth; the constant is this build's check, the paper prints none),
     and the total error decreases with eps."""
-    p, ct, bt = cfg1
+    p, ct, bt = sq32
     base = from_csr(p["A"], ct, bt)
     X0 = w.gaussian(ct.n, 10, 31)[ct.perm] * np.linspace(1, 1e-4, 10)
     Y0 = w.gaussian(ct.n, 10, 32)[ct.perm]
@@ -156,8 +156,8 @@ def test_truncation_error_blockwise_bound(cfg1):
     assert errs[0] > errs[1] > errs[2]
 
 
-def test_const_rel_mode(cfg1):
-    p, ct, bt = cfg1
+def test_const_rel_mode(sq32):
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     X = w.gaussian(ct.n, 6, 4)[ct.perm]
     ref = to_dense(Z) + X @ X.T
@@ -165,8 +165,8 @@ def test_const_rel_mode(cfg1):
     assert _rel2(to_dense(Z), ref) < 1e-8
 
 
-def test_skip_zero_update(cfg1):
-    p, ct, bt = cfg1
+def test_skip_zero_update(sq32):
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     Z0 = Z.copy()
     assert addlr(Z, 0, np.zeros((ct.n, 3)), w.gaussian(ct.n, 3, 1), TruncParams()) is False
@@ -174,17 +174,17 @@ def test_skip_zero_update(cfg1):
     assert all(np.array_equal(Z.N[b], Z0.N[b]) for b in Z.near)
 
 
-def test_rank_cap(cfg1):
+def test_rank_cap(sq32):
     from oracle.h2 import RankCapError
-    p, ct, bt = cfg1
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     X = w.gaussian(ct.n, 8, 1)[ct.perm]
     with pytest.raises(RankCapError):
         addlr(Z, 0, X, X, TruncParams(0.0, "none", 4))
 
 
-def test_matvec_plain_definition(cfg1):
-    p, ct, bt = cfg1
+def test_matvec_plain_definition(sq32):
+    p, ct, bt = sq32
     Z = from_csr(p["A"], ct, bt)
     X = w.gaussian(ct.n, 4, 8)[ct.perm]
     addlr(Z, 0, X, X[::-1].copy(), TruncParams(0.0, "none", 64))

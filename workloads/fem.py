@@ -149,16 +149,16 @@ def gaussian(n: int, k: int, seed: int) -> np.ndarray:
 
 _CONFIGS = {
     # name: (dim, N, sigma seed or None, rhs seed)
-    "cfg1": (2, 32, None, 2),
-    "cfg2": (2, 256, 10, 11),
-    "target": (2, 512, 20, 21),
-    "cfg3": (3, 64, 30, 31),
+    "p1_square_32": (2, 32, None, 2),            # P1, 32 x 32 grid, sigma = 1
+    "p1_square_256_sigma": (2, 256, 10, 11),     # P1, 256 x 256, sigma on 8 x 8 subdomains
+    "p1_square_512_sigma": (2, 512, 20, 21),     # P1, 512 x 512, sigma on 8 x 8 subdomains
+    "q1_cube_64_sigma": (3, 64, 30, 31),         # Q1, 64^3, sigma on 4 x 4 x 4 cell blocks
 }
 
 
 def problem(name_or_side, dim: int = 2, sigma_seed: int | None = None, rhs_seed: int = 0):
     """Return dict(coords, A (CSR, original order), b, N, dim) for a named
-    configuration ('cfg1', 'cfg2', 'target', 'cfg3') or for a grid side."""
+    workload (keys of _CONFIGS) or for a grid side."""
     if isinstance(name_or_side, str):
         dim, N, sigma_seed, rhs_seed = _CONFIGS[name_or_side]
     else:
