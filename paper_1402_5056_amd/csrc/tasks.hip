@@ -1019,12 +1019,15 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
   const int ss = trans ? 0 : 1, ds = 1 - ss;
   const int lane = lane_id(), wv = wave_id();
   double fl = 0.0;   // counted by lane 0 of each wave
-  // For a subdivided block no admissible leaf sits at the level of (t, s)
-  // itself: the forward transformation of the source root and the coupling
-  // sum of the destination root are never used, and are skipped.
-  const int top = e.bkind[b] == 0 ? 1 : 0;
+  // For a subdivided block (t, s) the leaves below pair sons of t with sons
+  // of s (a leaf cluster stands for itself), so the forward transformation
+  // of a source root with sons and the coupling sum of a destination root
+  // with sons are never used and are skipped.  A root that is a leaf (the
+  // other root then has sons, in unbalanced trees) is kept.
+  const int inner = e.bkind[b] == 0 ? 1 : 0;
+  const int top_s = inner && !is_leaf(e, sr) ? 1 : 0, top_d = inner && !is_leaf(e, dr) ? 1 : 0;
   // forward transformation over the source subtree
-  for (int lv = e.nlev - 1; lv >= e.level[sr] + top; --lv) {
+  for (int lv = e.nlev - 1; lv >= e.level[sr] + top_s; --lv) {
     const int lo = dlo(e, sr, lv), hi = lo + nlevel(e, sr, lv);
     for (int c = lo + wv; c < hi; c += NWAVE) {
       const int kc = e.k[ss][c];
@@ -1061,7 +1064,7 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
   const int *idx = trans ? e.colidx : e.rowidx;
   const int *nptr = trans ? e.ncolptr : e.nrowptr;
   const int *nidx = trans ? e.ncolidx : e.nrowidx;
-  for (int lv = e.level[dr] + top; lv < e.nlev; ++lv) {
+  for (int lv = e.level[dr] + top_d; lv < e.nlev; ++lv) {
     const int lo = dlo(e, dr, lv), hi = lo + nlevel(e, dr, lv);
     for (int c = lo + wv; c < hi; c += NWAVE) {
       const int kc = e.k[ds][c];
@@ -1082,7 +1085,7 @@ __device__ void task_bapply(const DevEnv &e, const Lds &L, int b, int trans, int
           }
           if (lane == 0) fl += 2.0 * kc * ko * m;
         }
-        if (lv > e.level[dr] + top) {
+        if (lv > e.level[dr] + top_d) {
           const int pc = e.parent[c];
           const int kp = e.k[ds][pc];
           MV Ec = Eslot(e, ds, c), yp = xhslot(e.yh, pc);

@@ -119,10 +119,13 @@ def test_rank_cap_error(lib):
     assert ei.value.name == "H2_ERR_STATE"
 
 
-@pytest.mark.parametrize("N,sigma_seed,eps", [(32, None, 1e-6), (32, 3, 1e-4), (16, 5, 1e-6)])
-def test_cholesky_parity(lib, N, sigma_seed, eps):
-    print(f"case: cholesky N={N} sigma={sigma_seed} eps={eps}", flush=True)
-    leaf = 32 if N >= 32 else 8
+@pytest.mark.parametrize("N,sigma_seed,eps,leaf", [(32, None, 1e-6, 32), (32, 3, 1e-4, 32), (16, 5, 1e-6, 8),
+                                                   (24, 3, 1e-6, 16), (40, 7, 1e-5, 24)])
+def test_cholesky_parity(lib, N, sigma_seed, eps, leaf):
+    """Includes unbalanced cluster trees (leaves on two levels: 24 x 24 grid
+    with leaf 16, 40 x 40 with leaf 24), where subdivided blocks can pair a
+    leaf with a cluster that has sons."""
+    print(f"case: cholesky N={N} sigma={sigma_seed} eps={eps} leaf={leaf}", flush=True)
     p, ctx, bt, M, oc, ob = _setup(lib, N, sigma_seed=sigma_seed, leaf=leaf, lower=True)
     L = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), TruncParams(eps, "block_rel", 32))
     lib.h2_cholesky(M, lib.trunc(eps, "block_rel", 32))
@@ -158,12 +161,14 @@ def test_precond_and_pcg(lib):
     assert np.linalg.norm(p["b"] - p["A"] @ x.cpu().numpy()) / np.linalg.norm(p["b"]) < 1e-8
 
 
-def test_precond_multi_rhs(lib):
+@pytest.mark.parametrize("N,leaf", [(32, 16), (24, 16)])
+def test_precond_multi_rhs(lib, N, leaf):
     """Preconditioner with several right-hand sides (the substitution's
-    coupling sums then have more columns than ranks of some clusters)."""
-    print("case: precond nrhs=5 N=32 leaf 16", flush=True)
+    coupling sums then have more columns than ranks of some clusters); the
+    24 x 24 grid with leaf 16 has leaves on two levels."""
+    print(f"case: precond nrhs=5 N={N} leaf {leaf}", flush=True)
     torch = gpu()
-    p, ctx, bt, M, oc, ob = _setup(lib, 32, sigma_seed=5, leaf=16, lower=True)
+    p, ctx, bt, M, oc, ob = _setup(lib, N, sigma_seed=5, leaf=leaf, lower=True)
     L = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), TruncParams(1e-6, "block_rel", 32))
     lib.h2_cholesky(M, lib.trunc(1e-6, "block_rel", 32))
     r = w.gaussian(oc.n, 5, 17)
