@@ -43,6 +43,18 @@ the same factor (Section 3; Section 6, Cases 1 and 2):
     An emission is added to the enclosing temporary (truncated addition),
     to N_tr for an inadmissible target, otherwise by addlr on (t, r).
 
+tinv(c) overwrites the factor L with an approximation of L^{-1} (Remark
+"Inversion" at the end of Section 6, specialised to A_12 = 0, so the Schur
+complement is A_22 and C_12 = 0):
+    leaf c:  N_cc <- (N_cc)^{-1} (dense lower triangular inverse).
+    else:    tinv(c1); B_21 = A_21 A_11^{-1} (in place, rmul_tri);
+             tinv(c2); C_21 = -C_22 B_21 (in place, lmul_tri, then negation).
+    The products with the triangular diagonal blocks run in place by
+    recursion over the sons of the triangular factor, with the product
+    Z(t, r) += X(t, s) Y(s, r) of Section 3 (mm_n) for the off-diagonal part
+    and, for an admissible leaf, the exact result applied as a low-rank update
+    of the shared basis (as in rsolve; reading).
+
 Truncated addition of low-rank matrices (the H-matrix rule recalled at the
 end of Section 3): QR of both stacked factors, SVD of the small core, drop
 singular values <= eps * ||core||_F (block_rel), <= eps * sigma_1
@@ -238,6 +250,170 @@ class _Chol:
             U = L.basis(0, r, cache) @ L.S[b]
             self._addlr(b, U, Wp - Wc)
 
+    # ----------------------------------------------------- triangular inverse
+    def trmv(self, c, w, trans=False):
+        """L_cc w (L_cc^* w for trans) for the lower triangular diagonal block
+        (c, c): dense lower triangle on a leaf, otherwise the sons' diagonal
+        blocks and the block (c2, c1)."""
+        L, ct, bt = self.L, self.ct, self.bt
+        if ct.is_leaf(c):
+            T = np.tril(L.N[bt.find(c, c)])
+            return (T.T if trans else T) @ w
+        c1, c2 = ct.sons(c)
+        n1 = int(ct.size[c1])
+        b = bt.find(c2, c1)
+        if not trans:
+            y1 = self.trmv(c1, w[:n1])
+            y2 = self.trmv(c2, w[n1:]) + block_apply(L, b, w[:n1])
+        else:
+            y1 = self.trmv(c1, w[:n1], True) + block_apply(L, b, w[n1:], trans=True)
+            y2 = self.trmv(c2, w[n1:], True)
+        return np.concatenate([y1, y2])
+
+    def mm_n(self, t, s, r, alpha, tmp=None):
+        """Z(t, r) += alpha X(t, s) Y(s, r), X = block (t, s), Y = block
+        (s, r) used as stored (not adjoint); all three lie strictly below the
+        diagonal.  Same recursion as mm: Case 1 over s' (outer), t', r' with
+        one temporary per son pair for an admissible leaf target; Case 2
+        precedence (s,r) admissible, (t,s) admissible, (t,s) inadmissible,
+        (s,r) inadmissible."""
+        L, ct, bt = self.L, self.ct, self.bt
+        bX, bY = bt.find(t, s), bt.find(s, r)
+        if bt.kind[bX] == INNER and bt.kind[bY] == INNER:
+            triples = [(t2, s2, r2) for s2 in ct.sons_plus(s)
+                       for t2 in ct.sons_plus(t) for r2 in ct.sons_plus(r)]
+            if tmp is not None:
+                for (t2, s2, r2) in triples:
+                    self.mm_n(t2, s2, r2, alpha, tmp)
+                return
+            bZ = bt.find(t, r)
+            if bt.kind[bZ] == INNER:
+                for (t2, s2, r2) in triples:
+                    self.mm_n(t2, s2, r2, alpha)
+            elif bt.kind[bZ] == NEAR:
+                self._count("near_dense_product")
+                cache = {}
+                P = block_dense(L, bX, cache) @ block_dense(L, bY, cache)
+                L.N[bZ] = L.N[bZ] + alpha * P
+            else:
+                self._count("temp_targets")
+                pairs = [(t2, r2) for t2 in ct.sons_plus(t) for r2 in ct.sons_plus(r)]
+                temps = {p: RkTemp(ct, p[0], p[1]) for p in pairs}
+                for (t2, s2, r2) in triples:
+                    self.mm_n(t2, s2, r2, alpha, temps[(t2, r2)])
+                for p in pairs:
+                    tm = temps[p]
+                    U = np.zeros((int(ct.size[t]), tm.U.shape[1]))
+                    V = np.zeros((int(ct.size[r]), tm.V.shape[1]))
+                    a = int(ct.offset[p[0]] - ct.offset[t])
+                    c = int(ct.offset[p[1]] - ct.offset[r])
+                    U[a:a + tm.U.shape[0]] = tm.U
+                    V[c:c + tm.V.shape[0]] = tm.V
+                    self._addlr(bZ, U, V)
+            return
+        cache = {}
+        if bt.kind[bY] == ADM:          # Y = V_s S W_r^*
+            U = alpha * (block_apply(L, bX, L.basis(0, s, cache), cache=cache) @ L.S[bY])
+            V = L.basis(1, r, cache)
+        elif bt.kind[bX] == ADM:        # X = V_t S W_s^*
+            U = alpha * (L.basis(0, t, cache) @ L.S[bX])
+            V = block_apply(L, bY, L.basis(1, s, cache), trans=True, cache=cache)
+        elif bt.kind[bX] == NEAR:
+            U = alpha * L.N[bX]
+            V = block_dense(L, bY, cache).T
+        else:
+            U = alpha * block_dense(L, bX, cache)
+            V = L.N[bY].T
+        if tmp is not None:
+            self._count("temp_add")
+            tmp.add(U, V, t, r, self.tp)
+        else:
+            self._emit_block(t, r, U, V)
+
+    def rmul_tri(self, c, b):
+        """X(r, c) <- X(r, c) L_cc in place on the block b = (r, c), with the
+        diagonal block already inverted.  Sons c1, c2 of c split X into
+        [X1 X2]: X1 <- X1 L_11 + X2 L_21 (recursion, then product with the
+        untouched X2), X2 <- X2 L_22."""
+        L, ct, bt = self.L, self.ct, self.bt
+        r = int(bt.row[b])
+        if bt.kind[b] == INNER:
+            if ct.is_leaf(c):
+                for r2 in ct.sons(r):
+                    self.rmul_tri(c, bt.find(r2, c))
+                return
+            c1, c2 = ct.sons(c)
+            rs = ct.sons_plus(r)
+            for r2 in rs:
+                self.rmul_tri(c1, bt.find(r2, c1))
+            for r2 in rs:
+                self.mm_n(r2, c2, c1, 1.0)
+            for r2 in rs:
+                self.rmul_tri(c2, bt.find(r2, c2))
+        elif bt.kind[b] == NEAR:
+            L.N[b] = L.N[b] @ np.tril(L.N[bt.find(c, c)])
+        else:
+            # V_r S W_c^* L_cc = V_r S (L_cc^* W_c)^*, added as the update
+            # (V_r S)(L_cc^* W_c - W_c)^* (W_c is shared)
+            cache = {}
+            Wc = L.basis(1, c, cache)
+            Wp = self.trmv(c, Wc, trans=True)
+            self._addlr(b, L.basis(0, r, cache) @ L.S[b], Wp - Wc)
+
+    def lmul_tri(self, c, b):
+        """Y(c, r) <- L_cc Y(c, r) in place on the block b = (c, r).  Sons
+        split Y into [Y1; Y2]: Y2 <- L_22 Y2 + L_21 Y1 (recursion, then
+        product with the untouched Y1), Y1 <- L_11 Y1."""
+        L, ct, bt = self.L, self.ct, self.bt
+        r = int(bt.col[b])
+        if bt.kind[b] == INNER:
+            if ct.is_leaf(c):
+                for r2 in ct.sons(r):
+                    self.lmul_tri(c, bt.find(c, r2))
+                return
+            c1, c2 = ct.sons(c)
+            rs = ct.sons_plus(r)
+            for r2 in rs:
+                self.lmul_tri(c2, bt.find(c2, r2))
+            for r2 in rs:
+                self.mm_n(c2, c1, r2, 1.0)
+            for r2 in rs:
+                self.lmul_tri(c1, bt.find(c1, r2))
+        elif bt.kind[b] == NEAR:
+            L.N[b] = np.tril(L.N[bt.find(c, c)]) @ L.N[b]
+        else:
+            # L_cc V_c S W_r^*, added as the update (L_cc V_c - V_c)(W_r S^*)^*
+            cache = {}
+            Vc = L.basis(0, c, cache)
+            Vp = self.trmv(c, Vc)
+            self._addlr(b, Vp - Vc, L.basis(1, r, cache) @ L.S[b].T)
+
+    def neg(self, b):
+        for l in self.bt.leaves_below(b):
+            if self.bt.kind[l] == ADM:
+                self.L.S[l] = -self.L.S[l]
+            else:
+                self.L.N[l] = -self.L.N[l]
+
+    def tinv(self, c):
+        """Remark "Inversion" with A_12 = 0: the Schur complement is A_22, so
+        C_22 = A_22^{-1}, C_12 = 0, C_11 = A_11^{-1} and
+        C_21 = -C_22 (A_21 A_11^{-1}); both products overwrite the block
+        (c2, c1) in place."""
+        L, ct, bt = self.L, self.ct, self.bt
+        if ct.is_leaf(c):
+            b = bt.find(c, c)
+            self._count("leaf_trtri")
+            L.N[b] = sla.solve_triangular(np.tril(L.N[b]), np.eye(int(ct.size[c])), lower=True)
+            return
+        c1, c2 = ct.sons(c)
+        b = bt.find(c2, c1)
+        self.tinv(c1)
+        self.rmul_tri(c1, b)
+        self.tinv(c2)
+        self.lmul_tri(c2, b)
+        self.neg(b)
+
     def chol(self, t):
         L, ct, bt = self.L, self.ct, self.bt
         if ct.is_leaf(t):
@@ -260,6 +436,30 @@ def cholesky(A: H2Matrix, tp: TruncParams, stats: dict | None = None) -> H2Matri
     overwritten in place and returned."""
     _Chol(A, tp, stats).chol(0)
     return A
+
+
+def tri_invert(L: H2Matrix, tp: TruncParams, stats: dict | None = None) -> H2Matrix:
+    """Approximate inverse G ~ L^{-1} of a lower triangular factor, in place
+    (same block tree and storage; diagonal leaves hold dense lower
+    triangular inverses)."""
+    _Chol(L, tp, stats).tinv(0)
+    return L
+
+
+def tri_apply(G: H2Matrix, w: np.ndarray, trans: bool = False) -> np.ndarray:
+    """G w (or G^* w) for a lower triangular H^2-matrix, cluster order, by
+    the plain definition: sum over the stored leaves."""
+    return block_apply(G, 0, np.asarray(w, dtype=np.float64), trans=trans)
+
+
+def precond_apply_inverse(G: H2Matrix, r: np.ndarray) -> np.ndarray:
+    """z = G^* G r with G ~ L^{-1}, r and z in original index order."""
+    perm = G.ct.perm
+    rc = np.asarray(r, dtype=np.float64)[perm]
+    z = tri_apply(G, tri_apply(G, rc), trans=True)
+    out = np.empty_like(z)
+    out[perm] = z
+    return out
 
 
 def forward_solve(L: H2Matrix, w: np.ndarray) -> np.ndarray:

@@ -120,3 +120,64 @@ def test_rk_truncated_addition():
     tmp.add(U, V, s0, r, tp)
     total[:int(ct.size[s0])] += U @ V.T
     assert np.allclose(tmp.U @ tmp.V.T, total, atol=1e-12)
+
+
+# ------------------------------------------------------- triangular inverse
+# Remark "Inversion" (end of Section 6) specialised to a lower triangular
+# factor.  Pins: without truncation the result is the dense inverse of the
+# Cholesky factor (LAPACK), on balanced and unbalanced trees; one leaf is a
+# dense inverse; with truncation ||I - G L|| = O(eps); the preconditioner
+# G^* G with an exact G makes PCG converge in one step.
+
+def _inverse(p, ct, bt, eps, mode, cap):
+    from oracle.arith import tri_invert
+    tp = TruncParams(eps, mode, cap)
+    L = cholesky(from_csr(p["A"], ct, bt, lower=True), tp)
+    Ld = np.tril(to_dense(L))
+    G = tri_invert(L.copy(), tp)
+    return Ld, np.tril(to_dense(G)), G
+
+
+@pytest.mark.parametrize("N,sigma_seed,leaf", [(32, None, 32), (16, 7, 8), (24, 3, 16)])
+def test_tri_inverse_exact_equals_dense_inverse(N, sigma_seed, leaf):
+    """24 x 24 with leaf 16 has leaves on two levels (subdivided blocks that
+    pair a leaf with a cluster that has sons)."""
+    p, ct, bt = _setup(N, sigma_seed=sigma_seed, leaf=leaf)
+    Ld, Gd, _ = _inverse(p, ct, bt, 0.0, "none", 1000)
+    Ap = p["A"].toarray()[ct.perm][:, ct.perm]
+    Lref = np.linalg.cholesky(Ap)
+    Gref = sla.solve_triangular(Lref, np.eye(ct.n), lower=True)
+    assert np.linalg.norm(Gd - Gref, 2) / np.linalg.norm(Gref, 2) < 1e-12
+    assert np.linalg.norm(Gd @ Ld - np.eye(ct.n), 2) < 1e-11
+
+
+def test_tri_inverse_single_leaf():
+    p, ct, bt = _setup(6)
+    assert ct.nc == 1
+    Ld, Gd, _ = _inverse(p, ct, bt, 1e-4, "block_rel", 32)
+    assert np.allclose(Gd, np.linalg.inv(Ld), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_tri_inverse_truncated_accuracy(eps):
+    p, ct, bt = _setup(32, sigma_seed=3)
+    Ld, Gd, G = _inverse(p, ct, bt, eps, "block_rel", 64)
+    rel = np.linalg.norm(np.eye(ct.n) - Gd @ Ld, 2)
+    assert rel < 200 * eps
+    assert G.k[0].max() <= 32 and G.k[1].max() <= 32
+    # the upper triangle stays empty: zero couplings above the diagonal are
+    # not stored, diagonal leaves are lower triangular
+    assert np.all(np.triu(to_dense(G), 1) == 0.0)
+
+
+def test_precond_inverse_pcg():
+    from oracle.arith import precond_apply_inverse
+    p, ct, bt = _setup(32)
+    _, _, G = _inverse(p, ct, bt, 0.0, "none", 1000)
+    x, it, rel = pcg(p["A"], p["b"], lambda r: precond_apply_inverse(G, r))
+    assert it == 1 and rel < 1e-12
+    p, ct, bt = _setup(32, sigma_seed=3)
+    _, _, G = _inverse(p, ct, bt, 1e-4, "block_rel", 64)
+    x, it, rel = pcg(p["A"], p["b"], lambda r: precond_apply_inverse(G, r))
+    assert rel <= 1e-8 and it <= 6
+    assert power_error(p["A"], lambda r: precond_apply_inverse(G, r), ct.n) < 0.5
