@@ -87,6 +87,22 @@ const char *h2_last_error(void);
  * leaf_size: 1..H2_MAX_LEAF; dim 1..3.  Result owned by the caller. */
 h2_status h2_ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords,
                          int32_t leaf_size, h2_ctree *out);
+/* Cluster tree by domain decomposition (Section 7 uses a domain decomposition
+ * cluster strategy; the paper gives no details).  Binary, like every tree
+ * here: a domain cluster with more than leaf_size points is cut by the grid
+ * hyperplane x_d = floor((lo_d + hi_d)/2) of its longest side d (lowest axis
+ * on ties) into D1 (x_d below), D2 (x_d above) and the interface I (on the
+ * plane); its sons are the union D1+D2 and I, ordered D1, D2, I (each in its
+ * current order), and the union, if larger than leaf_size, has the domain
+ * sons D1 and D2.  Interfaces and their descendants are bisected as in
+ * h2_ctree_build; a domain whose cut leaves D1, D2 or I empty is bisected and
+ * its sons stay domains.  A block tree built on this tree makes the pairs
+ * (D1, D2), (D2, D1) of every cut admissible leaves: on a stencil that
+ * couples only points at most one grid step apart in each axis they vanish,
+ * and, the order being a nested dissection, so does the Cholesky factor, so
+ * they keep rank 0.  Arguments, result and errors as for h2_ctree_build. */
+h2_status h2_ctree_build_dd(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords,
+                            int32_t leaf_size, h2_ctree *out);
 h2_status h2_ctree_info(h2_ctree ct, int64_t *n, int64_t *nclusters, int32_t *depth);
 /* Host copies of the tree tables (each array nclusters long, perm n long);
  * any pointer may be NULL. */
@@ -96,8 +112,10 @@ h2_status h2_ctree_destroy(h2_ctree ct);
 
 /* -------------------------------------------------------------- block tree */
 /* Block tree (Def. "Block tree", Section 2) of ct x ct: (t,s) is an
- * admissible leaf iff dist^2 > 0 and max(diam^2) <= eta^2 dist^2 for the
- * integer bounding boxes; a pair of leaf clusters is an inadmissible leaf;
+ * admissible leaf iff max(diam^2) <= eta^2 dist^2 for the integer bounding
+ * boxes and the boxes are at least two grid steps apart along some axis (no
+ * stencil of reach one couples them), or (t,s) is a zero pair of a
+ * domain-decomposition tree (h2_ctree_build_dd); a pair of leaf clusters is an inadmissible leaf;
  * other pairs are split into sons+(t) x sons+(s), t' outer.  Breadth-first
  * block numbering.  The block tree keeps a reference to ct. */
 h2_status h2_btree_build(h2_ctx ctx, h2_ctree ct, double eta, h2_btree *out);

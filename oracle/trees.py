@@ -12,13 +12,32 @@ Readings of points the paper leaves open:
   ordered depth first, so every cluster is a contiguous range
   ``perm[offset : offset + size]``.
 * Admissibility (the paper names only the parameter eta, Section 7): (t, s)
-  is admissible iff dist^2(B_t, B_s) > 0 and
-  max(diam^2(B_t), diam^2(B_s)) <= eta^2 * dist^2(B_t, B_s), evaluated in
-  exact integer arithmetic on the integer bounding boxes.
+  is admissible iff max(diam^2(B_t), diam^2(B_s)) <= eta^2 * dist^2(B_t, B_s)
+  and the boxes are at least two grid steps apart along some axis (so that
+  no stencil coupling only points within one step per axis reaches across),
+  evaluated in exact integer arithmetic on the integer bounding boxes.
 * Block tree: starting from (root, root), an admissible pair is an admissible
   leaf, a pair of two leaf clusters is an inadmissible leaf, every other pair
   is subdivided into sons+(t) x sons+(s) (Section 6, Case 1), enumerated with
   t' outer.  Blocks are numbered breadth first.
+
+Domain-decomposition clustering (Section 7 uses a domain decomposition
+cluster strategy in the style of Grasedyck, Kriemann and Le Borne; the paper
+gives no details, and all trees here stay binary as Section 3 assumes):
+
+* A domain cluster with more than ``leaf_size`` indices is cut by the grid
+  hyperplane x_d = m, d its longest axis (lowest on ties) and
+  m = floor((lo[d] + hi[d]) / 2), into D1 = {x_d < m}, the interface
+  I = {x_d = m} and D2 = {x_d > m}.  Its sons are the union U = D1 u D2 and
+  I, in this order, so the indices run D1, D2, I (each stable).  U, if it
+  holds more than ``leaf_size`` indices, has the sons D1 and D2, which are
+  domain clusters again.  Interface clusters and their descendants are split
+  by geometric bisection as above.  If D1, D2 or I would be empty, the
+  domain cluster is bisected instead and both sons stay domain clusters.
+* Block tree: the pairs (D1, D2) and (D2, D1) below a split union node are
+  admissible leaves whatever eta says.  On a stencil of reach 1 the matrix
+  vanishes there, and so does its Cholesky factor in this (nested
+  dissection) order: no fill ever enters, the blocks keep rank 0.
 """
 
 from __future__ import annotations
@@ -45,6 +64,7 @@ class ClusterTree:
     lo: np.ndarray            # (nc, dim) integer bounding boxes
     hi: np.ndarray
     depth: int = 0
+    union: np.ndarray | None = None   # True: sons are two separated domains
 
     @property
     def nc(self) -> int:
@@ -87,44 +107,77 @@ class ClusterTree:
         return a0 <= a and b <= b0 and self.level[t] >= self.level[t0]
 
 
-def build_cluster_tree(coords: np.ndarray, leaf_size: int = 32) -> ClusterTree:
+DOMAIN, UNION, OTHER = 0, 1, 2
+
+
+def build_cluster_tree(coords: np.ndarray, leaf_size: int = 32, dd: bool = False) -> ClusterTree:
+    """Geometric bisection (dd=False) or domain decomposition (dd=True)."""
     coords = np.asarray(coords, dtype=np.int64)
     n, dim = coords.shape
     perm = np.arange(n, dtype=np.int64)
     offset, size, level, son0, son1, parent, lo, hi = [], [], [], [], [], [], [], []
+    role, cut = [], []
     q = deque()
 
-    def new(off, sz, lev, par):
+    def new(off, sz, lev, par, rl, ct=0):
         idx = len(offset)
         offset.append(off); size.append(sz); level.append(lev)
         son0.append(-1); son1.append(-1); parent.append(par)
+        role.append(rl); cut.append(ct)
         pts = coords[perm[off:off + sz]]
         lo.append(pts.min(axis=0)); hi.append(pts.max(axis=0))
         q.append(idx)
         return idx
 
-    new(0, n, 0, -1)
+    new(0, n, 0, -1, DOMAIN if dd else OTHER)
     while q:
         t = q.popleft()
         off, sz = offset[t], size[t]
         if sz <= leaf_size:
             continue
+        idx = perm[off:off + sz]
+        if role[t] == UNION:
+            # the father already ordered D1 before D2
+            s0 = new(off, cut[t], level[t] + 1, t, DOMAIN)
+            s1 = new(off + cut[t], sz - cut[t], level[t] + 1, t, DOMAIN)
+            son0[t], son1[t] = s0, s1
+            continue
         ext = hi[t] - lo[t]
         d = int(np.argmax(ext))
-        idx = perm[off:off + sz]
+        if role[t] == DOMAIN:
+            m = (int(lo[t][d]) + int(hi[t][d])) // 2
+            x = coords[idx, d]
+            m1, mi, m2 = x < m, x == m, x > m
+            n1, ni, n2 = int(m1.sum()), int(mi.sum()), int(m2.sum())
+            if n1 > 0 and ni > 0 and n2 > 0:
+                perm[off:off + sz] = np.concatenate([idx[m1], idx[m2], idx[mi]])
+                s0 = new(off, n1 + n2, level[t] + 1, t, UNION, n1)
+                s1 = new(off + n1 + n2, ni, level[t] + 1, t, OTHER)
+                son0[t], son1[t] = s0, s1
+                continue
         mask = 2 * coords[idx, d] <= lo[t][d] + hi[t][d]
         n0 = int(mask.sum())
         assert 0 < n0 < sz
         perm[off:off + sz] = np.concatenate([idx[mask], idx[~mask]])
-        s0 = new(off, n0, level[t] + 1, t)
-        s1 = new(off + n0, sz - n0, level[t] + 1, t)
+        rs = DOMAIN if role[t] == DOMAIN else OTHER
+        s0 = new(off, n0, level[t] + 1, t, rs)
+        s1 = new(off + n0, sz - n0, level[t] + 1, t, rs)
         son0[t], son1[t] = s0, s1
     ct = ClusterTree(n, dim, perm, np.array(offset, np.int64), np.array(size, np.int64),
                      np.array(level, np.int64), np.array(son0, np.int64),
                      np.array(son1, np.int64), np.array(parent, np.int64),
                      np.array(lo, np.int64), np.array(hi, np.int64))
     ct.depth = int(ct.level.max())
+    ct.union = (np.array(role) == UNION) & (ct.son0 >= 0)
     return ct
+
+
+def dd_zero_pair(ct: ClusterTree, t: int, s: int) -> bool:
+    """(t, s) are the two domains below one split union node."""
+    if ct.union is None or t == s:
+        return False
+    p = int(ct.parent[t])
+    return p >= 0 and p == int(ct.parent[s]) and bool(ct.union[p])
 
 
 def admissible(ct: ClusterTree, t: int, s: int, eta2: float) -> bool:
@@ -133,7 +186,7 @@ def admissible(ct: ClusterTree, t: int, s: int, eta2: float) -> bool:
     diam_s = int(((hs - ls) ** 2).sum())
     gap = np.maximum(0, np.maximum(ls - ht, lt - hs))
     dist = int((gap ** 2).sum())
-    return dist > 0 and max(diam_t, diam_s) <= eta2 * dist
+    return int(gap.max()) >= 2 and max(diam_t, diam_s) <= eta2 * dist
 
 
 @dataclass
@@ -191,7 +244,7 @@ def build_block_tree(ct: ClusterTree, eta: float = 2.0) -> BlockTree:
     while q:
         b = q.popleft()
         t, s = row[b], col[b]
-        if admissible(ct, t, s, eta2):
+        if admissible(ct, t, s, eta2) or dd_zero_pair(ct, t, s):
             kind[b] = ADM
         elif ct.is_leaf(t) and ct.is_leaf(s):
             kind[b] = NEAR

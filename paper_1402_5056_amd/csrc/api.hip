@@ -90,22 +90,31 @@ struct h2_ctree_s {
   int dim = 0, leaf = 0, nc = 0, depth = 0, nlev = 0;
   std::vector<int64_t> perm;
   std::vector<int> offset, size, level, son0, son1, parent;
+  std::vector<char> uni;         // 1: the sons are two domains separated by an interface
   std::vector<int64_t> lo, hi;   // nc x dim
   std::vector<int> desc_lo, desc_hi;
   Dev<int64_t> d_perm;
   Dev<int> d_offset, d_size, d_level, d_son0, d_son1, d_parent, d_desc_lo, d_desc_hi;
 };
 
-static void build_ctree(h2_ctree_s &ct, const int32_t *coords) {
+// Roles of the clusters of a domain-decomposition tree: a domain is cut by an
+// interface hyperplane, a union holds the two domains of one cut, every other
+// cluster (interfaces and their descendants) is bisected.
+enum { ROLE_DOMAIN = 0, ROLE_UNION = 1, ROLE_OTHER = 2 };
+
+static void build_ctree(h2_ctree_s &ct, const int32_t *coords, bool dd) {
   const int64_t n = ct.n;
   const int dim = ct.dim;
   ct.perm.resize(n);
   for (int64_t i = 0; i < n; ++i) ct.perm[i] = i;
+  std::vector<char> role;
+  std::vector<int> cut;
   std::deque<int> q;
-  auto add = [&](int off, int sz, int lev, int par) {
+  auto add = [&](int off, int sz, int lev, int par, char rl, int ct_cut) {
     const int id = (int)ct.offset.size();
     ct.offset.push_back(off); ct.size.push_back(sz); ct.level.push_back(lev);
     ct.son0.push_back(-1); ct.son1.push_back(-1); ct.parent.push_back(par);
+    role.push_back(rl); cut.push_back(ct_cut);
     for (int d = 0; d < dim; ++d) {
       int64_t a = INT64_MAX, b = INT64_MIN;
       for (int i = off; i < off + sz; ++i) {
@@ -117,12 +126,20 @@ static void build_ctree(h2_ctree_s &ct, const int32_t *coords) {
     q.push_back(id);
     return id;
   };
-  add(0, (int)n, 0, -1);
+  add(0, (int)n, 0, -1, dd ? ROLE_DOMAIN : ROLE_OTHER, 0);
+  std::vector<int64_t> tmp;
   while (!q.empty()) {
     const int t = q.front();
     q.pop_front();
     const int off = ct.offset[t], sz = ct.size[t];
     if (sz <= ct.leaf) continue;
+    if (role[t] == ROLE_UNION) {
+      // the father already placed the first domain before the second
+      const int s0 = add(off, cut[t], ct.level[t] + 1, t, ROLE_DOMAIN, 0);
+      const int s1 = add(off + cut[t], sz - cut[t], ct.level[t] + 1, t, ROLE_DOMAIN, 0);
+      ct.son0[t] = s0; ct.son1[t] = s1;
+      continue;
+    }
     int dsplit = 0;
     int64_t best = -1;
     for (int d = 0; d < dim; ++d) {
@@ -131,15 +148,38 @@ static void build_ctree(h2_ctree_s &ct, const int32_t *coords) {
     }
     const int64_t mid2 = ct.lo[t * dim + dsplit] + ct.hi[t * dim + dsplit];
     auto first = ct.perm.begin() + off;
+    if (role[t] == ROLE_DOMAIN) {
+      // interface hyperplane x_d = floor((lo+hi)/2): order D1 (below), D2 (above), I
+      const int64_t m = mid2 >= 0 ? mid2 / 2 : -((-mid2 + 1) / 2);
+      int n1 = 0, ni = 0, n2 = 0;
+      for (int i = 0; i < sz; ++i) {
+        const int64_t x = coords[first[i] * dim + dsplit];
+        n1 += x < m; ni += x == m; n2 += x > m;
+      }
+      if (n1 > 0 && ni > 0 && n2 > 0) {
+        tmp.clear();
+        for (int i = 0; i < sz; ++i) if (coords[first[i] * dim + dsplit] < m) tmp.push_back(first[i]);
+        for (int i = 0; i < sz; ++i) if (coords[first[i] * dim + dsplit] > m) tmp.push_back(first[i]);
+        for (int i = 0; i < sz; ++i) if (coords[first[i] * dim + dsplit] == m) tmp.push_back(first[i]);
+        std::copy(tmp.begin(), tmp.end(), first);
+        const int s0 = add(off, n1 + n2, ct.level[t] + 1, t, ROLE_UNION, n1);
+        const int s1 = add(off + n1 + n2, ni, ct.level[t] + 1, t, ROLE_OTHER, 0);
+        ct.son0[t] = s0; ct.son1[t] = s1;
+        continue;
+      }
+    }
     auto mid = std::stable_partition(first, first + sz, [&](int64_t idx) {
       return 2 * (int64_t)coords[idx * dim + dsplit] <= mid2;
     });
     const int n0 = (int)(mid - first);
     if (n0 <= 0 || n0 >= sz) throw H2Error(H2_ERR_ARG, "cluster cannot be split (duplicate points?)");
-    const int s0 = add(off, n0, ct.level[t] + 1, t);
-    const int s1 = add(off + n0, sz - n0, ct.level[t] + 1, t);
+    const char rs = role[t] == ROLE_DOMAIN ? ROLE_DOMAIN : ROLE_OTHER;
+    const int s0 = add(off, n0, ct.level[t] + 1, t, rs, 0);
+    const int s1 = add(off + n0, sz - n0, ct.level[t] + 1, t, rs, 0);
     ct.son0[t] = s0; ct.son1[t] = s1;
   }
+  ct.uni.assign(ct.offset.size(), 0);
+  for (size_t t = 0; t < ct.offset.size(); ++t) ct.uni[t] = role[t] == ROLE_UNION && ct.son0[t] >= 0;
   ct.nc = (int)ct.offset.size();
   ct.depth = *std::max_element(ct.level.begin(), ct.level.end());
   ct.nlev = ct.depth + 1;
@@ -179,7 +219,7 @@ struct h2_btree_s {
 };
 
 static bool admissible(const h2_ctree_s &ct, int t, int s, double eta2) {
-  int64_t dt = 0, ds = 0, dist = 0;
+  int64_t dt = 0, ds = 0, dist = 0, gmax = 0;
   for (int d = 0; d < ct.dim; ++d) {
     const int64_t lt = ct.lo[t * ct.dim + d], ht = ct.hi[t * ct.dim + d];
     const int64_t ls = ct.lo[s * ct.dim + d], hs = ct.hi[s * ct.dim + d];
@@ -187,8 +227,13 @@ static bool admissible(const h2_ctree_s &ct, int t, int s, double eta2) {
     ds += (hs - ls) * (hs - ls);
     const int64_t g = std::max<int64_t>(0, std::max(ls - ht, lt - hs));
     dist += g * g;
+    gmax = std::max(gmax, g);
   }
-  return dist > 0 && (double)std::max(dt, ds) <= eta2 * (double)dist;
+  // at least two grid steps apart along some axis: no reach-one stencil couples the boxes
+  if (gmax >= 2 && (double)std::max(dt, ds) <= eta2 * (double)dist) return true;
+  // the two domains below one cut: the matrix and its Cholesky factor vanish there
+  const int p = ct.parent[t];
+  return t != s && p >= 0 && p == ct.parent[s] && ct.uni[p];
 }
 
 static void build_btree(h2_btree_s &bt) {
@@ -686,8 +731,8 @@ h2_status h2_ctx_synchronize(h2_ctx ctx) {
   });
 }
 
-h2_status h2_ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords, int32_t leaf_size,
-                         h2_ctree *out) {
+static h2_status ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords,
+                             int32_t leaf_size, bool dd, h2_ctree *out) {
   return guarded([&] {
     REQUIRE(ctx && coords && out, "null argument");
     REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
@@ -695,9 +740,19 @@ h2_status h2_ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coor
     REQUIRE(leaf_size >= 1 && leaf_size <= H2_MAX_LEAF, "leaf_size must be 1..H2_MAX_LEAF");
     auto ct = std::make_unique<h2_ctree_s>();
     ct->ctx = ctx; ct->n = n; ct->dim = dim; ct->leaf = leaf_size;
-    build_ctree(*ct, coords);
+    build_ctree(*ct, coords, dd);
     *out = ct.release();
   });
+}
+
+h2_status h2_ctree_build(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords, int32_t leaf_size,
+                         h2_ctree *out) {
+  return ctree_build(ctx, dim, n, coords, leaf_size, false, out);
+}
+
+h2_status h2_ctree_build_dd(h2_ctx ctx, int32_t dim, int64_t n, const int32_t *coords,
+                            int32_t leaf_size, h2_ctree *out) {
+  return ctree_build(ctx, dim, n, coords, leaf_size, true, out);
 }
 
 h2_status h2_ctree_info(h2_ctree ct, int64_t *n, int64_t *nclusters, int32_t *depth) {

@@ -67,6 +67,7 @@ _SIG = {
     "h2_ctx_destroy": [_vp],
     "h2_ctx_synchronize": [_vp],
     "h2_ctree_build": [_vp, _i32, _i64, _vp, _i32, _P(_vp)],
+    "h2_ctree_build_dd": [_vp, _i32, _i64, _vp, _i32, _P(_vp)],
     "h2_ctree_info": [_vp, _P(_i64), _P(_i64), _P(_i32)],
     "h2_ctree_export": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "h2_ctree_destroy": [_vp],
@@ -193,6 +194,14 @@ def h2_ctree_build(ctx: Ctx, coords: np.ndarray, leaf_size: int = 32) -> CTree:
     c = _np(coords, np.int32)
     h = _vp()
     _check(_lib.h2_ctree_build(ctx.h, c.shape[1], c.shape[0], c.ctypes.data, int(leaf_size), C.byref(h)))
+    return CTree(h.value, keep=(ctx,))
+
+
+def h2_ctree_build_dd(ctx: Ctx, coords: np.ndarray, leaf_size: int = 32) -> CTree:
+    c = _np(coords, np.int32)
+    h = _vp()
+    _check(_lib.h2_ctree_build_dd(ctx.h, c.shape[1], c.shape[0], c.ctypes.data, int(leaf_size),
+                                  C.byref(h)))
     return CTree(h.value, keep=(ctx,))
 
 

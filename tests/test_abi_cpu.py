@@ -58,6 +58,24 @@ def test_trees_bit_exact_vs_oracle(N, dim, leaf, eta):
     assert h2lr.h2_btree_find(bt, 0, 5) == -1
 
 
+@pytest.mark.parametrize("N,dim,leaf,eta", [(32, 2, 32, 4.0), (256, 2, 32, 4.0), (29, 2, 7, 2.0),
+                                             (16, 3, 32, 2.0), (13, 3, 8, 4.0), (45, 2, 16, 4.0)])
+def test_dd_trees_bit_exact_vs_oracle(N, dim, leaf, eta):
+    from paper_1402_5056_amd import h2lr
+    ctx = h2lr.h2_ctx_create(-1)
+    c = w.grid_points(N, dim)
+    ct = h2lr.h2_ctree_build_dd(ctx, c, leaf)
+    bt = h2lr.h2_btree_build(ctx, ct, eta)
+    oc = build_cluster_tree(c, leaf, dd=True)
+    ob = build_block_tree(oc, eta)
+    e = h2lr.h2_ctree_export(ct)
+    for k in ("perm", "offset", "size", "level", "son0", "son1", "parent"):
+        assert np.array_equal(e[k], getattr(oc, k)), k
+    b = h2lr.h2_btree_export(bt)
+    for k in ("row", "col", "kind", "parent"):
+        assert np.array_equal(b[k], getattr(ob, k)), k
+
+
 def test_abi_argument_errors():
     from paper_1402_5056_amd import h2lr
     ctx = h2lr.h2_ctx_create(-1)

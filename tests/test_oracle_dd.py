@@ -1,0 +1,128 @@
+"""Pins of the domain-decomposition cluster tree (Section 7 clusters the
+model problem by domain decomposition) and of the H^2 Cholesky factorisation
+on it.  The tree is pinned by what nested dissection fixes: the interface
+separates the two domains of every cut, the matrix vanishes between them,
+and the exact (LAPACK) Cholesky factor of the reordered matrix has exactly
+zero entries there, so the zero blocks of the block tree never fill."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.arith import cholesky, precond_apply
+from oracle.h2 import TruncParams, from_csr, to_dense
+from oracle.solve import pcg
+from oracle.trees import ADM, NEAR, admissible, build_block_tree, build_cluster_tree, dd_zero_pair
+
+
+def _dd(N, dim=2, leaf=32, eta=4.0):
+    ct = build_cluster_tree(w.grid_points(N, dim), leaf, dd=True)
+    return ct, build_block_tree(ct, eta)
+
+
+def _matrix(N, dim, seed):
+    if dim == 2:
+        return w.fem2d_p1(N, w.sigma_subdomains_2d(N, 8, seed))
+    return w.fem3d_q1(N, w.sigma_blocks_3d(N, 4, seed))
+
+
+@pytest.mark.parametrize("N,dim,leaf", [(24, 2, 8), (33, 2, 32), (64, 2, 32), (8, 3, 8), (12, 3, 32)])
+def test_dd_tree_structure(N, dim, leaf):
+    ct, bt = _dd(N, dim, leaf)
+    pts = w.grid_points(N, dim)
+    assert sorted(ct.perm.tolist()) == list(range(ct.n))
+    nunion = 0
+    for t in range(ct.nc):
+        if ct.is_leaf(t):
+            assert ct.size[t] <= leaf
+            continue
+        s0, s1 = ct.sons(t)
+        a, b = ct.rng(t)
+        assert ct.rng(s0)[0] == a and ct.rng(s0)[1] == ct.rng(s1)[0] and ct.rng(s1)[1] == b
+        if ct.union[t]:
+            nunion += 1
+            # the sibling of a union is the interface: one plane x_d = m
+            # with the first domain strictly below and the second above
+            f = int(ct.parent[t])
+            assert ct.sons(f)[0] == t
+            I = pts[ct.perm[slice(*ct.rng(ct.sons(f)[1]))]]
+            D1 = pts[ct.perm[slice(*ct.rng(s0))]]
+            D2 = pts[ct.perm[slice(*ct.rng(s1))]]
+            planes = [d for d in range(dim) if (I[:, d] == I[0, d]).all()
+                      and D1[:, d].max() < I[0, d] < D2[:, d].min()]
+            assert planes, t
+    assert nunion > 0
+    # block leaves still partition I x I exactly once
+    cover = np.zeros((ct.n, ct.n), np.int64)
+    nzero = 0
+    for b in range(bt.nb):
+        if bt.kind[b] == 0:
+            continue
+        t, s = int(bt.row[b]), int(bt.col[b])
+        cover[slice(*ct.rng(t)), slice(*ct.rng(s))] += 1
+        if bt.kind[b] == ADM and not admissible(ct, t, s, 16.0):
+            assert dd_zero_pair(ct, t, s)
+            nzero += 1
+        if bt.kind[b] == NEAR:
+            assert ct.is_leaf(t) and ct.is_leaf(s)
+    assert (cover == 1).all()
+    assert nzero > 0
+
+
+@pytest.mark.parametrize("N,dim,seed", [(24, 2, 3), (40, 2, None), (8, 3, 5), (12, 3, None)])
+def test_dd_zero_blocks_have_no_fill(N, dim, seed):
+    """A and its exact Cholesky factor (LAPACK) vanish on every admissible
+    leaf of the DD block tree; the zero pairs are exactly zero in L."""
+    ct, bt = _dd(N, dim, 8 if N < 30 else 32)
+    A = _matrix(N, dim, seed).toarray()[ct.perm][:, ct.perm]
+    L = np.linalg.cholesky(A)
+    checked = 0
+    for b in range(bt.nb):
+        t, s = int(bt.row[b]), int(bt.col[b])
+        if bt.kind[b] != ADM:
+            continue
+        assert not A[slice(*ct.rng(t)), slice(*ct.rng(s))].any()
+        if dd_zero_pair(ct, t, s) and bt.is_lower(b):
+            assert not L[slice(*ct.rng(t)), slice(*ct.rng(s))].any()
+            checked += 1
+    assert checked > 0
+
+
+def test_bisection_tree_has_fill_where_dd_has_none():
+    """Plant check for the test above: in bisection order the factor fills
+    the block between the two halves of the root."""
+    ct = build_cluster_tree(w.grid_points(24, 2), 8)
+    A = _matrix(24, 2, 3).toarray()[ct.perm][:, ct.perm]
+    L = np.linalg.cholesky(A)
+    s0, s1 = ct.sons(0)
+    assert np.abs(L[slice(*ct.rng(s1)), slice(*ct.rng(s0))]).max() > 1e-3
+
+
+@pytest.mark.parametrize("N,dim,leaf,seed", [(24, 2, 8, 3), (33, 2, 32, None), (8, 3, 8, 5)])
+def test_dd_cholesky_exact_equals_lapack(N, dim, leaf, seed):
+    ct, bt = _dd(N, dim, leaf)
+    A = _matrix(N, dim, seed)
+    L = cholesky(from_csr(A, ct, bt, lower=True), TruncParams(0.0, "none", 1000))
+    D = np.tril(to_dense(L))
+    Lref = np.linalg.cholesky(A.toarray()[ct.perm][:, ct.perm])
+    assert np.linalg.norm(D - Lref, 2) / np.linalg.norm(Lref, 2) < 1e-13
+    for b in L.adm:
+        t, s = int(bt.row[b]), int(bt.col[b])
+        if dd_zero_pair(ct, t, s):
+            assert L.S[b].size == 0 or not L.S[b].any()
+
+
+def test_dd_cholesky_truncated_preconditioner():
+    """Truncated factor on the DD tree: ||A - LL*|| / ||A|| = O(eps) and PCG
+    reaches 1e-8 in a few steps (Table 1 reports m = 3)."""
+    N = 48
+    ct, bt = _dd(N, 2, 32)
+    A = _matrix(N, 2, None)
+    eps = 50.0 / N ** 2
+    L = cholesky(from_csr(A, ct, bt, lower=True), TruncParams(eps, "block_rel", 32))
+    Ap = A.toarray()[ct.perm][:, ct.perm]
+    D = np.tril(to_dense(L))
+    assert np.linalg.norm(Ap - D @ D.T, 2) / np.linalg.norm(Ap, 2) < 50 * eps
+    b = w.gaussian(ct.n, 1, 9)[:, 0]
+    x, it, rel = pcg(A, b, lambda r: precond_apply(L, r))
+    assert it <= 6 and rel <= 1e-8
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) < 1e-7

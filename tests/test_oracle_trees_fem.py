@@ -137,10 +137,27 @@ def test_fem_far_blocks_vanish():
 
 
 def test_nonzero_far_block_rejected():
-    """Q1 on a 12^3 grid with leaf 32 couples an admissible block: rejected."""
+    """A matrix with a coupling inside an admissible block is rejected."""
     from oracle.h2 import from_csr
+    pb = w.problem(32, dim=2, sigma_seed=4)
+    ct = build_cluster_tree(pb["coords"], 32)
+    bt = build_block_tree(ct, 2.0)
+    b = int(np.flatnonzero(bt.kind == ADM)[0])
+    i = int(ct.perm[ct.offset[bt.row[b]]])
+    j = int(ct.perm[ct.offset[bt.col[b]]])
+    A = pb["A"].tolil()
+    A[i, j] = A[j, i] = -0.5
+    with pytest.raises(ValueError):
+        from_csr(A.tocsr(), ct, bt)
+
+
+def test_stencil_neighbours_never_admissible():
+    """Clusters one grid step apart are never admissible, whatever eta: the
+    Q1 stencil on a 12^3 grid with leaf 32 reaches across such a pair."""
     pb = w.problem(12, dim=3, sigma_seed=4)
     ct = build_cluster_tree(pb["coords"], 32)
     bt = build_block_tree(ct, 2.0)
-    with pytest.raises(ValueError):
-        from_csr(pb["A"], ct, bt)
+    Ap = abs(pb["A"]).toarray()[ct.perm][:, ct.perm]
+    for b in np.flatnonzero(bt.kind == ADM):
+        t, s = int(bt.row[b]), int(bt.col[b])
+        assert not Ap[slice(*ct.rng(t)), slice(*ct.rng(s))].any()
