@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--sigma-seed", type=str, default="10",
                     help="seed of the piecewise-constant coefficient, or 'none' for sigma = 1")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--precond", choices=("substitution", "inverse"), default="substitution",
+                    help="preconditioner: substitutions with the factor L, or products with "
+                         "G ~ L^{-1} formed by the triangular inversion after the factorisation")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sides", type=str, default="64,128",
                     help="grid sides the oracle is timed on (bounded sample)")
@@ -153,10 +156,23 @@ def main():
     x = torch.zeros_like(b)
     tr = h2lr.trunc(args.eps, "block_rel", 32)
 
+    inverse = args.precond == "inverse"
+    inv_info = {}
+
     def step(evs):
         h2lr.h2_mat_assign(L, A0)
         evs[0].record(stream)
         h2lr.h2_cholesky(L, tr)
+        evs[3].record(stream)
+        if inverse:
+            # h2_cholesky returns after its device work has finished; the
+            # counters of the factor are read here (two small copies) so that
+            # the inversion is not run a second time for them
+            inv_info["chol_flops"] = h2lr.h2_mat_flops(L, reset=True)
+            inv_info["stats"] = h2lr.h2_mat_stats(L)
+            print("[bench]   factorisation done, inverting", file=sys.stderr, flush=True)
+            h2lr.h2_tri_invert(L, tr)
+            inv_info["inv_flops"] = h2lr.h2_mat_flops(L, reset=True)
         evs[1].record(stream)
         it, rel, ok = h2lr.h2_pcg(csr, L, b, x, args.rtol, 500)
         evs[2].record(stream)
@@ -166,11 +182,11 @@ def main():
 
     print(f"[bench] n={n}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
-        step([torch.cuda.Event(enable_timing=True) for _ in range(3)])
+        step([torch.cuda.Event(enable_timing=True) for _ in range(4)])
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
     h2lr.h2_mat_flops(L, reset=True)
     torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     flops = []
     iters = []
     t0 = time.perf_counter()
@@ -182,19 +198,26 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     setup_ms = [e[0].elapsed_time(e[1]) for e in events]
+    chol_ms = [e[0].elapsed_time(e[3]) for e in events]
     solve_ms = [e[1].elapsed_time(e[2]) for e in events]
     step_ms = sorted(s + v for s, v in zip(setup_ms, solve_ms))
     wall = t1 - t0
     # flops of the factorisation alone (the PCG solve adds substitution flops)
     xres = x.cpu().numpy()
     true_rel = float(np.linalg.norm(p["b"] - p["A"] @ xres) / np.linalg.norm(p["b"]))
-    h2lr.h2_mat_flops(L, reset=True)
-    h2lr.h2_mat_assign(L, A0)
-    h2lr.h2_cholesky(L, tr)
-    chol_flops = h2lr.h2_mat_flops(L, reset=True)
+    if inverse:
+        chol_flops = inv_info["chol_flops"]
+        inv_flops = inv_info["inv_flops"]
+        stored, kr, kc = inv_info["stats"]
+    else:
+        h2lr.h2_mat_flops(L, reset=True)
+        h2lr.h2_mat_assign(L, A0)
+        h2lr.h2_cholesky(L, tr)
+        chol_flops = h2lr.h2_mat_flops(L, reset=True)
+        stored, kr, kc = h2lr.h2_mat_stats(L)
     setup_s = float(np.median(setup_ms)) / 1e3
-    achieved_tflops = chol_flops / setup_s / 1e12
-    stored, kr, kc = h2lr.h2_mat_stats(L)
+    chol_s = float(np.median(chol_ms)) / 1e3
+    achieved_tflops = chol_flops / chol_s / 1e12
 
     out = {
         "metric": "H²-LR setup sec & solves/sec to 1e-8 residual, FP64 vs mixed; p50/p99 latency",
@@ -215,10 +238,14 @@ def main():
                                + (", domain-decomposition" if args.cluster == "dd" else
                                   ", geometric-bisection")
                                + f" cluster tree leaf 32, eta {args.eta:g}, "
-                               f"block-relative eps {args.eps}, H2-Cholesky + PCG 1 Gaussian RHS "
-                               f"to {args.rtol}",
+                               f"block-relative eps {args.eps}, H2-Cholesky"
+                               + (" + triangular inverse" if inverse else "")
+                               + f" + PCG 1 Gaussian RHS to {args.rtol}",
                    "n": n, "precision": "fp64", "parallelism": "1 GPU"},
         "setup_s": setup_s,
+        "cholesky_s": chol_s,
+        "inverse_s": (setup_s - chol_s) if inverse else None,
+        "precond": args.precond,
         "solve_s": float(np.median(solve_ms)) / 1e3,
         "solves_per_s": 1e3 / float(np.median(solve_ms)),
         "pcg_iters": iters,
@@ -238,6 +265,11 @@ def main():
             "flops_per_launch": chol_flops,
         },
     }
+    if inverse:
+        out["inverse_flops"] = inv_flops
+        g_stored, g_kr, g_kc = h2lr.h2_mat_stats(L)    # L holds G ~ L^{-1} now
+        out["inverse_mem_per_dof_kb"] = g_stored * 8.0 / n / 1024.0
+        out["inverse_max_rank"] = [g_kr, g_kc]
     if args.trace:
         # one more factorisation with the device counters on (not part of the timed steps)
         h2lr.h2_mat_assign(L, A0)

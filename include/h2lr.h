@@ -193,8 +193,22 @@ h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, doub
  * H2_ERR_RANK_CAP; the matrix is then poisoned. */
 h2_status h2_cholesky(h2_mat a, const h2_trunc *tr);
 
+/* In-place approximate inverse G ~ L^{-1} of a Cholesky factor made by
+ * h2_cholesky (the inversion remark at the end of Section 6, with the upper
+ * off-diagonal block zero: C_11 = L_11^{-1}, C_22 = L_22^{-1},
+ * C_21 = -C_22 L_21 C_11, the products by the Section 3 recursion with local
+ * low-rank updates).  G keeps the block structure of L; its diagonal leaves
+ * hold dense lower triangular inverses (zero above the diagonal).  After
+ * the call h2_precond and h2_pcg apply G^* G, and h2_matvec applies G.
+ * Fails with H2_ERR_RANK_CAP (matrix then poisoned), H2_ERR_ARG if the
+ * matrix is not lower-stored or already inverted. */
+h2_status h2_tri_invert(h2_mat l, const h2_trunc *tr);
+/* *inverse = 1 if h2_tri_invert has turned the matrix into G ~ L^{-1}. */
+h2_status h2_mat_is_inverse(h2_mat m, int32_t *inverse);
+
 /* z = (L L^*)^{-1} r by forward and backward substitution with the factor
- * (Section 3, block forward substitution with vector right-hand sides).
+ * (Section 3, block forward substitution with vector right-hand sides), or
+ * z = G^* G r by two H^2 matrix-vector products after h2_tri_invert.
  * r, z: device, n x nrhs, original order; r and z may alias. */
 h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs);
 
@@ -207,7 +221,7 @@ h2_status h2_csr_destroy(h2_csr a);
 h2_status h2_spmv(h2_csr a, const double *x, double *y);
 
 /* Preconditioned conjugate gradients (Section 1; stopping rule of Section 7)
- * for A x = b with preconditioner (L L^*)^{-1}: x0 = 0, stop when the
+ * for A x = b with preconditioner (L L^*)^{-1} (G^* G after h2_tri_invert): x0 = 0, stop when the
  * recursive residual satisfies ||r||_2 <= rtol ||b||_2.  b, x: device,
  * length n, original order.  iters: products with A performed; relres: final
  * ||r||/||b||.  Returns H2_ERR_NOT_CONVERGED if maxit is reached. */

@@ -301,7 +301,8 @@ struct h2_mat_s {
   Dev<DevEnv> d_env;          // device copy of env read by the interpreter
   DevEnv env_uploaded{};
   bool env_valid = false;
-  TaskList chol, prec;
+  TaskList chol, prec, tinv, prec_inv;
+  bool inverse = false;   // holds G ~ L^{-1} (h2_tri_invert) instead of a factor L
   DevEnv env{};
 };
 
@@ -604,6 +605,172 @@ struct Planner {
     }
   }
 
+  // Z(t, r) += alpha X(t, s) Y(s, r) with X = block (t, s) and Y = block
+  // (s, r) of a lower triangular matrix, all three strictly below the
+  // diagonal: the recursion of mm with the second factor used as stored
+  // instead of transposed.
+  void mm_n(int t, int s, int r, double alpha, int tmp, int tT, int rT) {
+    const int bX = find(t, s), bY = find(s, r);
+    if (bt.kind[bX] == 0 && bt.kind[bY] == 0) {
+      const auto ts = sons_plus(t), ss = sons_plus(s), rs = sons_plus(r);
+      if (tmp >= 0) {
+        for (int s2 : ss) for (int t2 : ts) for (int r2 : rs) mm_n(t2, s2, r2, alpha, tmp, tT, rT);
+        return;
+      }
+      const int bZ = find(t, r);
+      if (bt.kind[bZ] == 0) {
+        for (int s2 : ss) for (int t2 : ts) for (int r2 : rs) mm_n(t2, s2, r2, alpha, -1, 0, 0);
+      } else if (bt.kind[bZ] == 2) {
+        const int ns = ct.size[s];
+        for (int c0 = 0; c0 < ns; c0 += BC) {
+          const int nc = std::min(BC, ns - c0);
+          emit(OP_IDENT, s, B_I, c0, nc);
+          bapply(bX, 0, B_I, B_A, 1.0, 0.0);
+          bapply(bY, 1, B_I, B_B, 1.0, 0.0);
+          emit(OP_NEAR_ADD, bZ, B_A, B_B, 0, 0, 0, 0, 0, alpha);
+        }
+      } else {
+        std::vector<std::pair<int, int>> pairs;
+        for (int t2 : ts) for (int r2 : rs) pairs.push_back({t2, r2});
+        for (size_t p = 0; p < pairs.size(); ++p) emit(OP_TEMP_INIT, TU((int)p), TV((int)p), t, r);
+        for (int s2 : ss)
+          for (int t2 : ts)
+            for (int r2 : rs) {
+              int p = 0;
+              while (pairs[p].first != t2 || pairs[p].second != r2) ++p;
+              mm_n(t2, s2, r2, alpha, p, t2, r2);
+            }
+        for (size_t p = 0; p < pairs.size(); ++p) addlr(bZ, TU((int)p), TV((int)p));
+      }
+      return;
+    }
+    if (bt.kind[bY] == 1) {          // Y = V_s S W_r^*: U = alpha (X V_s) S, V = W_r
+      emit(OP_EXPAND, 0, s, B_W);
+      bapply(bX, 0, B_W, B_A, 1.0, 0.0);
+      emit(OP_RMUL_S, B_A, B_U, bY, 0, t, 0, 0, 0, alpha);
+      emit(OP_EXPAND, 1, r, B_V);
+    } else if (bt.kind[bX] == 1) {   // X = V_t S W_s^*: U = alpha V_t S, V = Y^* W_s
+      emit(OP_EXPAND, 0, t, B_A);
+      emit(OP_RMUL_S, B_A, B_U, bX, 0, t, 0, 0, 0, alpha);
+      emit(OP_EXPAND, 1, s, B_W);
+      bapply(bY, 1, B_W, B_V, 1.0, 0.0);
+    } else if (bt.kind[bX] == 2) {   // U = alpha N_X, V = Y^* expanded
+      emit(OP_COPY_NEAR, bX, B_U, 0, 0, 0, 0, 0, 0, alpha);
+      emit(OP_IDENT, s, B_I, 0, ct.size[s]);
+      bapply(bY, 1, B_I, B_V, 1.0, 0.0);
+    } else {                         // U = alpha X expanded, V = N_Y^*
+      emit(OP_IDENT, s, B_I, 0, ct.size[s]);
+      bapply(bX, 0, B_I, B_U, alpha, 0.0);
+      emit(OP_COPY_NEAR, bY, B_V, 1, 0, 0, 0, 0, 0, 1.0);
+    }
+    if (tmp >= 0) {
+      emit(OP_TEMP_ADD, TU(tmp), TV(tmp), t, r, B_U, B_V, tT, rT);
+    } else {
+      const int bZ = find(t, r);
+      if (bt.kind[bZ] == 2) emit(OP_NEAR_ADD, bZ, B_U, B_V, 0, 0, 0, 0, 0, 1.0);
+      else addlr(bZ, B_U, B_V);
+    }
+  }
+
+  // buf|_c <- G_cc buf|_c (trans: G_cc^* buf|_c) in place, G lower
+  // triangular: dense lower triangle on a leaf, otherwise the sons' diagonal
+  // blocks and the block (c2, c1); the part that is read later is updated
+  // last.
+  void trmv(int c, int buf, int trans) {
+    if (leaf(c)) { emit(OP_TRMV, find(c, c), buf, trans); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    if (!trans) {
+      trmv(c2, buf, 0);
+      bapply(find(c2, c1), 0, buf, buf, 1.0, 1.0);
+      trmv(c1, buf, 0);
+    } else {
+      trmv(c1, buf, 1);
+      bapply(find(c2, c1), 1, buf, buf, 1.0, 1.0);
+      trmv(c2, buf, 1);
+    }
+  }
+
+  // X(r, c) <- X(r, c) G_cc in place on block b = (r, c), the diagonal
+  // block (c, c) already inverted.  Sons c1, c2 of c split X into [X1 X2]:
+  // X1 <- X1 G_11, X1 += X2 G_21 (X2 still untouched), X2 <- X2 G_22.
+  void rmul_tri(int c, int b) {
+    const int r = bt.row[b];
+    if (bt.kind[b] == 0) {
+      if (leaf(c)) {
+        for (int r2 : sons_plus(r)) rmul_tri(c, find(r2, c));
+        return;
+      }
+      const int c1 = ct.son0[c], c2 = ct.son1[c];
+      const auto rs = sons_plus(r);
+      for (int r2 : rs) rmul_tri(c1, find(r2, c1));
+      for (int r2 : rs) mm_n(r2, c2, c1, 1.0, -1, 0, 0);
+      for (int r2 : rs) rmul_tri(c2, find(r2, c2));
+    } else if (bt.kind[b] == 2) {
+      emit(OP_NEAR_TRMUL, b, find(c, c), 1);          // N_b <- N_b G_cc
+    } else {
+      // V_r S W_c^* G_cc = V_r S (G_cc^* W_c)^*, added as the update
+      // (V_r S)(G_cc^* W_c - W_c)^* because W_c is shared
+      emit(OP_EXPAND, 1, c, B_W);
+      emit(OP_COPY, B_W, B_WP, c);
+      trmv(c, B_WP, 1);
+      emit(OP_SUB, B_WP, B_W, B_V, c);
+      emit(OP_EXPAND, 0, r, B_A);
+      emit(OP_RMUL_S, B_A, B_U, b, 0, r, 0, 0, 0, 1.0);
+      addlr(b, B_U, B_V);
+    }
+  }
+
+  // Y(c, r) <- G_cc Y(c, r) in place on block b = (c, r).  Sons split Y into
+  // [Y1; Y2]: Y2 <- G_22 Y2, Y2 += G_21 Y1 (Y1 still untouched),
+  // Y1 <- G_11 Y1.
+  void lmul_tri(int c, int b) {
+    const int r = bt.col[b];
+    if (bt.kind[b] == 0) {
+      if (leaf(c)) {
+        for (int r2 : sons_plus(r)) lmul_tri(c, find(c, r2));
+        return;
+      }
+      const int c1 = ct.son0[c], c2 = ct.son1[c];
+      const auto rs = sons_plus(r);
+      for (int r2 : rs) lmul_tri(c2, find(c2, r2));
+      for (int r2 : rs) mm_n(c2, c1, r2, 1.0, -1, 0, 0);
+      for (int r2 : rs) lmul_tri(c1, find(c1, r2));
+    } else if (bt.kind[b] == 2) {
+      emit(OP_NEAR_TRMUL, b, find(c, c), 0);          // N_b <- G_cc N_b
+    } else {
+      // G_cc V_c S W_r^*, added as the update (G_cc V_c - V_c)(W_r S^*)^*
+      emit(OP_EXPAND, 0, c, B_W);
+      emit(OP_COPY, B_W, B_WP, c);
+      trmv(c, B_WP, 0);
+      emit(OP_SUB, B_WP, B_W, B_U, c);
+      emit(OP_EXPAND, 1, r, B_A);
+      emit(OP_RMUL_S, B_A, B_V, b, 1, r, 0, 0, 0, 1.0);
+      addlr(b, B_U, B_V);
+    }
+  }
+
+  void neg(int b) {
+    std::vector<int> lv;
+    leaves_of(b, lv);
+    const int off = (int)aux.size();
+    for (int l : lv) aux.push_back(l);
+    emit(OP_NEG, off, (int)lv.size());
+  }
+
+  // Triangular inverse (the inversion remark at the end of Section 6 with
+  // A_12 = 0): C_11 = A_11^{-1}, C_22 = A_22^{-1}, C_21 = -C_22 A_21 C_11,
+  // the last formed in place on the block (c2, c1).
+  void tinv(int c) {
+    if (leaf(c)) { emit(OP_TRTRI, find(c, c)); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    const int b = find(c2, c1);
+    tinv(c1);
+    rmul_tri(c1, b);
+    tinv(c2);
+    lmul_tri(c2, b);
+    neg(b);
+  }
+
   void chol(int t) {
     if (leaf(t)) { emit(OP_POTRF, find(t, t), t); return; }
     const int t1 = ct.son0[t], t2 = ct.son1[t];
@@ -877,6 +1044,7 @@ h2_status h2_mat_copy(h2_mat src, h2_mat *out) {
     require_ok(src);
     auto m = std::make_unique<h2_mat_s>();
     m->ctx = src->ctx; m->stream = src->stream; m->bt = src->bt; m->lower = src->lower;
+    m->inverse = src->inverse;
     mat_lists(*m);
     mat_alloc(*m);
     hipStream_t s = src->ctx->stream;
@@ -912,6 +1080,7 @@ h2_status h2_mat_assign(h2_mat dst, h2_mat src) {
     cp(dst->d_S, src->d_S); cp(dst->d_N, src->d_N);
     HIPCHK(hipMemsetAsync(dst->d_err.p, 0, dst->d_err.n * sizeof(int), s));
     dst->poisoned = false;
+    dst->inverse = src->inverse;
   });
 }
 
@@ -1046,6 +1215,7 @@ h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
   return guarded([&] {
     require_ok(a);
     REQUIRE(a->lower, "h2_cholesky needs a matrix created with lower != 0");
+    REQUIRE(!a->inverse, "h2_cholesky on an inverted factor");
     set_trunc(*a, tr);
     if (!a->chol.built) {
       std::vector<Task> tasks;
@@ -1058,7 +1228,30 @@ h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
   });
 }
 
+// z = G^* G r for an inverted factor G ~ L^{-1}: two products with the
+// lower triangular H^2 matrix (all stored leaves, every level at once).
+static void precond_inverse_device(h2_mat g, const double *r, double *z, int nrhs) {
+  const h2_ctree_s &ct = *g->bt->ct;
+  hipStream_t s = g->ctx->stream;
+  if (!g->prec_inv.built) {
+    std::vector<Task> tasks;
+    Planner P(*g, tasks);
+    P.bapply(0, 0, B_X, B_Y, 1.0, 0.0);
+    P.bapply(0, 1, B_Y, B_X, 1.0, 0.0);
+    upload_tasks(*g, g->prec_inv, tasks, P.aux);
+  }
+  const long work = (long)ct.n * nrhs;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, 0, nrhs, ct.d_perm.p, r,
+                     (long)ct.n, g->env.buf[B_X], g->d_bcols.p, (int)B_X);
+  HIPCHK(hipGetLastError());
+  run_tasks(*g, g->prec_inv);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
+                     g->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
+  HIPCHK(hipGetLastError());
+}
+
 static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
+  if (l->inverse) { precond_inverse_device(l, r, z, nrhs); return; }
   const h2_ctree_s &ct = *l->bt->ct;
   hipStream_t s = l->ctx->stream;
   if (!l->prec.built) {
@@ -1078,6 +1271,31 @@ static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
                      l->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
   HIPCHK(hipGetLastError());
+}
+
+h2_status h2_tri_invert(h2_mat l, const h2_trunc *tr) {
+  return guarded([&] {
+    require_ok(l);
+    REQUIRE(l->lower, "h2_tri_invert needs a lower triangular factor");
+    REQUIRE(!l->inverse, "matrix is already inverted");
+    set_trunc(*l, tr);
+    if (!l->tinv.built) {
+      std::vector<Task> tasks;
+      Planner P(*l, tasks);
+      P.tinv(0);
+      upload_tasks(*l, l->tinv, tasks, P.aux);
+    }
+    run_tasks(*l, l->tinv);
+    l->inverse = true;
+    check_device_error(*l);
+  });
+}
+
+h2_status h2_mat_is_inverse(h2_mat m, int32_t *inverse) {
+  return guarded([&] {
+    REQUIRE(m && inverse, "null argument");
+    *inverse = m->inverse ? 1 : 0;
+  });
 }
 
 h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs) {

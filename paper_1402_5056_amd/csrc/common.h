@@ -27,7 +27,7 @@ enum Op : int {
   OP_EXPAND,         // i0 side, i1 cluster, i2 buf       -> buf rows = expanded basis, cols = k
   OP_BAPPLY,         // i0 block, i1 trans, i2 in, i3 out; alpha, beta
   OP_RMUL_S,         // i0 in, i1 out, i2 block, i3 transS, i4 rows cluster; alpha
-  OP_COPY_NEAR,      // i0 block, i1 out; alpha          -> rows of row cluster, cols = #col cluster
+  OP_COPY_NEAR,      // i0 block, i1 out, i2 trans; alpha -> rows of row (trans: column) cluster
   OP_IDENT,          // i0 cluster, i1 buf, i2 first col, i3 ncols
   OP_NEAR_ADD,       // i0 block, i1 U, i2 V; alpha
   OP_TEMP_INIT,      // i0 U, i1 V, i2 row cluster, i3 col cluster
@@ -42,6 +42,10 @@ enum Op : int {
   OP_SV_LEAF,        // i0 diagonal leaf block, i1 buf, i2 trans
   OP_SV_CROSS,       // i0 aux offset, i1 groups, i2 buf, i3 trans  leaves of (c2, c1), solved -> unsolved part
   OP_SV_UP,          // i0 cluster, i1 buf, i2 trans   forward transformation of a solved cluster
+  OP_TRTRI,          // i0 diagonal leaf block         N <- inverse of its lower triangle
+  OP_TRMV,           // i0 diagonal leaf block, i1 buf, i2 trans   buf rows <- tril(N) (or its transpose) buf rows
+  OP_NEG,            // i0 aux offset, i1 count        negate the stored leaf blocks listed in aux
+  OP_NEAR_TRMUL,     // i0 near block, i1 diagonal leaf block, i2 side   N <- tril(N_cc) N (0) or N tril(N_cc) (1)
 };
 
 struct Task {

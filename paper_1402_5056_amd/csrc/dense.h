@@ -951,4 +951,43 @@ __device__ void wg_trsv_lower(int n, int m, MV L, MV B, int trans) {
   __syncthreads();
 }
 
+
+// A (n x n, n <= LS) <- L^{-1} for the lower triangular L held in A; the
+// strict upper triangle of the result is exactly zero.  Column c of the
+// inverse solves L x = e_c; one wave per column, L staged in registers by
+// every wave before any column is written.
+__device__ void wg_trtri_lower(int n, MV A) {
+  double row[LS];
+  wave_load_tri<LS>(n, A, 0, row);
+  __syncthreads();
+  const int lane = lane_id();
+  for (int c = wave_id(); c < n; c += num_waves()) {
+    double b = lane == c ? 1.0 : 0.0;
+    b = wave_tri_solve<LS>(n, row, 0, b);
+    if (lane < n) A(lane, c) = b;
+  }
+  __syncthreads();
+}
+
+// B (n x m) <- L B (trans = 0) or L^T B (trans = 1) for the lower triangle
+// of L (n <= LS; entries above the diagonal are ignored), in place; one wave
+// per column of B.
+__device__ void wg_trmv_lower(int n, int m, MV L, MV B, int trans) {
+  double row[LS];
+  wave_load_tri<LS>(n, L, trans, row);
+  const int lane = lane_id();
+  for (int c = wave_id(); c < m; c += num_waves()) {
+    const double x = lane < n ? B(lane, c) : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < LS; ++l) {
+      const double xl = __shfl(x, l, 64);
+      const bool in_tri = trans ? (l >= lane) : (l <= lane);
+      if (l < n && in_tri) acc = fma(row[l], xl, acc);
+    }
+    if (lane < n) B(lane, c) = acc;
+  }
+  __syncthreads();
+}
+
 }  // namespace h2

@@ -106,7 +106,8 @@ __device__ __forceinline__ void count(const DevEnv &e, double f) {
 constexpr int NWAVE = NT / 64;
 constexpr int WREG = 2304;      // doubles of LDS per wave for work matrices
 constexpr int WSMALL = 256;     // doubles of LDS per wave for vectors
-constexpr int WGLOB = 16384;    // doubles of global scratch per wave (overflow)
+constexpr int WGLOB = 65536;    // doubles of global scratch per wave (overflow)
+constexpr int TEMP_WAVE_MAX = 16384;   // larger truncated additions run on the whole workgroup
 constexpr int PRECOND_MIN = 6;  // SVDs with more columns are QR-preconditioned
 constexpr size_t LDS_WAVE_DOUBLES = (size_t)NWAVE * (WREG + WSMALL);
 constexpr size_t LDS_TOTAL_DOUBLES = LDS_WAVE_DOUBLES > LDS_DOUBLES ? LDS_WAVE_DOUBLES : LDS_DOUBLES;
@@ -1284,16 +1285,17 @@ __device__ void task_rmul_s(const DevEnv &e, int bin, int bout, int b, int trans
   __syncthreads();
 }
 
-__device__ void task_copy_near(const DevEnv &e, int b, int bout, double alpha) {
+__device__ void task_copy_near(const DevEnv &e, int b, int bout, int trans, double alpha) {
   const int t = e.brow[b], s = e.bcol[b];
   MV N = Nslot(e, b);
-  MV out = bufrows(e, bout, t);
+  MV out = bufrows(e, bout, trans ? s : t);
   const int mt = e.size[t], ns = e.size[s];
   for (int q = threadIdx.x; q < mt * ns; q += blockDim.x) {
     const int i = q % mt, j = q / mt;
-    out(i, j) = alpha * N(i, j);
+    if (trans) out(j, i) = alpha * N(i, j);
+    else out(i, j) = alpha * N(i, j);
   }
-  if (threadIdx.x == 0) e.bcols[bout] = ns;
+  if (threadIdx.x == 0) e.bcols[bout] = trans ? mt : ns;
   __syncthreads();
 }
 
@@ -1427,7 +1429,7 @@ __device__ void task_temp_add(const DevEnv &e, const Lds &L, double *lds, const 
     const long need0 = (long)(mt | 1) * kk + (kk | 1) + (long)(qa | 1) * qb + (long)(qb | 1) * qb +
                        (long)(qa | 1) * qa + (long)(mt | 1) * (qa > qb ? qa : qb) + 3L * (kk | 1) * (kk + 1);
     const long need1 = (long)(mr | 1) * kk + (kk | 1) + (long)(mr | 1) * (qa > qb ? qa : qb);
-    if (need0 > WGLOB || need1 > WGLOB) { task_temp_add_wg(e, L, tk); return; }
+    if (need0 > TEMP_WAVE_MAX || need1 > TEMP_WAVE_MAX) { task_temp_add_wg(e, L, tk); return; }
   }
   const int w = wave_id(), lane = lane_id();
   // only waves 0 and 1 hold matrices here: each gets the LDS of half of the
@@ -1583,6 +1585,54 @@ __device__ void task_copy(const DevEnv &e, int ba, int bo, int cl) {
   __syncthreads();
 }
 
+// Inverse of the lower triangular diagonal leaf (c, c) in place (leaf case
+// of the triangular inversion).
+__device__ void task_trtri(const DevEnv &e, int bcc) {
+  const int n = e.size[e.brow[bcc]];
+  wg_trtri_lower(n, Nslot(e, bcc));
+  count(e, (double)n * n * n / 3.0);
+}
+
+// buf|_c <- tril(N_cc) buf|_c (trans: transposed), the leaf case of the
+// product with a lower triangular matrix.
+__device__ void task_trmv(const DevEnv &e, int bcc, int bi, int trans) {
+  if (e.bcols[bi] == 0) return;   // no columns
+  const int c = e.brow[bcc];
+  wg_trmv_lower(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), trans);
+  count(e, (double)e.size[c] * e.size[c] * e.bcols[bi]);
+}
+
+// Product of an inadmissible leaf with a lower triangular diagonal leaf, in
+// place: N_b <- tril(N_cc) N_b (side 0, b = (c, r)) or N_b <- N_b tril(N_cc)
+// (side 1, b = (r, c)), the second as N_b^T <- tril(N_cc)^T N_b^T.
+__device__ void task_near_trmul(const DevEnv &e, int b, int bcc, int side) {
+  const int nc = e.size[e.brow[bcc]];
+  MV N = Nslot(e, b);
+  if (side == 0) wg_trmv_lower(nc, e.size[e.bcol[b]], Nslot(e, bcc), N, 0);
+  else wg_trmv_lower(nc, e.size[e.brow[b]], Nslot(e, bcc), mv_t(N), 1);
+  count(e, (double)nc * nc * (side == 0 ? e.size[e.bcol[b]] : e.size[e.brow[b]]));
+}
+
+// Negate every stored leaf block listed in aux[off .. off + cnt): the
+// coupling matrix of an admissible leaf, the dense block of an
+// inadmissible one.  One wave per block.
+__device__ void task_neg(const DevEnv &e, const int *aux, int off, int cnt) {
+  const int lane = lane_id();
+  for (int q = wave_id(); q < cnt; q += num_waves()) {
+    const int b = aux[off + q];
+    if (e.bkind[b] == 1) {
+      MV S = Sslot(e, b);
+      const int kt = e.k[0][e.brow[b]], ks = e.k[1][e.bcol[b]];
+      for (int p = lane; p < kt * ks; p += 64) S(p % kt, p / kt) = -S(p % kt, p / kt);
+    } else {
+      MV N = Nslot(e, b);
+      const int mt = e.size[e.brow[b]], ms = e.size[e.bcol[b]];
+      for (int p = lane; p < mt * ms; p += 64) N(p % mt, p / mt) = -N(p % mt, p / mt);
+    }
+  }
+  __syncthreads();
+}
+
 // ============================================================ interpreter
 __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, int ntask,
                                                const DevEnv *__restrict__ env, const int *__restrict__ aux) {
@@ -1613,7 +1663,7 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
         break;
       }
       case OP_RMUL_S: task_rmul_s(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.i[4], tk.alpha); break;
-      case OP_COPY_NEAR: task_copy_near(e, tk.i[0], tk.i[1], tk.alpha); break;
+      case OP_COPY_NEAR: task_copy_near(e, tk.i[0], tk.i[1], tk.i[2], tk.alpha); break;
       case OP_IDENT: task_ident(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_NEAR_ADD: task_near_add(e, tk.i[0], tk.i[1], tk.i[2], tk.alpha); break;
       case OP_TEMP_INIT: task_temp_init(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
@@ -1637,6 +1687,10 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
       case OP_SV_LEAF: task_sv_leaf(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_SV_CROSS: task_sv_cross(e, aux, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_SV_UP: task_sv_up(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_TRTRI: task_trtri(e, tk.i[0]); break;
+      case OP_TRMV: task_trmv(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_NEG: task_neg(e, aux, tk.i[0], tk.i[1]); break;
+      case OP_NEAR_TRMUL: task_near_trmul(e, tk.i[0], tk.i[1], tk.i[2]); break;
       default: set_error(e, E_ARG, tk.op); break;
     }
     if (e.prof && threadIdx.x == 0 && tk.op > 0 && tk.op < 32) {

@@ -87,6 +87,8 @@ _SIG = {
     "h2_matvec": [_vp, _i32, _d, _vp, _d, _vp, _i32],
     "h2_cholesky": [_vp, _P(h2_trunc)],
     "h2_precond": [_vp, _vp, _vp, _i32],
+    "h2_tri_invert": [_vp, _vp],
+    "h2_mat_is_inverse": [_vp, _P(_i32)],
     "h2_csr_create": [_vp, _i64, _vp, _vp, _vp, _P(_vp)],
     "h2_csr_destroy": [_vp],
     "h2_spmv": [_vp, _vp, _vp],
@@ -342,6 +344,16 @@ def h2_matvec(m: Mat, x, y, trans: bool = False, alpha: float = 1.0, beta: float
 
 def h2_cholesky(m: Mat, tr: h2_trunc):
     _check(_lib.h2_cholesky(m.h, C.byref(tr)))
+
+
+def h2_tri_invert(m: Mat, tr: h2_trunc):
+    _check(_lib.h2_tri_invert(m.h, C.byref(tr)))
+
+
+def h2_mat_is_inverse(m: Mat) -> bool:
+    v = _i32()
+    _check(_lib.h2_mat_is_inverse(m.h, C.byref(v)))
+    return bool(v.value)
 
 
 def h2_precond(m: Mat, r, z):
