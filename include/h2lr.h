@@ -50,6 +50,7 @@ typedef struct h2_ctree_s *h2_ctree;
 typedef struct h2_btree_s *h2_btree;
 typedef struct h2_mat_s *h2_mat;
 typedef struct h2_csr_s *h2_csr;
+typedef struct h2_job_s *h2_job;
 
 /* Recompression accuracy (Section 4, last paragraph; Section 7 "block-relative
  * accuracy").  mode 0 = block-relative: every block entering a weight stack is
@@ -146,6 +147,15 @@ h2_status h2_mat_copy(h2_mat src, h2_mat *out);
  * device-to-device copies only, no allocation.  Clears a poisoned dst. */
 h2_status h2_mat_assign(h2_mat dst, h2_mat src);
 h2_status h2_mat_destroy(h2_mat m);
+/* Device bytes h2_mat_from_csr allocates for a matrix on bt (lower: as its
+ * argument): storage, work areas and block lists; task lists (made by the
+ * first factorisation / solve), PCG vectors and the tree tables (shared by
+ * the matrices of one tree) come on top.  Host-only; for admission by an HBM
+ * budget. */
+h2_status h2_estimate_bytes(h2_btree bt, int32_t lower, int64_t *bytes);
+/* Device bytes the matrix holds now, task lists and PCG vectors included
+ * (tree tables excluded). */
+h2_status h2_mat_bytes(h2_mat m, int64_t *bytes);
 /* stored_values: floating point values held by bases, transfers, couplings
  * and nearfield blocks at the current ranks; max ranks of both bases. */
 h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row,
@@ -193,6 +203,29 @@ h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, doub
  * H2_ERR_RANK_CAP; the matrix is then poisoned. */
 h2_status h2_cholesky(h2_mat a, const h2_trunc *tr);
 
+/* h2_cholesky of count independent matrices in one launch (one workgroup
+ * per matrix; the same Section 3 recursion and arithmetic as h2_cholesky,
+ * so each factor equals the one h2_cholesky makes alone).  mats: host array
+ * of distinct lower-stored matrices on one device and stream, any sizes.
+ * status: optional host array of count entries receiving each matrix's
+ * result.  Every matrix is factorised; a failed one is poisoned and the
+ * call returns the status of the first failure (message names its index),
+ * the others keep valid factors.  Blocks until the launch has finished. */
+h2_status h2_cholesky_batched(h2_mat *mats, int32_t count, const h2_trunc *tr, h2_status *status);
+
+/* The launch half of h2_cholesky_batched: plans (first call per matrix),
+ * starts the factorisations on the matrices' stream and returns at once.
+ * Until h2_job_finish, the matrices are busy: every other call on them fails
+ * with H2_ERR_ARG (h2_mat_destroy with H2_ERR_STATE).  Launches on different
+ * streams run concurrently on the device. */
+h2_status h2_cholesky_launch(h2_mat *mats, int32_t count, const h2_trunc *tr, h2_job *job);
+/* *done = 1 once the launched work has finished (does not block). */
+h2_status h2_job_query(h2_job job, int32_t *done);
+/* Waits for the job, checks every matrix as h2_cholesky_batched does (status
+ * optional, count entries), releases the matrices and frees the job (also
+ * when it returns an error). */
+h2_status h2_job_finish(h2_job job, h2_status *status);
+
 /* In-place approximate inverse G ~ L^{-1} of a Cholesky factor made by
  * h2_cholesky (the inversion remark at the end of Section 6, with the upper
  * off-diagonal block zero: C_11 = L_11^{-1}, C_22 = L_22^{-1},
@@ -227,6 +260,18 @@ h2_status h2_spmv(h2_csr a, const double *x, double *y);
  * ||r||/||b||.  Returns H2_ERR_NOT_CONVERGED if maxit is reached. */
 h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit,
                  int32_t *iters, double *relres);
+
+/* h2_pcg for count independent systems A_i x_i = b_i in lockstep on one
+ * stream: the products and vector updates of each system are launched one
+ * after another, the preconditioner applications of all unconverged systems
+ * run in one launch (one workgroup each); a converged system stops.  Same
+ * arithmetic as h2_pcg, so each result equals the single solve.  as, ls, bs,
+ * xs: host arrays of count entries (device vectors, original order, lengths
+ * n_i); ls distinct Cholesky factors (not inverted) on one stream.  iters,
+ * relres, status: optional host arrays of count entries.  Returns the first
+ * failure (H2_ERR_NOT_CONVERGED if a system reached maxit). */
+h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs, int32_t count,
+                         double rtol, int32_t maxit, int32_t *iters, double *relres, h2_status *status);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -288,6 +289,7 @@ struct h2_mat_s {
   h2_btree bt;
   bool lower = false;
   bool poisoned = false;
+  bool busy = false;      // part of a launched, unfinished batch (h2_job)
   int nadm = 0, nnear = 0;
   std::vector<int> bslot, adm, nearb;
   std::vector<int> rowptr, rowidx, colptr, colidx, nrowptr, nrowidx, ncolptr, ncolidx;
@@ -346,6 +348,44 @@ static void mat_alloc(h2_mat_s &m) {
   m.d_err.alloc(4); m.d_err.zero(s);
   m.d_flops.alloc(1 + NWAVE); m.d_flops.zero(s);
   m.d_wscr.alloc((size_t)NWAVE * WGLOB);
+}
+
+// Device bytes a matrix holds now: storage, work areas, task lists, PCG
+// vectors (the tree tables, shared by all matrices of a tree, excluded).
+static size_t mat_bytes_now(const h2_mat_s &m) {
+  size_t b = 0;
+  auto add = [&](const auto &d) { b += d.n * sizeof(*d.p); };
+  add(m.d_bslot); add(m.d_rowptr); add(m.d_rowidx); add(m.d_colptr); add(m.d_colidx);
+  add(m.d_nrowptr); add(m.d_nrowidx); add(m.d_ncolptr); add(m.d_ncolidx);
+  for (int side = 0; side < 2; ++side) {
+    add(m.d_k[side]); add(m.d_rho_m[side]); add(m.d_wrho_m[side]); add(m.d_wB_m[side]); add(m.d_wnewk[side]);
+    add(m.d_leaf[side]); add(m.d_E[side]); add(m.d_rho[side]); add(m.d_wrho[side]); add(m.d_wB[side]);
+    add(m.d_wR[side]);
+  }
+  add(m.d_bcols); add(m.d_err); add(m.d_S); add(m.d_N); add(m.d_xh); add(m.d_yh); add(m.d_buf);
+  add(m.d_pcg); add(m.d_prof); add(m.d_flops); add(m.d_wscr); add(m.d_env);
+  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv}) { add(tl->d); add(tl->aux); }
+  return b;
+}
+
+// Device bytes h2_mat_from_csr allocates for a block tree (storage, work
+// areas and block lists; no task lists yet): the sizes of mat_alloc and
+// mat_lists.
+static size_t mat_bytes_planned(const h2_btree_s &bt, bool lower) {
+  const h2_ctree_s &ct = *bt.ct;
+  const size_t nc = ct.nc;
+  size_t nadm = 0, nnear = 0;
+  for (int b = 0; b < bt.nb; ++b) {
+    if (bt.kind[b] == 0) continue;
+    const int t = bt.row[b], s = bt.col[b];
+    if (lower && !(t == s || ct.offset[t] > ct.offset[s])) continue;
+    (bt.kind[b] == 1 ? nadm : nnear)++;
+  }
+  size_t ints = bt.nb + 4 * (nc + 1) + 2 * nadm + 2 * nnear + 2 * 5 * nc + NBUF + 4;
+  size_t dbl = 2 * (nc * LS * KC + 2 * nc * KC * KC + 3 * nc * KM * KM) + std::max<size_t>(nadm, 1) * KC * KC +
+               std::max<size_t>(nnear, 1) * LS * LS + 2 * nc * KC * BC + (size_t)NBUF * ct.n * BC + 1 + NWAVE +
+               (size_t)NWAVE * WGLOB;
+  return ints * sizeof(int) + dbl * sizeof(double);
 }
 
 static void mat_lists(h2_mat_s &m) {
@@ -862,6 +902,7 @@ static void check_device_error(h2_mat_s &m) {
 static void require_ok(h2_mat m) {
   REQUIRE(m != nullptr, "null matrix");
   if (m->poisoned) throw H2Error(H2_ERR_STATE, "matrix poisoned by an earlier failure");
+  REQUIRE(!m->busy, "matrix belongs to an unfinished batch (finish its job first)");
 }
 
 static int grid_for(long work) {
@@ -1123,9 +1164,27 @@ h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n) {
 
 h2_status h2_mat_destroy(h2_mat m) {
   // Touches no other object: handles may be destroyed in any order.
+  if (m && m->busy) {
+    g_last_error = "matrix belongs to an unfinished batch (finish its job first)";
+    return H2_ERR_STATE;
+  }
   if (m) (void)hipStreamSynchronize(m->stream);
   delete m;
   return H2_OK;
+}
+
+h2_status h2_estimate_bytes(h2_btree bt, int32_t lower, int64_t *bytes) {
+  return guarded([&] {
+    REQUIRE(bt != nullptr && bytes != nullptr, "null argument");
+    *bytes = (int64_t)mat_bytes_planned(*bt, lower != 0);
+  });
+}
+
+h2_status h2_mat_bytes(h2_mat m, int64_t *bytes) {
+  return guarded([&] {
+    REQUIRE(m != nullptr && bytes != nullptr, "null argument");
+    *bytes = (int64_t)mat_bytes_now(*m);
+  });
 }
 
 h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row, int32_t *max_rank_col) {
@@ -1228,6 +1287,173 @@ h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
   });
 }
 
+static bool g_lds_attr_batch_set = false;
+
+// Device arrays of batch descriptors are recycled, never freed: freeing
+// device memory waits for the whole device, which would stall the host
+// while launches on other streams run.
+static std::mutex g_items_mu;
+static std::vector<Dev<BatchItem> *> g_items_free;
+
+static Dev<BatchItem> *items_acquire(size_t count) {
+  std::lock_guard<std::mutex> lk(g_items_mu);
+  for (size_t i = 0; i < g_items_free.size(); ++i)
+    if (g_items_free[i]->n >= count) {
+      Dev<BatchItem> *d = g_items_free[i];
+      g_items_free.erase(g_items_free.begin() + i);
+      return d;
+    }
+  auto *d = new Dev<BatchItem>();
+  try {
+    d->alloc(std::max<size_t>(count, 64));
+  } catch (...) {
+    d->p = nullptr;   // nothing to free
+    delete d;
+    throw;
+  }
+  return d;
+}
+
+static void items_release(Dev<BatchItem> *d) {
+  if (!d) return;
+  std::lock_guard<std::mutex> lk(g_items_mu);
+  g_items_free.push_back(d);
+}
+
+// One k_interp_batch launch over items (uploaded from the host vector, which
+// must stay untouched until the stream has passed the launch).
+static void launch_batch(Dev<BatchItem> &d_items, const std::vector<BatchItem> &items, int nthreads,
+                         hipStream_t s) {
+  const size_t lds = LDS_TOTAL_DOUBLES * sizeof(double);
+  if (!g_lds_attr_batch_set) {
+    HIPCHK(hipFuncSetAttribute((const void *)k_interp_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    g_lds_attr_batch_set = true;
+  }
+  REQUIRE(d_items.n >= items.size(), "internal: descriptor array too small");
+  HIPCHK(hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_interp_batch, dim3((unsigned)items.size()), dim3(nthreads), lds, s,
+                     (const BatchItem *)d_items.p);
+  HIPCHK(hipGetLastError());
+}
+
+// Checks of a batch: distinct matrices, usable, on one device and stream.
+static std::vector<h2_mat_s *> batch_members(h2_mat *mats, int32_t count, const char *what) {
+  REQUIRE(mats != nullptr && count >= 1, "need at least one matrix");
+  std::vector<h2_mat_s *> ms(mats, mats + count);
+  for (h2_mat_s *m : ms) {
+    require_ok(m);
+    REQUIRE(m->lower, (std::string(what) + " needs matrices created with lower != 0").c_str());
+    REQUIRE(!m->inverse, (std::string(what) + " on an inverted factor").c_str());
+    REQUIRE(m->ctx->device == ms[0]->ctx->device && m->ctx->stream == ms[0]->ctx->stream,
+            "all matrices of a batch must share one device and stream");
+  }
+  std::vector<h2_mat_s *> sorted(ms);
+  std::sort(sorted.begin(), sorted.end());
+  REQUIRE(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), "a matrix appears twice in the batch");
+  return ms;
+}
+
+// Checks every matrix of a finished batch; failed ones are poisoned and
+// their status stored, the first failure is rethrown.
+static void batch_errors(const std::vector<h2_mat_s *> &ms, h2_status *status) {
+  bool failed = false;
+  H2Error first(H2_OK, "");
+  for (size_t i = 0; i < ms.size(); ++i) {
+    try {
+      check_device_error(*ms[i]);
+    } catch (const H2Error &e) {
+      if (status) status[i] = e.code;
+      if (!failed) {
+        first = H2Error(e.code, "matrix " + std::to_string(i) + " of the batch: " + e.what());
+        failed = true;
+      }
+    }
+  }
+  if (failed) throw first;
+}
+
+}  // extern "C"
+
+struct h2_job_s {
+  std::vector<h2_mat_s *> ms;
+  std::vector<BatchItem> items;
+  Dev<BatchItem> *d_items = nullptr;
+  hipEvent_t done = nullptr;
+  hipStream_t stream = nullptr;
+  ~h2_job_s() {
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    } else if (d_items) {
+      (void)hipStreamSynchronize(stream);   // launched but no event: wait before reuse
+    }
+    items_release(d_items);
+    for (h2_mat_s *m : ms) m->busy = false;
+  }
+};
+
+extern "C" {
+
+h2_status h2_cholesky_launch(h2_mat *mats, int32_t count, const h2_trunc *tr, h2_job *job) {
+  return guarded([&] {
+    REQUIRE(job != nullptr, "null output");
+    *job = nullptr;
+    auto j = std::make_unique<h2_job_s>();
+    std::vector<h2_mat_s *> ms = batch_members(mats, count, "h2_cholesky_launch");
+    j->items.resize(count);
+    for (int i = 0; i < count; ++i) {
+      h2_mat_s &m = *ms[i];
+      set_trunc(m, tr);
+      if (!m.chol.built) {
+        std::vector<Task> tasks;
+        Planner P(m, tasks);
+        P.chol(0);
+        upload_tasks(m, m.chol, tasks, P.aux);
+      }
+      sync_env(m);
+      j->items[i] = BatchItem{m.chol.d.p, m.d_env.p, m.chol.aux.p, m.chol.count, 0};
+    }
+    j->stream = ms[0]->ctx->stream;
+    j->d_items = items_acquire(count);
+    launch_batch(*j->d_items, j->items, NT, j->stream);
+    HIPCHK(hipEventCreateWithFlags(&j->done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(j->done, j->stream));
+    j->ms = ms;
+    for (h2_mat_s *m : ms) m->busy = true;
+    *job = j.release();
+  });
+}
+
+h2_status h2_job_query(h2_job job, int32_t *done) {
+  return guarded([&] {
+    REQUIRE(job != nullptr && done != nullptr, "null argument");
+    const hipError_t e = hipEventQuery(job->done);
+    if (e == hipErrorNotReady) { *done = 0; return; }
+    HIPCHK(e);
+    *done = 1;
+  });
+}
+
+h2_status h2_job_finish(h2_job job, h2_status *status) {
+  return guarded([&] {
+    REQUIRE(job != nullptr, "null job");
+    std::unique_ptr<h2_job_s> j(job);
+    if (status)
+      for (size_t i = 0; i < j->ms.size(); ++i) status[i] = H2_OK;
+    HIPCHK(hipEventSynchronize(j->done));
+    for (h2_mat_s *m : j->ms) m->busy = false;
+    batch_errors(j->ms, status);
+  });
+}
+
+h2_status h2_cholesky_batched(h2_mat *mats, int32_t count, const h2_trunc *tr, h2_status *status) {
+  h2_job job = nullptr;
+  const h2_status st = h2_cholesky_launch(mats, count, tr, &job);
+  if (st != H2_OK) return st;
+  return h2_job_finish(job, status);
+}
+
 // z = G^* G r for an inverted factor G ~ L^{-1}: two products with the
 // lower triangular H^2 matrix (all stored leaves, every level at once).
 static void precond_inverse_device(h2_mat g, const double *r, double *z, int nrhs) {
@@ -1250,10 +1476,8 @@ static void precond_inverse_device(h2_mat g, const double *r, double *z, int nrh
   HIPCHK(hipGetLastError());
 }
 
-static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
-  if (l->inverse) { precond_inverse_device(l, r, z, nrhs); return; }
-  const h2_ctree_s &ct = *l->bt->ct;
-  hipStream_t s = l->ctx->stream;
+// Task list of the forward and backward substitution with a factor L.
+static const TaskList &prec_list(h2_mat l) {
   if (!l->prec.built) {
     std::vector<Task> tasks;
     Planner P(*l, tasks);
@@ -1261,16 +1485,35 @@ static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
     P.bsolve_h2(0, B_X);
     upload_tasks(*l, l->prec, tasks, P.aux);
   }
+  return l->prec;
+}
+
+// the substitution tasks (and the leaf solves) use the run-time wave count;
+// four waves measured faster than eight for them
+constexpr int PREC_THREADS = 256;
+
+static void prec_gather(h2_mat l, const double *r, int nrhs) {
+  const h2_ctree_s &ct = *l->bt->ct;
   const long work = (long)ct.n * nrhs;
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, 0, nrhs, ct.d_perm.p, r,
-                     (long)ct.n, l->env.buf[B_X], l->d_bcols.p, (int)B_X);
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, l->ctx->stream, (int)ct.n, 0, nrhs,
+                     ct.d_perm.p, r, (long)ct.n, l->env.buf[B_X], l->d_bcols.p, (int)B_X);
   HIPCHK(hipGetLastError());
-  // the substitution tasks (and the leaf solves) use the run-time wave
-  // count; four waves measured faster than eight for them
-  run_tasks(*l, l->prec, 256);
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, s, (int)ct.n, nrhs, ct.d_perm.p,
-                     l->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
+}
+
+static void prec_scatter(h2_mat l, double *z, int nrhs) {
+  const h2_ctree_s &ct = *l->bt->ct;
+  const long work = (long)ct.n * nrhs;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, l->ctx->stream, (int)ct.n, nrhs,
+                     ct.d_perm.p, l->env.buf[B_X], z, (long)ct.n, 1.0, 0.0);
   HIPCHK(hipGetLastError());
+}
+
+static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
+  if (l->inverse) { precond_inverse_device(l, r, z, nrhs); return; }
+  const TaskList &tl = prec_list(l);
+  prec_gather(l, r, nrhs);
+  run_tasks(*l, tl, PREC_THREADS);
+  prec_scatter(l, z, nrhs);
 }
 
 h2_status h2_tri_invert(h2_mat l, const h2_trunc *tr) {
@@ -1338,6 +1581,127 @@ h2_status h2_spmv(h2_csr a, const double *x, double *y) {
     hipLaunchKernelGGL(k_spmv, dim3(grid_for(a->n)), dim3(256), 0, a->ctx->stream, (int)a->n, a->rp.p, a->ci.p,
                        a->v.p, x, y);
     HIPCHK(hipGetLastError());
+  });
+}
+
+h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs, int32_t count,
+                         double rtol, int32_t maxit, int32_t *iters, double *relres, h2_status *status) {
+  return guarded([&] {
+    REQUIRE(as && bs && xs, "null argument");
+    REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
+    std::vector<h2_mat_s *> ms = batch_members(ls, count, "h2_pcg_batched");
+    if (status)
+      for (int i = 0; i < count; ++i) status[i] = H2_OK;
+    hipStream_t s = ms[0]->ctx->stream;
+    const int NP = 256;   // partial sums of the dot products
+    struct St {
+      h2_csr_s *a; h2_mat_s *l; const double *b; double *x;
+      int n, g, it; double *r, *z, *p, *q, *part, *sc; double nb, rel; bool active, conv;
+    };
+    std::vector<St> st(count);
+    for (int i = 0; i < count; ++i) {
+      St &t = st[i];
+      t.a = as[i]; t.l = ms[i]; t.b = bs[i]; t.x = xs[i];
+      REQUIRE(t.a && t.b && t.x, "null argument");
+      REQUIRE(t.a->n == t.l->bt->ct->n, "size mismatch");
+      t.n = (int)t.a->n;
+      t.g = grid_for(t.n);
+      if (t.l->d_pcg.n < (size_t)4 * t.n + NP + 8) t.l->d_pcg.alloc((size_t)4 * t.n + NP + 8);
+      t.r = t.l->d_pcg.p; t.z = t.r + t.n; t.p = t.z + t.n; t.q = t.p + t.n; t.part = t.q + t.n; t.sc = t.part + NP;
+      t.it = 0; t.rel = 0.0; t.active = true; t.conv = false;
+      prec_list(t.l);
+      sync_env(*t.l);
+    }
+    auto dot = [&](St &t, const double *u, const double *v, double *dst) {
+      hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, t.n, u, v, t.part);
+      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, t.part, dst);
+    };
+    std::vector<double> hs(count);
+    auto read_scalars = [&](int slot) {     // sc[slot] of every active problem
+      for (int i = 0; i < count; ++i)
+        if (st[i].active) HIPCHK(hipMemcpyAsync(&hs[i], st[i].sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    };
+    std::vector<BatchItem> items(count);
+    struct ItemsGuard {
+      Dev<BatchItem> *d; hipStream_t s;
+      ~ItemsGuard() { (void)hipStreamSynchronize(s); items_release(d); }
+    } guard{items_acquire(count), s};
+    Dev<BatchItem> &d_items = *guard.d;
+    // z = (L L^*)^{-1} r of every active problem: one launch, one workgroup each
+    auto precond_all = [&]() {
+      for (int i = 0; i < count; ++i) {
+        St &t = st[i];
+        const TaskList &tl = t.l->prec;
+        items[i] = BatchItem{tl.d.p, t.l->d_env.p, tl.aux.p, t.active ? tl.count : 0, 0};
+        if (t.active) prec_gather(t.l, t.r, 1);
+      }
+      launch_batch(d_items, items, PREC_THREADS, s);
+      for (St &t : st)
+        if (t.active) prec_scatter(t.l, t.z, 1);
+    };
+    for (St &t : st) {
+      HIPCHK(hipMemsetAsync(t.x, 0, t.n * sizeof(double), s));
+      HIPCHK(hipMemcpyAsync(t.r, t.b, t.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      dot(t, t.b, t.b, t.sc + 4);
+    }
+    read_scalars(4);
+    for (int i = 0; i < count; ++i) {
+      st[i].nb = std::sqrt(hs[i]);
+      if (st[i].nb == 0.0) { st[i].active = false; st[i].conv = true; }
+    }
+    precond_all();
+    for (St &t : st) {
+      if (!t.active) continue;
+      HIPCHK(hipMemcpyAsync(t.p, t.z, t.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      dot(t, t.r, t.z, t.sc + 0);
+    }
+    for (;;) {
+      bool any = false;
+      for (St &t : st) {
+        if (!t.active) continue;
+        any = true;
+        hipLaunchKernelGGL(k_spmv, dim3(t.g), dim3(256), 0, s, t.n, t.a->rp.p, t.a->ci.p, t.a->v.p, t.p, t.q);
+        ++t.it;
+        dot(t, t.p, t.q, t.sc + 1);
+        hipLaunchKernelGGL(k_pcg_update_xr, dim3(t.g), dim3(256), 0, s, t.n, t.sc, t.p, t.q, t.x, t.r);
+        dot(t, t.r, t.r, t.sc + 3);
+      }
+      if (!any) break;
+      read_scalars(3);
+      any = false;
+      for (int i = 0; i < count; ++i) {
+        St &t = st[i];
+        if (!t.active) continue;
+        t.rel = std::sqrt(hs[i]) / t.nb;
+        if (t.rel <= rtol) { t.conv = true; t.active = false; }
+        else if (t.it >= maxit) t.active = false;
+        any = any || t.active;
+      }
+      if (!any) break;
+      precond_all();
+      for (St &t : st) {
+        if (!t.active) continue;
+        dot(t, t.r, t.z, t.sc + 2);
+        hipLaunchKernelGGL(k_pcg_update_p, dim3(t.g), dim3(256), 0, s, t.n, t.sc, t.z, t.p);
+        hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, t.sc + 0, t.sc + 2);
+      }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) {
+      if (iters) iters[i] = st[i].it;
+      if (relres) relres[i] = st[i].rel;
+    }
+    batch_errors(ms, status);
+    int bad = -1;
+    for (int i = 0; i < count; ++i)
+      if (!st[i].conv) {
+        if (status) status[i] = H2_ERR_NOT_CONVERGED;
+        if (bad < 0) bad = i;
+      }
+    if (bad >= 0)
+      throw H2Error(H2_ERR_NOT_CONVERGED, "PCG did not reach the tolerance (first: problem " + std::to_string(bad) + ")");
   });
 }
 

@@ -93,6 +93,15 @@ struct DevEnv {
   double *wscr;                    // per-wave global overflow work areas
 };
 
+// One entry of a batched interpreter launch.
+struct BatchItem {
+  const Task *tasks;
+  const DevEnv *env;
+  const int *aux;
+  int ntask;
+  int pad;
+};
+
 // Layout of the optional profile counters (ticks of the 100 MHz wall clock).
 constexpr int PROF_COUNT = 0;      // [0, 32): tasks executed per op
 constexpr int PROF_TICKS = 32;     // [32, 64): ticks per op

@@ -1634,8 +1634,9 @@ __device__ void task_neg(const DevEnv &e, const int *aux, int off, int cnt) {
 }
 
 // ============================================================ interpreter
-__global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, int ntask,
-                                               const DevEnv *__restrict__ env, const int *__restrict__ aux) {
+// One workgroup replays one task list against one matrix.
+__device__ __forceinline__ void interp_run(const Task *__restrict__ tasks, int ntask,
+                                           const DevEnv *__restrict__ env, const int *__restrict__ aux) {
   extern __shared__ double lds_raw[];
   const DevEnv &e = *env;
   const Lds L = lds_layout(lds_raw);
@@ -1703,6 +1704,18 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
       if (e.err[0] != 0) return;
     }
   }
+}
+
+__global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, int ntask,
+                                               const DevEnv *__restrict__ env, const int *__restrict__ aux) {
+  interp_run(tasks, ntask, env, aux);
+}
+
+// Independent matrices in one launch: workgroup i replays items[i] (its own
+// task list, matrix and work areas; nothing is shared between workgroups).
+__global__ __launch_bounds__(NT) void k_interp_batch(const BatchItem *__restrict__ items) {
+  const BatchItem it = items[blockIdx.x];
+  interp_run(it.tasks, it.ntask, it.env, it.aux);
 }
 
 // ======================================================== helper kernels

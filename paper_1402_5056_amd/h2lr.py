@@ -81,11 +81,18 @@ _SIG = {
     "h2_mat_assign": [_vp, _vp],
     "h2_mat_destroy": [_vp],
     "h2_mat_stats": [_vp, _P(_i64), _P(_i32), _P(_i32)],
+    "h2_estimate_bytes": [_vp, _i32, _P(_i64)],
+    "h2_mat_bytes": [_vp, _P(_i64)],
     "h2_profile": [_vp, _i32, _vp, _i32],
     "h2_mat_flops": [_vp, _P(_d), _i32],
     "h2_lowrank_update": [_vp, _i64, _i32, _vp, _i64, _vp, _i64, _P(h2_trunc)],
     "h2_matvec": [_vp, _i32, _d, _vp, _d, _vp, _i32],
     "h2_cholesky": [_vp, _P(h2_trunc)],
+    "h2_cholesky_batched": [_P(_vp), _i32, _P(h2_trunc), _P(C.c_int)],
+    "h2_cholesky_launch": [_P(_vp), _i32, _P(h2_trunc), _P(_vp)],
+    "h2_job_query": [_vp, _P(_i32)],
+    "h2_job_finish": [_vp, _P(C.c_int)],
+    "h2_pcg_batched": [_P(_vp), _P(_vp), _P(_vp), _P(_vp), _i32, _d, _i32, _P(_i32), _P(_d), _P(C.c_int)],
     "h2_precond": [_vp, _vp, _vp, _i32],
     "h2_tri_invert": [_vp, _vp],
     "h2_mat_is_inverse": [_vp, _P(_i32)],
@@ -344,6 +351,81 @@ def h2_matvec(m: Mat, x, y, trans: bool = False, alpha: float = 1.0, beta: float
 
 def h2_cholesky(m: Mat, tr: h2_trunc):
     _check(_lib.h2_cholesky(m.h, C.byref(tr)))
+
+
+def h2_estimate_bytes(bt: BTree, lower: bool = True) -> int:
+    v = _i64()
+    _check(_lib.h2_estimate_bytes(bt.h, 1 if lower else 0, C.byref(v)))
+    return v.value
+
+
+def h2_mat_bytes(m: Mat) -> int:
+    v = _i64()
+    _check(_lib.h2_mat_bytes(m.h, C.byref(v)))
+    return v.value
+
+
+def h2_cholesky_batched(mats, tr: h2_trunc):
+    """Factorise the matrices in one launch; returns the per-matrix status
+    list.  Raises H2Error for the first failure (the others are factorised)."""
+    arr = (_vp * len(mats))(*[m.h for m in mats])
+    st = (C.c_int * len(mats))()
+    status = _lib.h2_cholesky_batched(arr, len(mats), C.byref(tr), st)
+    codes = list(st)
+    _check(status)
+    return codes
+
+
+class Job:
+    """A launched batch of factorisations (h2_cholesky_launch); holds its
+    matrices until finish()."""
+
+    def __init__(self, h, mats):
+        self.h = h
+        self.mats = list(mats)
+
+    def done(self) -> bool:
+        v = _i32()
+        _check(_lib.h2_job_query(self.h, C.byref(v)))
+        return bool(v.value)
+
+    def finish(self, check: bool = True):
+        """Per-matrix status list; raises H2Error for the first failure when
+        check is true."""
+        if self.h is None:
+            raise H2Error(-1, "job already finished")
+        st = (C.c_int * len(self.mats))()
+        h, self.h = self.h, None
+        status = _lib.h2_job_finish(h, st)
+        codes = list(st)
+        self.mats = []
+        if check:
+            _check(status)
+        return codes
+
+
+def h2_cholesky_launch(mats, tr: h2_trunc) -> Job:
+    arr = (_vp * len(mats))(*[m.h for m in mats])
+    h = _vp()
+    _check(_lib.h2_cholesky_launch(arr, len(mats), C.byref(tr), C.byref(h)))
+    return Job(h.value, mats)
+
+
+def h2_pcg_batched(csrs, mats, bs, xs, rtol: float = 1e-8, maxit: int = 500, check: bool = True):
+    """Returns (iters list, relres list, status list); raises H2Error for the
+    first failure when check is true."""
+    k = len(mats)
+    A = (_vp * k)(*[a.h for a in csrs])
+    Ls = (_vp * k)(*[m.h for m in mats])
+    B = (_vp * k)(*[_ptr(b) for b in bs])
+    X = (_vp * k)(*[_ptr(x) for x in xs])
+    it = (_i32 * k)()
+    rel = (_d * k)()
+    st = (C.c_int * k)()
+    status = _lib.h2_pcg_batched(A, Ls, B, X, k, float(rtol), int(maxit), it, rel, st)
+    if check:
+        _check(status)
+    return list(it), list(rel), list(st)
 
 
 def h2_tri_invert(m: Mat, tr: h2_trunc):

@@ -1,0 +1,231 @@
+"""Serving loop for setup + solve requests (continuous batching on one GPU).
+
+A request brings a sparse SPD matrix (CSR, original order), the integer grid
+coordinates of its unknowns and 1..16 right-hand sides.  The server builds
+the cluster and block trees, H^2(A), the H^2-Cholesky factor and solves every
+right-hand side by PCG; the result is the solution block.
+
+Scheduling (host side only; every numerical step runs in the h2lr library):
+
+* admission: a waiting request is admitted first-come first-served when its
+  device bytes (``h2_estimate_bytes`` plus an allowance for task lists and
+  PCG vectors) fit the HBM budget next to everything still held; a request
+  larger than the whole budget is rejected;
+* launch slots: each slot owns a HIP stream; admitted requests are
+  factorised together in one batched launch (``h2_cholesky_launch``, one
+  workgroup per problem) on a free slot, so launches made while others run
+  overlap on the device;
+* completion: a finished launch is checked, and all right-hand sides of its
+  requests are solved by batched PCG (``h2_pcg_batched``: the preconditioner
+  applications of all systems in one launch per iteration);
+* release: device memory of finished requests is released when no launch is
+  in flight (freeing device memory waits for the device), and only then
+  returns to the budget.
+
+Latency of a request = completion time - arrival time.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import h2lr
+
+TASK_BYTES_PER_DOF = 2048     # allowance for task lists and PCG vectors per unknown
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds after the start of the run
+    A: object                      # scipy CSR, SPD
+    coords: np.ndarray             # n x dim int32
+    B: np.ndarray                  # n x nrhs right-hand sides
+    result: np.ndarray | None = None
+    iters: list = field(default_factory=list)
+    status: str = "waiting"        # waiting, admitted, running, done, rejected, failed
+    error: str = ""
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    nbytes: int = 0
+    # device objects while the request is held
+    _ct: object = None
+    _bt: object = None
+    _L: object = None
+    _csr: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+class Server:
+    def __init__(self, budget_bytes: int, eps: float = 1e-4, eta: float = 2.0, leaf: int = 32,
+                 rtol: float = 1e-8, maxit: int = 500, slots: int = 2, max_batch: int = 32,
+                 device: int = 0):
+        self.budget = int(budget_bytes)
+        self.tr = h2lr.trunc(eps, "block_rel", 32)
+        self.eta, self.leaf, self.rtol, self.maxit = eta, leaf, rtol, maxit
+        self.max_batch = max_batch
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        self.ctxs = [h2lr.h2_ctx_create(device, s.cuda_stream) for s in self.streams]
+        self.host_ctx = h2lr.h2_ctx_create(-1)
+        self.used = 0                  # bytes held by admitted, unreleased requests
+        self.peak = 0
+        self.launches = 0
+        self.max_inflight = 0
+
+    # ------------------------------------------------------------ helpers
+    def _estimate(self, r: Request) -> int:
+        r._ct = h2lr.h2_ctree_build(self.host_ctx, r.coords, self.leaf)
+        r._bt = h2lr.h2_btree_build(self.host_ctx, r._ct, self.eta)
+        n = r.A.shape[0]
+        return h2lr.h2_estimate_bytes(r._bt, True) + TASK_BYTES_PER_DOF * n
+
+    def _materialise(self, r: Request, slot: int):
+        ctx = self.ctxs[slot]
+        # trees again on the slot's context (the host-only trees hold no device data)
+        ct = h2lr.h2_ctree_build(ctx, r.coords, self.leaf)
+        bt = h2lr.h2_btree_build(ctx, ct, self.eta)
+        r._ct, r._bt = ct, bt
+        r._L = h2lr.h2_mat_from_csr(ctx, bt, r.A, lower=True)
+        r._csr = h2lr.h2_csr_create(ctx, r.A)
+
+    def _release(self, r: Request):
+        for name in ("_L", "_csr", "_bt", "_ct"):
+            obj = getattr(r, name)
+            if obj is not None:
+                obj.close()
+            setattr(r, name, None)
+        self.used -= r.nbytes
+
+    def _solve(self, reqs, slot: int):
+        """All right-hand sides of the finished requests by batched PCG: round
+        j solves column j of every request that has more than j columns."""
+        stream = self.streams[slot]
+        with torch.cuda.stream(stream):
+            for r in reqs:
+                r.result = np.zeros_like(r.B)
+                r.iters = []
+            nmax = max(r.B.shape[1] for r in reqs)
+            for j in range(nmax):
+                act = [r for r in reqs if r.B.shape[1] > j]
+                bs = [torch.tensor(np.ascontiguousarray(r.B[:, j]), device="cuda") for r in act]
+                xs = [torch.zeros_like(b) for b in bs]
+                stream.synchronize()
+                its, _, codes = h2lr.h2_pcg_batched([r._csr for r in act], [r._L for r in act], bs, xs,
+                                                    self.rtol, self.maxit, check=False)
+                for r, x, it, c in zip(act, xs, its, codes):
+                    r.result[:, j] = x.cpu().numpy()
+                    r.iters.append(it)
+                    if c != 0 and r.status != "failed":
+                        r.status, r.error = "failed", h2lr.STATUS.get(c, str(c))
+
+    # --------------------------------------------------------------- loop
+    def run(self, requests, poll: float = 5e-4, log=None):
+        """Serve the requests (arrival times relative to the start); returns
+        them with results, status and timestamps."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        waiting: list[Request] = []
+        admitted: list[list[Request]] = [[] for _ in self.ctxs]   # per slot, not yet launched
+        jobs: dict[int, tuple] = {}                               # slot -> (job, requests)
+        to_release: list[Request] = []
+        nxt = 0
+        t0 = time.perf_counter()
+        done = 0
+        while done < len(requests):
+            now = time.perf_counter() - t0
+            while nxt < len(pending) and pending[nxt].arrival <= now:
+                waiting.append(pending[nxt])
+                nxt += 1
+            # release finished requests when nothing is in flight
+            if to_release and not jobs:
+                for r in to_release:
+                    self._release(r)
+                to_release = []
+            # admission, first come first served, onto free slots
+            free = [s for s in range(len(self.ctxs)) if s not in jobs]
+            while waiting and free:
+                r = waiting[0]
+                if r.nbytes == 0:
+                    r.nbytes = self._estimate(r)
+                if r.nbytes > self.budget:
+                    waiting.pop(0)
+                    r.status, r.error, r.t_done = "rejected", "larger than the HBM budget", now
+                    done += 1
+                    continue
+                if self.used + r.nbytes > self.budget:
+                    break
+                slot = min(free, key=lambda s: len(admitted[s]))
+                if len(admitted[slot]) >= self.max_batch:
+                    break
+                waiting.pop(0)
+                self._materialise(r, slot)
+                self.used += r.nbytes
+                self.peak = max(self.peak, self.used)
+                r.status, r.t_admit = "admitted", time.perf_counter() - t0
+                admitted[slot].append(r)
+            # launch every free slot that holds admitted requests
+            for s in free:
+                if admitted[s]:
+                    reqs = admitted[s]
+                    admitted[s] = []
+                    try:
+                        job = h2lr.h2_cholesky_launch([r._L for r in reqs], self.tr)
+                    except h2lr.H2Error as e:
+                        for r in reqs:
+                            r.status, r.error, r.t_done = "failed", str(e), time.perf_counter() - t0
+                            to_release.append(r)
+                            done += 1
+                        continue
+                    for r in reqs:
+                        r.status = "running"
+                    jobs[s] = (job, reqs)
+                    self.launches += 1
+                    self.max_inflight = max(self.max_inflight, len(jobs))
+                    if log:
+                        log(f"launch {self.launches}: slot {s}, {len(reqs)} problems, {len(jobs)} in flight, "
+                            f"{self.used / 2**30:.2f} GiB held")
+            # completions
+            progressed = False
+            for s in list(jobs):
+                job, reqs = jobs[s]
+                if not job.done():
+                    continue
+                progressed = True
+                del jobs[s]
+                codes = job.finish(check=False)
+                ok = []
+                for r, c in zip(reqs, codes):
+                    if c == 0:
+                        ok.append(r)
+                    else:
+                        r.status, r.error = "failed", h2lr.STATUS.get(c, str(c))
+                if ok:
+                    self._solve(ok, s)
+                tnow = time.perf_counter() - t0
+                for r in reqs:
+                    if r.status == "running":
+                        r.status = "done"
+                    r.t_done = tnow
+                    to_release.append(r)
+                    done += 1
+            if not progressed and nxt >= len(pending) and not waiting and not any(admitted) and not jobs:
+                break
+            if not progressed:
+                time.sleep(poll)
+        for r in to_release:
+            self._release(r)
+        return requests
+
+
+def latency_summary(requests):
+    lat = np.array([r.latency for r in requests if r.status == "done"])
+    if lat.size == 0:
+        return {"p50_s": None, "p99_s": None, "completed": 0}
+    return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "completed": int(lat.size)}

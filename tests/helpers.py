@@ -26,6 +26,7 @@ def dense_via_matvec(h2lr, M, n, trans=False):
         X = torch.zeros((nc, n), dtype=torch.float64, device="cuda")
         X[torch.arange(nc), torch.arange(c0, c0 + nc)] = 1.0
         Y = torch.zeros_like(X)
+        torch.cuda.synchronize()      # the matrix may live on another stream
         h2lr.h2_matvec(M, X, Y, trans=trans)
         torch.cuda.synchronize()
         D[:, c0:c0 + nc] = Y.cpu().numpy().T

@@ -1,0 +1,203 @@
+"""Batched H^2-Cholesky: independent problems of different sizes factorised
+in one launch (one workgroup each) through the C ABI.  Each factor must equal
+the one h2_cholesky makes alone (same arithmetic, bit for bit) and the CPU
+oracle's within 1e-12 relative spectral error in FP64."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.arith import cholesky as o_cholesky
+from oracle.h2 import TruncParams, from_csr as o_from_csr, to_dense as o_to_dense
+from oracle.solve import pcg as o_pcg
+from oracle.arith import precond_apply as o_precond
+from oracle.trees import build_block_tree, build_cluster_tree
+from tests.helpers import dense_via_matvec, gpu, rel2, to_original
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+# (grid side, coefficient seed, leaf size, eta, domain decomposition): balanced,
+# unbalanced (leaves on two levels) and domain-decomposition trees
+CASES = [(16, 7, 8, 2.0, False), (24, 3, 16, 2.0, False), (32, None, 32, 2.0, False),
+         (40, 7, 24, 2.0, False), (33, None, 32, 4.0, True), (48, 5, 32, 2.0, False)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    gpu()
+    from paper_1402_5056_amd import h2lr
+    return h2lr
+
+
+def _problem(lib, ctx, side, sigma_seed, leaf, eta, dd, negate=False):
+    p = w.problem(side, sigma_seed=sigma_seed, rhs_seed=side)
+    A = -p["A"] if negate else p["A"]
+    ct = (lib.h2_ctree_build_dd if dd else lib.h2_ctree_build)(ctx, p["coords"], leaf)
+    bt = lib.h2_btree_build(ctx, ct, eta)
+    return p, A, bt
+
+
+def test_batched_equals_single_and_oracle(lib):
+    print("case: batched cholesky of 6 problems (sides 16..48)", flush=True)
+    ctx = lib.h2_ctx_create(0)
+    eps = 1e-5
+    tr = lib.trunc(eps, "block_rel", 32)
+    probs, batch, single = [], [], []
+    for side, sg, leaf, eta, dd in CASES:
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, eta, dd)
+        probs.append((p, A, side, sg, leaf, eta, dd))
+        batch.append(lib.h2_mat_from_csr(ctx, bt, A, lower=True))
+        single.append(lib.h2_mat_from_csr(ctx, bt, A, lower=True))
+    codes = lib.h2_cholesky_batched(batch, tr)
+    assert codes == [0] * len(CASES)
+    for (p, A, side, sg, leaf, eta, dd), Mb, Ms in zip(probs, batch, single):
+        lib.h2_cholesky(Ms, tr)
+        n = A.shape[0]
+        Db = dense_via_matvec(lib, Mb, n)
+        Ds = dense_via_matvec(lib, Ms, n)
+        assert np.array_equal(Db, Ds), f"side {side}: batched factor differs from the single one"
+        assert lib.h2_mat_stats(Mb) == lib.h2_mat_stats(Ms)
+        oc = build_cluster_tree(p["coords"], leaf, dd=dd)
+        ob = build_block_tree(oc, eta)
+        L = o_cholesky(o_from_csr(A, oc, ob, lower=True), TruncParams(eps, "block_rel", 32))
+        err = rel2(Db, to_original(np.tril(o_to_dense(L)), oc.perm))
+        print(f"  side {side} leaf {leaf} dd {dd}: ||L_batch - L_oracle||_2 / ||L_oracle||_2 = {err:.3e}",
+              flush=True)
+        assert err < TOL
+
+
+def test_batched_pcg(lib):
+    print("case: pcg with batched factors (sides 24, 32)", flush=True)
+    torch = gpu()
+    ctx = lib.h2_ctx_create(0)
+    tr = lib.trunc(1e-4, "block_rel", 32)
+    items = []
+    for side, sg, leaf in ((24, 3, 16), (32, 4, 32)):
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False)
+        items.append((p, A, leaf, lib.h2_mat_from_csr(ctx, bt, A, lower=True)))
+    lib.h2_cholesky_batched([m for *_, m in items], tr)
+    for p, A, leaf, M in items:
+        oc = build_cluster_tree(p["coords"], leaf)
+        ob = build_block_tree(oc, 2.0)
+        L = o_cholesky(o_from_csr(A, oc, ob, lower=True), TruncParams(1e-4, "block_rel", 32))
+        csr = lib.h2_csr_create(ctx, A)
+        b = torch.tensor(p["b"], device="cuda")
+        x = torch.zeros_like(b)
+        it, rel, ok = lib.h2_pcg(csr, M, b, x, 1e-8, 100)
+        xo, ito, _ = o_pcg(A, p["b"], lambda v: o_precond(L, v))
+        print(f"  n={A.shape[0]}: pcg iterations batched {it} oracle {ito}", flush=True)
+        assert ok and it == ito
+        assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-10
+
+
+def test_batched_failure_is_per_matrix(lib):
+    """A matrix that is not positive definite fails alone: its status is
+    H2_ERR_NOT_SPD and it is poisoned; the others are factorised."""
+    print("case: batched cholesky with one negated (not SPD) matrix", flush=True)
+    ctx = lib.h2_ctx_create(0)
+    tr = lib.trunc(1e-6, "block_rel", 32)
+    mats, ref = [], []
+    for i, (side, sg, leaf) in enumerate(((16, 7, 8), (24, 3, 16), (16, 5, 8))):
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False, negate=(i == 1))
+        mats.append(lib.h2_mat_from_csr(ctx, bt, A, lower=True))
+        ref.append((A, lib.h2_mat_from_csr(ctx, bt, A, lower=True)))
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_cholesky_batched(mats, tr)
+    assert ei.value.name == "H2_ERR_NOT_SPD"
+    assert "matrix 1" in str(ei.value)
+    for i in (0, 2):
+        A, Ms = ref[i]
+        lib.h2_cholesky(Ms, tr)
+        n = A.shape[0]
+        assert np.array_equal(dense_via_matvec(lib, mats[i], n), dense_via_matvec(lib, Ms, n))
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_cholesky(mats[1], tr)
+    assert ei.value.name == "H2_ERR_STATE"
+
+
+def test_batched_argument_errors(lib):
+    print("case: batched cholesky argument errors", flush=True)
+    ctx = lib.h2_ctx_create(0)
+    p, A, bt = _problem(lib, ctx, 16, 7, 8, 2.0, False)
+    M = lib.h2_mat_from_csr(ctx, bt, A, lower=True)
+    full = lib.h2_mat_from_csr(ctx, bt, A, lower=False)
+    tr = lib.trunc(1e-6)
+    for mats in ([M, M], [full], []):
+        with pytest.raises(lib.H2Error) as ei:
+            lib.h2_cholesky_batched(mats, tr)
+        assert ei.value.name == "H2_ERR_ARG"
+
+
+def test_pcg_batched_equals_single(lib):
+    """Batched PCG (one preconditioner launch for all unconverged systems)
+    gives each system the iterates of its single solve."""
+    print("case: batched pcg of 4 systems vs single solves", flush=True)
+    torch = gpu()
+    ctx = lib.h2_ctx_create(0)
+    tr = lib.trunc(1e-4, "block_rel", 32)
+    probs = []
+    for side, sg, leaf in ((16, 7, 8), (24, 3, 16), (32, 4, 32), (48, 5, 32)):
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False)
+        M = lib.h2_mat_from_csr(ctx, bt, A, lower=True)
+        probs.append((p, A, M, lib.h2_csr_create(ctx, A)))
+    lib.h2_cholesky_batched([q[2] for q in probs], tr)
+    bs = [torch.tensor(q[0]["b"], device="cuda") for q in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    its, rels, codes = lib.h2_pcg_batched([q[3] for q in probs], [q[2] for q in probs], bs, xs, 1e-10, 200)
+    assert codes == [0] * len(probs)
+    for (p, A, M, csr), b, x, it, rel in zip(probs, bs, xs, its, rels):
+        x1 = torch.zeros_like(b)
+        it1, rel1, ok = lib.h2_pcg(csr, M, b, x1, 1e-10, 200)
+        print(f"  n={A.shape[0]}: iterations batched {it} single {it1}", flush=True)
+        assert ok and it == it1 and rel == rel1
+        assert torch.equal(x, x1)
+        xr = x.cpu().numpy()
+        assert np.linalg.norm(p["b"] - A @ xr) / np.linalg.norm(p["b"]) < 1e-9
+
+
+def test_pcg_batched_not_converged(lib):
+    print("case: batched pcg with maxit 1", flush=True)
+    torch = gpu()
+    ctx = lib.h2_ctx_create(0)
+    p, A, bt = _problem(lib, ctx, 24, 3, 16, 2.0, False)
+    M = lib.h2_mat_from_csr(ctx, bt, A, lower=True)
+    lib.h2_cholesky(M, lib.trunc(1e-2, "block_rel", 32))
+    b = torch.tensor(p["b"], device="cuda")
+    x = torch.zeros_like(b)
+    its, rels, codes = lib.h2_pcg_batched([lib.h2_csr_create(ctx, A)], [M], [b], [x], 1e-14, 1, check=False)
+    assert its == [1] and codes == [-7]
+
+
+def test_launch_overlapping_streams(lib):
+    """Two launches on two streams are in flight together; their matrices
+    are busy until finish; each factor equals the single one."""
+    print("case: two launched batches on two streams", flush=True)
+    torch = gpu()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    c1 = lib.h2_ctx_create(0, s1.cuda_stream)
+    c2 = lib.h2_ctx_create(0, s2.cuda_stream)
+    c0 = lib.h2_ctx_create(0)
+    tr = lib.trunc(1e-5, "block_rel", 32)
+    groups = []
+    for ctx, sides in ((c1, ((32, 4, 32), (16, 7, 8))), (c2, ((24, 3, 16), (40, 7, 24)))):
+        g = []
+        for side, sg, leaf in sides:
+            p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False)
+            p0, A0, bt0 = _problem(lib, c0, side, sg, leaf, 2.0, False)
+            g.append((A, lib.h2_mat_from_csr(ctx, bt, A, lower=True), lib.h2_mat_from_csr(c0, bt0, A0, lower=True)))
+        groups.append(g)
+    torch.cuda.synchronize()
+    j1 = lib.h2_cholesky_launch([q[1] for q in groups[0]], tr)
+    j2 = lib.h2_cholesky_launch([q[1] for q in groups[1]], tr)
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_cholesky(groups[0][0][1], tr)
+    assert ei.value.name == "H2_ERR_ARG"
+    j1.done()
+    j2.done()
+    assert j2.finish() == [0, 0]
+    assert j1.finish() == [0, 0]
+    for g in groups:
+        for A, M, Ms in g:
+            lib.h2_cholesky(Ms, tr)
+            n = A.shape[0]
+            assert np.array_equal(dense_via_matvec(lib, M, n), dense_via_matvec(lib, Ms, n))
