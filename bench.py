@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--serve-sides", type=str, default="64,96,128")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-release", choices=("idle", "eager"), default="idle",
+                    help="free finished requests only when no launch is in flight, or at once")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="only copy a float64 device buffer of this size once and exit: the "
                          "reference dispatch for scaling the HBM byte counters of a profile")
@@ -263,7 +265,7 @@ def bench_serve(args):
 
     def run():
         srv = serve.Server(int(args.serve_budget_gib * 2**30), eps=args.eps, eta=args.eta, rtol=args.rtol,
-                           slots=args.serve_slots)
+                           slots=args.serve_slots, release=args.serve_release)
         t = time.perf_counter()
         out = srv.run(reqs, log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
         return srv, out, time.perf_counter() - t
@@ -297,6 +299,7 @@ def bench_serve(args):
         "rhs_solved": int(sum(r.B.shape[1] for r in out)),
         "launches": srv.launches, "max_launches_in_flight": srv.max_inflight,
         "peak_budget_gib": srv.peak / 2**30,
+        "release": args.serve_release, "release_host_s": srv.release_s,
         "worst_true_relres": worst,
     }
     print(json.dumps(res), flush=True)

@@ -261,17 +261,21 @@ h2_status h2_spmv(h2_csr a, const double *x, double *y);
 h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit,
                  int32_t *iters, double *relres);
 
-/* h2_pcg for count independent systems A_i x_i = b_i in lockstep on one
- * stream: the products and vector updates of each system are launched one
- * after another, the preconditioner applications of all unconverged systems
- * run in one launch (one workgroup each); a converged system stops.  Same
- * arithmetic as h2_pcg, so each result equals the single solve.  as, ls, bs,
- * xs: host arrays of count entries (device vectors, original order, lengths
- * n_i); ls distinct Cholesky factors (not inverted) on one stream.  iters,
- * relres, status: optional host arrays of count entries.  Returns the first
- * failure (H2_ERR_NOT_CONVERGED if a system reached maxit). */
-h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs, int32_t count,
-                         double rtol, int32_t maxit, int32_t *iters, double *relres, h2_status *status);
+/* h2_pcg for count independent systems A_i X_i = B_i in lockstep on one
+ * stream, each with nrhs[i] right-hand sides (one CG iteration per column):
+ * the products and vector updates of each column are launched one after
+ * another, the preconditioner applications of all systems with an
+ * unconverged column run in one launch (one workgroup per system, all its
+ * columns at once); a converged column stops.  as, ls, bs, xs, nrhs: host
+ * arrays of count entries; bs[i], xs[i]: device, n_i x nrhs[i] column-major
+ * (leading dimension n_i), original order; nrhs NULL means one column each,
+ * 1 <= nrhs[i] <= H2_MAX_COLS; ls distinct Cholesky factors (not inverted)
+ * on one stream.  iters, relres, status: optional host arrays with one entry
+ * per column (systems in order, columns in order).  Returns the first
+ * failure (H2_ERR_NOT_CONVERGED if a column reached maxit). */
+h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
+                         const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
+                         double *relres, h2_status *status);
 
 #ifdef __cplusplus
 }

@@ -1584,42 +1584,67 @@ h2_status h2_spmv(h2_csr a, const double *x, double *y) {
   });
 }
 
-h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs, int32_t count,
-                         double rtol, int32_t maxit, int32_t *iters, double *relres, h2_status *status) {
+h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
+                         const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
+                         double *relres, h2_status *status) {
   return guarded([&] {
     REQUIRE(as && bs && xs, "null argument");
     REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
     std::vector<h2_mat_s *> ms = batch_members(ls, count, "h2_pcg_batched");
-    if (status)
-      for (int i = 0; i < count; ++i) status[i] = H2_OK;
     hipStream_t s = ms[0]->ctx->stream;
     const int NP = 256;   // partial sums of the dot products
-    struct St {
-      h2_csr_s *a; h2_mat_s *l; const double *b; double *x;
-      int n, g, it; double *r, *z, *p, *q, *part, *sc; double nb, rel; bool active, conv;
+    // one CG iteration state per column; a system's columns share its
+    // preconditioner launches
+    struct Col {
+      const double *b; double *x, *r, *z, *p, *q, *part, *sc;
+      double nb, rel; int it; bool active, conv;
     };
-    std::vector<St> st(count);
+    struct Sys {
+      h2_csr_s *a; h2_mat_s *l; int n, g, k, c0; double *R, *Z;
+    };
+    std::vector<Sys> sys(count);
+    std::vector<Col> col;
     for (int i = 0; i < count; ++i) {
-      St &t = st[i];
-      t.a = as[i]; t.l = ms[i]; t.b = bs[i]; t.x = xs[i];
-      REQUIRE(t.a && t.b && t.x, "null argument");
-      REQUIRE(t.a->n == t.l->bt->ct->n, "size mismatch");
-      t.n = (int)t.a->n;
-      t.g = grid_for(t.n);
-      if (t.l->d_pcg.n < (size_t)4 * t.n + NP + 8) t.l->d_pcg.alloc((size_t)4 * t.n + NP + 8);
-      t.r = t.l->d_pcg.p; t.z = t.r + t.n; t.p = t.z + t.n; t.q = t.p + t.n; t.part = t.q + t.n; t.sc = t.part + NP;
-      t.it = 0; t.rel = 0.0; t.active = true; t.conv = false;
-      prec_list(t.l);
-      sync_env(*t.l);
+      Sys &y = sys[i];
+      y.a = as[i]; y.l = ms[i];
+      REQUIRE(y.a && bs[i] && xs[i], "null argument");
+      REQUIRE(y.a->n == y.l->bt->ct->n, "size mismatch");
+      y.n = (int)y.a->n;
+      y.k = nrhs ? nrhs[i] : 1;
+      REQUIRE(y.k >= 1 && y.k <= BC, "nrhs must be in [1, H2_MAX_COLS]");
+      y.g = grid_for(y.n);
+      const size_t need = (size_t)(4 * y.n + NP + 8) * y.k;
+      if (y.l->d_pcg.n < need) y.l->d_pcg.alloc(need);
+      double *base = y.l->d_pcg.p;
+      y.R = base;
+      y.Z = y.R + (size_t)y.n * y.k;
+      double *P = y.Z + (size_t)y.n * y.k, *Q = P + (size_t)y.n * y.k, *PART = Q + (size_t)y.n * y.k;
+      double *SC = PART + (size_t)NP * y.k;
+      y.c0 = (int)col.size();
+      for (int c = 0; c < y.k; ++c) {
+        const size_t o = (size_t)c * y.n;
+        col.push_back(Col{bs[i] + o, xs[i] + o, y.R + o, y.Z + o, P + o, Q + o, PART + (size_t)c * NP,
+                          SC + 8 * c, 0.0, 0.0, 0, true, false});
+      }
+      prec_list(y.l);
+      sync_env(*y.l);
     }
-    auto dot = [&](St &t, const double *u, const double *v, double *dst) {
-      hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, t.n, u, v, t.part);
-      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, t.part, dst);
+    const int ncol = (int)col.size();
+    if (status)
+      for (int c = 0; c < ncol; ++c) status[c] = H2_OK;
+    auto sys_active = [&](const Sys &y) {
+      for (int c = 0; c < y.k; ++c)
+        if (col[y.c0 + c].active) return true;
+      return false;
     };
-    std::vector<double> hs(count);
-    auto read_scalars = [&](int slot) {     // sc[slot] of every active problem
-      for (int i = 0; i < count; ++i)
-        if (st[i].active) HIPCHK(hipMemcpyAsync(&hs[i], st[i].sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    auto dot = [&](const Sys &y, Col &c, const double *u, const double *v, double *dst) {
+      hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, y.n, u, v, c.part);
+      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, c.part, dst);
+    };
+    std::vector<double> hs(ncol);
+    auto read_scalars = [&](int slot) {     // sc[slot] of every active column
+      for (int c = 0; c < ncol; ++c)
+        if (col[c].active) HIPCHK(hipMemcpyAsync(&hs[c], col[c].sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
     };
     std::vector<BatchItem> items(count);
@@ -1628,80 +1653,98 @@ h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double
       ~ItemsGuard() { (void)hipStreamSynchronize(s); items_release(d); }
     } guard{items_acquire(count), s};
     Dev<BatchItem> &d_items = *guard.d;
-    // z = (L L^*)^{-1} r of every active problem: one launch, one workgroup each
+    // Z = (L L^*)^{-1} R for every system with an active column: one launch,
+    // one workgroup per system, all its columns at once
     auto precond_all = [&]() {
       for (int i = 0; i < count; ++i) {
-        St &t = st[i];
-        const TaskList &tl = t.l->prec;
-        items[i] = BatchItem{tl.d.p, t.l->d_env.p, tl.aux.p, t.active ? tl.count : 0, 0};
-        if (t.active) prec_gather(t.l, t.r, 1);
+        Sys &y = sys[i];
+        const bool act = sys_active(y);
+        const TaskList &tl = y.l->prec;
+        items[i] = BatchItem{tl.d.p, y.l->d_env.p, tl.aux.p, act ? tl.count : 0, 0};
+        if (act) prec_gather(y.l, y.R, y.k);
       }
       launch_batch(d_items, items, PREC_THREADS, s);
-      for (St &t : st)
-        if (t.active) prec_scatter(t.l, t.z, 1);
+      for (Sys &y : sys)
+        if (sys_active(y)) prec_scatter(y.l, y.Z, y.k);
     };
-    for (St &t : st) {
-      HIPCHK(hipMemsetAsync(t.x, 0, t.n * sizeof(double), s));
-      HIPCHK(hipMemcpyAsync(t.r, t.b, t.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      dot(t, t.b, t.b, t.sc + 4);
-    }
+    for (Sys &y : sys)
+      for (int c = 0; c < y.k; ++c) {
+        Col &t = col[y.c0 + c];
+        HIPCHK(hipMemsetAsync(t.x, 0, y.n * sizeof(double), s));
+        HIPCHK(hipMemcpyAsync(t.r, t.b, y.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        dot(y, t, t.b, t.b, t.sc + 4);
+      }
     read_scalars(4);
-    for (int i = 0; i < count; ++i) {
-      st[i].nb = std::sqrt(hs[i]);
-      if (st[i].nb == 0.0) { st[i].active = false; st[i].conv = true; }
+    for (int c = 0; c < ncol; ++c) {
+      col[c].nb = std::sqrt(hs[c]);
+      if (col[c].nb == 0.0) { col[c].active = false; col[c].conv = true; }
     }
     precond_all();
-    for (St &t : st) {
-      if (!t.active) continue;
-      HIPCHK(hipMemcpyAsync(t.p, t.z, t.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      dot(t, t.r, t.z, t.sc + 0);
-    }
+    for (Sys &y : sys)
+      for (int c = 0; c < y.k; ++c) {
+        Col &t = col[y.c0 + c];
+        if (!t.active) continue;
+        HIPCHK(hipMemcpyAsync(t.p, t.z, y.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        dot(y, t, t.r, t.z, t.sc + 0);
+      }
     for (;;) {
       bool any = false;
-      for (St &t : st) {
-        if (!t.active) continue;
-        any = true;
-        hipLaunchKernelGGL(k_spmv, dim3(t.g), dim3(256), 0, s, t.n, t.a->rp.p, t.a->ci.p, t.a->v.p, t.p, t.q);
-        ++t.it;
-        dot(t, t.p, t.q, t.sc + 1);
-        hipLaunchKernelGGL(k_pcg_update_xr, dim3(t.g), dim3(256), 0, s, t.n, t.sc, t.p, t.q, t.x, t.r);
-        dot(t, t.r, t.r, t.sc + 3);
-      }
+      for (Sys &y : sys)
+        for (int c = 0; c < y.k; ++c) {
+          Col &t = col[y.c0 + c];
+          if (!t.active) continue;
+          any = true;
+          hipLaunchKernelGGL(k_spmv, dim3(y.g), dim3(256), 0, s, y.n, y.a->rp.p, y.a->ci.p, y.a->v.p, t.p, t.q);
+          ++t.it;
+          dot(y, t, t.p, t.q, t.sc + 1);
+          hipLaunchKernelGGL(k_pcg_update_xr, dim3(y.g), dim3(256), 0, s, y.n, t.sc, t.p, t.q, t.x, t.r);
+          dot(y, t, t.r, t.r, t.sc + 3);
+        }
       if (!any) break;
       read_scalars(3);
       any = false;
-      for (int i = 0; i < count; ++i) {
-        St &t = st[i];
+      for (Col &t : col) {
         if (!t.active) continue;
-        t.rel = std::sqrt(hs[i]) / t.nb;
+        t.rel = std::sqrt(hs[&t - col.data()]) / t.nb;
         if (t.rel <= rtol) { t.conv = true; t.active = false; }
         else if (t.it >= maxit) t.active = false;
         any = any || t.active;
       }
       if (!any) break;
       precond_all();
-      for (St &t : st) {
-        if (!t.active) continue;
-        dot(t, t.r, t.z, t.sc + 2);
-        hipLaunchKernelGGL(k_pcg_update_p, dim3(t.g), dim3(256), 0, s, t.n, t.sc, t.z, t.p);
-        hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, t.sc + 0, t.sc + 2);
-      }
+      for (Sys &y : sys)
+        for (int c = 0; c < y.k; ++c) {
+          Col &t = col[y.c0 + c];
+          if (!t.active) continue;
+          dot(y, t, t.r, t.z, t.sc + 2);
+          hipLaunchKernelGGL(k_pcg_update_p, dim3(y.g), dim3(256), 0, s, y.n, t.sc, t.z, t.p);
+          hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, t.sc + 0, t.sc + 2);
+        }
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    for (int i = 0; i < count; ++i) {
-      if (iters) iters[i] = st[i].it;
-      if (relres) relres[i] = st[i].rel;
+    for (int c = 0; c < ncol; ++c) {
+      if (iters) iters[c] = col[c].it;
+      if (relres) relres[c] = col[c].rel;
     }
-    batch_errors(ms, status);
+    std::vector<h2_status> sst(count, H2_OK);
+    try {
+      batch_errors(ms, sst.data());
+    } catch (const H2Error &) {
+      if (status)
+        for (int i = 0; i < count; ++i)
+          for (int c = 0; c < sys[i].k; ++c) status[sys[i].c0 + c] = sst[i];
+      throw;
+    }
     int bad = -1;
-    for (int i = 0; i < count; ++i)
-      if (!st[i].conv) {
-        if (status) status[i] = H2_ERR_NOT_CONVERGED;
-        if (bad < 0) bad = i;
+    for (int c = 0; c < ncol; ++c)
+      if (!col[c].conv) {
+        if (status) status[c] = H2_ERR_NOT_CONVERGED;
+        if (bad < 0) bad = c;
       }
     if (bad >= 0)
-      throw H2Error(H2_ERR_NOT_CONVERGED, "PCG did not reach the tolerance (first: problem " + std::to_string(bad) + ")");
+      throw H2Error(H2_ERR_NOT_CONVERGED,
+                    "PCG did not reach the tolerance (first: right-hand side " + std::to_string(bad) + ")");
   });
 }
 

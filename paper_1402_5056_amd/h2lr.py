@@ -92,7 +92,8 @@ _SIG = {
     "h2_cholesky_launch": [_P(_vp), _i32, _P(h2_trunc), _P(_vp)],
     "h2_job_query": [_vp, _P(_i32)],
     "h2_job_finish": [_vp, _P(C.c_int)],
-    "h2_pcg_batched": [_P(_vp), _P(_vp), _P(_vp), _P(_vp), _i32, _d, _i32, _P(_i32), _P(_d), _P(C.c_int)],
+    "h2_pcg_batched": [_P(_vp), _P(_vp), _P(_vp), _P(_vp), _P(_i32), _i32, _d, _i32, _P(_i32), _P(_d),
+                       _P(C.c_int)],
     "h2_precond": [_vp, _vp, _vp, _i32],
     "h2_tri_invert": [_vp, _vp],
     "h2_mat_is_inverse": [_vp, _P(_i32)],
@@ -412,17 +413,25 @@ def h2_cholesky_launch(mats, tr: h2_trunc) -> Job:
 
 
 def h2_pcg_batched(csrs, mats, bs, xs, rtol: float = 1e-8, maxit: int = 500, check: bool = True):
-    """Returns (iters list, relres list, status list); raises H2Error for the
+    """bs[i], xs[i]: device float64 tensors of shape (n_i,) or (k_i, n_i)
+    (k_i right-hand sides, contiguous).  Returns (iters, relres, status),
+    flat lists with one entry per right-hand side; raises H2Error for the
     first failure when check is true."""
     k = len(mats)
     A = (_vp * k)(*[a.h for a in csrs])
     Ls = (_vp * k)(*[m.h for m in mats])
     B = (_vp * k)(*[_ptr(b) for b in bs])
     X = (_vp * k)(*[_ptr(x) for x in xs])
-    it = (_i32 * k)()
-    rel = (_d * k)()
-    st = (C.c_int * k)()
-    status = _lib.h2_pcg_batched(A, Ls, B, X, k, float(rtol), int(maxit), it, rel, st)
+    cols = [1 if b.dim() == 1 else b.shape[0] for b in bs]
+    for b, x, c in zip(bs, xs, cols):
+        if not (b.is_contiguous() and x.is_contiguous() and b.shape == x.shape):
+            raise H2Error(-1, "right-hand sides and solutions must be contiguous and of equal shape")
+    nr = (_i32 * k)(*cols)
+    tot = sum(cols)
+    it = (_i32 * tot)()
+    rel = (_d * tot)()
+    st = (C.c_int * tot)()
+    status = _lib.h2_pcg_batched(A, Ls, B, X, nr, k, float(rtol), int(maxit), it, rel, st)
     if check:
         _check(status)
     return list(it), list(rel), list(st)

@@ -16,11 +16,12 @@ Scheduling (host side only; every numerical step runs in the h2lr library):
   workgroup per problem) on a free slot, so launches made while others run
   overlap on the device;
 * completion: a finished launch is checked, and all right-hand sides of its
-  requests are solved by batched PCG (``h2_pcg_batched``: the preconditioner
-  applications of all systems in one launch per iteration);
-* release: device memory of finished requests is released when no launch is
-  in flight (freeing device memory waits for the device), and only then
-  returns to the budget.
+  requests are solved by one batched PCG (``h2_pcg_batched``: one CG
+  iteration per column; per iteration the preconditioner applications of
+  all requests, all columns of a request at once, in one launch);
+* release: device memory of finished requests returns to the budget when it
+  is freed: when no launch is in flight ("idle", the default: freeing device
+  memory may wait for the whole device), or at once ("eager").
 
 Latency of a request = completion time - arrival time.
 """
@@ -66,7 +67,7 @@ class Request:
 class Server:
     def __init__(self, budget_bytes: int, eps: float = 1e-4, eta: float = 2.0, leaf: int = 32,
                  rtol: float = 1e-8, maxit: int = 500, slots: int = 2, max_batch: int = 32,
-                 device: int = 0):
+                 device: int = 0, release: str = "idle"):
         self.budget = int(budget_bytes)
         self.tr = h2lr.trunc(eps, "block_rel", 32)
         self.eta, self.leaf, self.rtol, self.maxit = eta, leaf, rtol, maxit
@@ -78,6 +79,10 @@ class Server:
         self.peak = 0
         self.launches = 0
         self.max_inflight = 0
+        if release not in ("idle", "eager"):
+            raise ValueError("release must be 'idle' or 'eager'")
+        self.release = release
+        self.release_s = 0.0           # host time spent freeing device memory
 
     # ------------------------------------------------------------ helpers
     def _estimate(self, r: Request) -> int:
@@ -96,34 +101,34 @@ class Server:
         r._csr = h2lr.h2_csr_create(ctx, r.A)
 
     def _release(self, r: Request):
+        t = time.perf_counter()
         for name in ("_L", "_csr", "_bt", "_ct"):
             obj = getattr(r, name)
             if obj is not None:
                 obj.close()
             setattr(r, name, None)
         self.used -= r.nbytes
+        self.release_s += time.perf_counter() - t
 
     def _solve(self, reqs, slot: int):
-        """All right-hand sides of the finished requests by batched PCG: round
-        j solves column j of every request that has more than j columns."""
+        """All right-hand sides of the finished requests in one batched PCG
+        (each request's columns share its preconditioner applications)."""
         stream = self.streams[slot]
         with torch.cuda.stream(stream):
-            for r in reqs:
-                r.result = np.zeros_like(r.B)
-                r.iters = []
-            nmax = max(r.B.shape[1] for r in reqs)
-            for j in range(nmax):
-                act = [r for r in reqs if r.B.shape[1] > j]
-                bs = [torch.tensor(np.ascontiguousarray(r.B[:, j]), device="cuda") for r in act]
-                xs = [torch.zeros_like(b) for b in bs]
-                stream.synchronize()
-                its, _, codes = h2lr.h2_pcg_batched([r._csr for r in act], [r._L for r in act], bs, xs,
-                                                    self.rtol, self.maxit, check=False)
-                for r, x, it, c in zip(act, xs, its, codes):
-                    r.result[:, j] = x.cpu().numpy()
-                    r.iters.append(it)
-                    if c != 0 and r.status != "failed":
-                        r.status, r.error = "failed", h2lr.STATUS.get(c, str(c))
+            bs = [torch.tensor(np.ascontiguousarray(r.B.T), device="cuda") for r in reqs]
+            xs = [torch.zeros_like(b) for b in bs]
+            stream.synchronize()
+            its, _, codes = h2lr.h2_pcg_batched([r._csr for r in reqs], [r._L for r in reqs], bs, xs,
+                                                self.rtol, self.maxit, check=False)
+            pos = 0
+            for r, x in zip(reqs, xs):
+                k = r.B.shape[1]
+                r.result = np.ascontiguousarray(x.cpu().numpy().T)
+                r.iters = its[pos:pos + k]
+                bad = [c for c in codes[pos:pos + k] if c != 0]
+                if bad and r.status != "failed":
+                    r.status, r.error = "failed", h2lr.STATUS.get(bad[0], str(bad[0]))
+                pos += k
 
     # --------------------------------------------------------------- loop
     def run(self, requests, poll: float = 5e-4, log=None):
@@ -143,7 +148,7 @@ class Server:
                 waiting.append(pending[nxt])
                 nxt += 1
             # release finished requests when nothing is in flight
-            if to_release and not jobs:
+            if to_release and (not jobs or self.release == "eager"):
                 for r in to_release:
                     self._release(r)
                 to_release = []

@@ -201,3 +201,39 @@ def test_launch_overlapping_streams(lib):
             lib.h2_cholesky(Ms, tr)
             n = A.shape[0]
             assert np.array_equal(dense_via_matvec(lib, M, n), dense_via_matvec(lib, Ms, n))
+
+
+def test_pcg_batched_multi_rhs(lib):
+    """Several right-hand sides per system: one CG iteration per column, the
+    columns of a system share its preconditioner launches; each column
+    matches the single-column solve (iteration count, solution within
+    1e-12 relative)."""
+    print("case: batched pcg with 1, 5 and 16 right-hand sides", flush=True)
+    torch = gpu()
+    ctx = lib.h2_ctx_create(0)
+    tr = lib.trunc(1e-4, "block_rel", 32)
+    probs = []
+    for (side, sg, leaf), k in zip(((16, 7, 8), (24, 3, 16), (32, 4, 32)), (1, 5, 16)):
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False)
+        M = lib.h2_mat_from_csr(ctx, bt, A, lower=True)
+        B = w.gaussian(A.shape[0], k, 50 + side)
+        probs.append((A, M, lib.h2_csr_create(ctx, A), B))
+    lib.h2_cholesky_batched([q[1] for q in probs], tr)
+    bs = [torch.tensor(np.ascontiguousarray(q[3].T), device="cuda") for q in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    its, rels, codes = lib.h2_pcg_batched([q[2] for q in probs], [q[1] for q in probs], bs, xs, 1e-10, 200)
+    assert len(its) == 22 and codes == [0] * 22
+    pos = 0
+    for (A, M, csr, B), b, x in zip(probs, bs, xs):
+        X = x.cpu().numpy().T
+        for c in range(B.shape[1]):
+            b1 = torch.tensor(B[:, c], device="cuda")
+            x1 = torch.zeros_like(b1)
+            it1, _, ok = lib.h2_pcg(csr, M, b1, x1, 1e-10, 200)
+            x1 = x1.cpu().numpy()
+            err = np.linalg.norm(X[:, c] - x1) / np.linalg.norm(x1)
+            assert ok and its[pos] == it1, (pos, its[pos], it1)
+            assert err < 1e-12, (pos, err)
+            assert np.linalg.norm(B[:, c] - A @ X[:, c]) / np.linalg.norm(B[:, c]) < 1e-9
+            pos += 1
+    print(f"  iterations per column {its}", flush=True)
