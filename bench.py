@@ -75,6 +75,27 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_traffic.md")
+
+
+def measured_traffic(args):
+    """HBM bytes of one factorisation launch from the committed device-counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), for the
+    default workload only; None otherwise or when the summary is absent."""
+    default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
+               and args.sigma_seed == "10")
+    if not default:
+        return None
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                if line.startswith("traffic_bytes_per_factorisation:"):
+                    return float(line.split(":", 1)[1])
+    except OSError:
+        return None
+    return None
+
+
 def sigma_seed(args):
     return None if args.sigma_seed.lower() == "none" else int(args.sigma_seed)
 
@@ -464,7 +485,8 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args),
+            "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT) if measured_traffic(args) else None,
             "flops_per_launch": chol_flops,
         },
     }
