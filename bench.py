@@ -58,6 +58,8 @@ def parse():
                          "from --batch-sides, piecewise-constant sigma), factorised in one launch, "
                          "then one PCG solve each")
     ap.add_argument("--batch-sides", type=str, default="64,96,128,192,256")
+    ap.add_argument("--batch-updates", type=int, default=4, help="low-rank updates per problem (0..4)")
+    ap.add_argument("--batch-update-rank", type=int, default=16)
     ap.add_argument("--serve", type=int, default=0,
                     help="serving form instead: this many setup+solve requests with Poisson "
                          "arrivals (--serve-rate per second), grid sides from --serve-sides, "
@@ -161,7 +163,8 @@ def cpu_baseline(args, n_target: int):
 def bench_batch(args):
     """Batched form: independent problems of mixed sizes, one workgroup each
     in one interpreter launch.  A step resets every factor to its H^2(A),
-    factorises all of them in one launch (setup) and solves every system by
+    factorises all of them in one launch (setup) while the low-rank updates
+    of full-storage copies run in a second launch on another stream, and solves every system by
     PCG in lockstep (the preconditioner applications of all systems in one
     launch per iteration).  The sequential comparison is measured too: one single-problem
     factorisation per distinct grid side, summed over the batch's sides."""
@@ -173,40 +176,71 @@ def bench_batch(args):
     sides_all = [int(v) for v in args.batch_sides.split(",")]
     rng = np.random.default_rng(1000)
     sides = [int(v) for v in rng.choice(sides_all, size=args.batch)]
-    stream = torch.cuda.current_stream()
+    # own (non-blocking) streams: work on the legacy default stream would
+    # serialise with the synchronous uploads of the other launch
+    stream = torch.cuda.Stream()
     ctx = h2lr.h2_ctx_create(0, stream.cuda_stream)
     tr = h2lr.trunc(args.eps, "block_rel", 32)
+    # the low-rank updates work on full-storage copies of H^2(A) on a second
+    # stream, concurrently with the factorisations
+    ustream = torch.cuda.Stream()
+    uctx = h2lr.h2_ctx_create(0, ustream.cuda_stream)
     probs = []
     for i, side in enumerate(sides):
         p = w.problem(side, sigma_seed=1000 + i, rhs_seed=2000 + i)
         ct = h2lr.h2_ctree_build(ctx, p["coords"], 32)
         bt = h2lr.h2_btree_build(ctx, ct, args.eta)
         A0 = h2lr.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
+        uct = h2lr.h2_ctree_build(uctx, p["coords"], 32)
+        ubt = h2lr.h2_btree_build(uctx, uct, args.eta)
+        U0 = h2lr.h2_mat_from_csr(uctx, ubt, p["A"], lower=False)
+        ex = h2lr.h2_btree_export(ubt)
+        tree = h2lr.h2_ctree_export(uct)
+        sons = [b for b in range(len(ex["parent"])) if ex["parent"][b] == 0]
+        ups = []
+        for j, b in enumerate(sons[:args.batch_updates]):
+            mt, ms_ = int(tree["size"][ex["row"][b]]), int(tree["size"][ex["col"][b]])
+            X = w.gaussian(mt, args.batch_update_rank, 3000 + 8 * i + j)
+            Y = w.gaussian(ms_, args.batch_update_rank, 4000 + 8 * i + j)
+            ups.append((b, torch.tensor(np.ascontiguousarray(X.T), device="cuda").t(),
+                        torch.tensor(np.ascontiguousarray(Y.T), device="cuda").t()))
+        bvec = torch.tensor(p["b"], device="cuda")
         probs.append({"p": p, "A0": A0, "L": h2lr.h2_mat_copy(A0), "csr": h2lr.h2_csr_create(ctx, p["A"]),
-                      "b": torch.tensor(p["b"], device="cuda")})
+                      "b": bvec, "x": torch.zeros_like(bvec), "U0": U0, "U": h2lr.h2_mat_copy(U0),
+                      "ups": ups})
+    torch.cuda.synchronize()
     ntot = sum(q["p"]["A"].shape[0] for q in probs)
     print(f"[bench] batch of {args.batch} problems, sides {sides}, total n = {ntot}", file=sys.stderr, flush=True)
     mats = [q["L"] for q in probs]
 
+    umats = [q["U"] for q in probs]
+
     def step():
         for q in probs:
             h2lr.h2_mat_assign(q["L"], q["A0"])
+            h2lr.h2_mat_assign(q["U"], q["U0"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h2lr.h2_cholesky_batched(mats, tr)
+        job = h2lr.h2_cholesky_launch(mats, tr)             # factorisations, stream 1
+        if args.batch_updates > 0:                         # updates, stream 2, meanwhile
+            h2lr.h2_lowrank_update_batched(umats, [q["ups"] for q in probs], tr)
+        tu = time.perf_counter()
+        job.finish()
         t1 = time.perf_counter()
-        for q in probs:
-            q["x"] = torch.zeros_like(q["b"])
+        times["updates"].append(tu - t0)
         # all systems in lockstep, preconditioner applications in one launch
+        # (the solver clears x itself)
         its, _, _ = h2lr.h2_pcg_batched([q["csr"] for q in probs], mats, [q["b"] for q in probs],
                                         [q["x"] for q in probs], args.rtol, 500)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, its
 
+    times = {"updates": []}
     for i in range(args.warmup):
         step()
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+    times["updates"].clear()
     setup, solve, iters = [], [], None
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -244,9 +278,15 @@ def bench_batch(args):
         "config": {"workload": f"{args.batch} independent P1 FEM problems on the unit square, grid sides "
                                f"drawn from {{{args.batch_sides}}} (seed 1000), sigma 8x8 subdomains "
                                f"log-uniform [1e-2,1e2] (seed 1000+i), bisection cluster tree leaf 32, "
-                               f"eta {args.eta:g}, block-relative eps {args.eps}, batched H2-Cholesky in one "
-                               f"launch + batched PCG 1 Gaussian RHS each to {args.rtol}",
+                               f"eta {args.eta:g}, block-relative eps {args.eps}; per problem {args.batch_updates} "
+                               f"rank-{args.batch_update_rank} Gaussian updates of the root's son blocks of a "
+                               f"full-storage copy (one launch, concurrent with) the batched H2-Cholesky "
+                               f"(one launch), then batched PCG 1 Gaussian RHS each to {args.rtol}",
                    "problems": args.batch, "total_n": ntot, "precision": "fp64", "parallelism": "1 GPU"},
+        "updates_per_problem": min(args.batch_updates, 4),
+        "update_rank": args.batch_update_rank,
+        "updates_done_s": float(np.median(times["updates"])) if times["updates"] else None,
+        "update_max_rank": max(h2lr.h2_mat_stats(q["U"])[1] for q in probs),
         "batched_setup_s": setup_s,
         "setup_problems_per_s": args.batch / setup_s,
         "sequential_setup_s_estimate": seq,

@@ -68,6 +68,7 @@ typedef struct {
 #define H2_MAX_LEAF 32       /* largest leaf cluster                          */
 #define H2_MAX_COLS 64       /* right-hand sides of one matvec / solve        */
 #define H2_MAX_UPDATE_RANK 32 /* columns of a low-rank update factor          */
+#define H2_MAX_BATCH_UPDATES 4 /* updates per matrix in one batched call      */
 
 /* ---------------------------------------------------------------- context */
 /* device: HIP device ordinal, or -1 for a host-only context that can build
@@ -186,6 +187,20 @@ h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n);
  * is poisoned (H2_ERR_STATE on later calls). */
 h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X, int64_t ldx,
                             const double *Y, int64_t ldy, const h2_trunc *tr);
+
+/* Local low-rank updates of count distinct matrices in one launch (one
+ * workgroup per matrix; each matrix's updates run in order with the
+ * arithmetic of h2_lowrank_update, so the results equal the single calls).
+ * Matrix i receives nupd[i] (0..H2_MAX_BATCH_UPDATES) updates, taken in order
+ * from the flat host arrays blocks, ks, Xs, ldxs, Ys, ldys (argument meaning
+ * as for h2_lowrank_update); the matrices share one device and stream.
+ * Arguments are checked before any device work.  status: optional, count
+ * entries; a matrix whose update fails (H2_ERR_RANK_CAP) is poisoned, the
+ * others are updated, the first failure is returned.  Blocks until done. */
+h2_status h2_lowrank_update_batched(h2_mat *mats, int32_t count, const int32_t *nupd, const int64_t *blocks,
+                                   const int32_t *ks, const double *const *Xs, const int64_t *ldxs,
+                                   const double *const *Ys, const int64_t *ldys, const h2_trunc *tr,
+                                   h2_status *status);
 
 /* y = alpha op(Z) x + beta y, op = identity (trans = 0) or transpose.
  * x, y: device, n x nrhs column-major (leading dimension n), original order,

@@ -304,6 +304,7 @@ struct h2_mat_s {
   DevEnv env_uploaded{};
   bool env_valid = false;
   TaskList chol, prec, tinv, prec_inv;
+  TaskList upd;           // the last batched update's list (storage reused: no frees)
   bool inverse = false;   // holds G ~ L^{-1} (h2_tri_invert) instead of a factor L
   DevEnv env{};
 };
@@ -364,7 +365,7 @@ static size_t mat_bytes_now(const h2_mat_s &m) {
   }
   add(m.d_bcols); add(m.d_err); add(m.d_S); add(m.d_N); add(m.d_xh); add(m.d_yh); add(m.d_buf);
   add(m.d_pcg); add(m.d_prof); add(m.d_flops); add(m.d_wscr); add(m.d_env);
-  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv}) { add(tl->d); add(tl->aux); }
+  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv, &m.upd}) { add(tl->d); add(tl->aux); }
   return b;
 }
 
@@ -828,6 +829,19 @@ static void upload_tasks(h2_mat_s &m, TaskList &tl, const std::vector<Task> &tas
   if (!tasks.empty())
     HIPCHK(hipMemcpy(tl.d.p, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
   tl.aux.alloc(aux.size());
+  if (!aux.empty())
+    HIPCHK(hipMemcpy(tl.aux.p, aux.data(), aux.size() * sizeof(int), hipMemcpyHostToDevice));
+  tl.count = (int)tasks.size();
+  tl.built = true;
+}
+
+// As upload_tasks, but keeps the device arrays when they are large enough:
+// freeing device memory would wait for every stream of the device.
+static void upload_tasks_reuse(TaskList &tl, const std::vector<Task> &tasks, const std::vector<int> &aux) {
+  if (tl.d.n < tasks.size()) tl.d.alloc(tasks.size());
+  if (!tasks.empty())
+    HIPCHK(hipMemcpy(tl.d.p, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
+  if (tl.aux.n < aux.size()) tl.aux.alloc(aux.size());
   if (!aux.empty())
     HIPCHK(hipMemcpy(tl.aux.p, aux.data(), aux.size() * sizeof(int), hipMemcpyHostToDevice));
   tl.count = (int)tasks.size();
@@ -1338,13 +1352,16 @@ static void launch_batch(Dev<BatchItem> &d_items, const std::vector<BatchItem> &
 }
 
 // Checks of a batch: distinct matrices, usable, on one device and stream.
-static std::vector<h2_mat_s *> batch_members(h2_mat *mats, int32_t count, const char *what) {
+static std::vector<h2_mat_s *> batch_members(h2_mat *mats, int32_t count, const char *what,
+                                             bool factors = true) {
   REQUIRE(mats != nullptr && count >= 1, "need at least one matrix");
   std::vector<h2_mat_s *> ms(mats, mats + count);
   for (h2_mat_s *m : ms) {
     require_ok(m);
-    REQUIRE(m->lower, (std::string(what) + " needs matrices created with lower != 0").c_str());
-    REQUIRE(!m->inverse, (std::string(what) + " on an inverted factor").c_str());
+    if (factors) {
+      REQUIRE(m->lower, (std::string(what) + " needs matrices created with lower != 0").c_str());
+      REQUIRE(!m->inverse, (std::string(what) + " on an inverted factor").c_str());
+    }
     REQUIRE(m->ctx->device == ms[0]->ctx->device && m->ctx->stream == ms[0]->ctx->stream,
             "all matrices of a batch must share one device and stream");
   }
@@ -1444,6 +1461,74 @@ h2_status h2_job_finish(h2_job job, h2_status *status) {
     HIPCHK(hipEventSynchronize(j->done));
     for (h2_mat_s *m : j->ms) m->busy = false;
     batch_errors(j->ms, status);
+  });
+}
+
+h2_status h2_lowrank_update_batched(h2_mat *mats, int32_t count, const int32_t *nupd, const int64_t *blocks,
+                                   const int32_t *ks, const double *const *Xs, const int64_t *ldxs,
+                                   const double *const *Ys, const int64_t *ldys, const h2_trunc *tr,
+                                   h2_status *status) {
+  return guarded([&] {
+    REQUIRE(nupd && blocks && ks && Xs && ldxs && Ys && ldys, "null argument");
+    std::vector<h2_mat_s *> ms = batch_members(mats, count, "h2_lowrank_update_batched", false);
+    if (status)
+      for (int i = 0; i < count; ++i) status[i] = H2_OK;
+    // validate everything before any device work
+    int u0 = 0;
+    for (int i = 0; i < count; ++i) {
+      const h2_mat_s &z = *ms[i];
+      const h2_btree_s &bt = *z.bt;
+      const h2_ctree_s &ct = *bt.ct;
+      REQUIRE(nupd[i] >= 0 && nupd[i] <= H2_MAX_BATCH_UPDATES, "updates per matrix out of range");
+      for (int u = u0; u < u0 + nupd[i]; ++u) {
+        REQUIRE(blocks[u] >= 0 && blocks[u] < bt.nb, "block out of range");
+        REQUIRE(ks[u] >= 0 && ks[u] <= H2_MAX_UPDATE_RANK, "update rank out of range");
+        const int t0 = bt.row[blocks[u]], s0 = bt.col[blocks[u]];
+        if (z.lower) REQUIRE(t0 == s0 || ct.offset[t0] > ct.offset[s0], "block above the diagonal of a lower matrix");
+        if (ks[u] == 0) continue;
+        REQUIRE(Xs[u] && Ys[u], "null factor");
+        REQUIRE(ldxs[u] >= ct.size[t0] && ldys[u] >= ct.size[s0], "leading dimension too small");
+      }
+      u0 += nupd[i];
+    }
+    hipStream_t s = ms[0]->ctx->stream;
+    std::vector<BatchItem> items(count);
+    u0 = 0;
+    for (int i = 0; i < count; ++i) {
+      h2_mat_s &z = *ms[i];
+      const h2_btree_s &bt = *z.bt;
+      const h2_ctree_s &ct = *bt.ct;
+      set_trunc(z, tr);
+      std::vector<Task> tasks;
+      Planner P(z, tasks);
+      // update j's factors go to the j-th pair of product temporaries, which
+      // the local update itself leaves untouched; the updates run in order
+      for (int j = 0; j < nupd[i]; ++j) {
+        const int u = u0 + j, k = ks[u];
+        if (k == 0) continue;
+        const int b = (int)blocks[u], t0 = bt.row[b], s0 = bt.col[b];
+        const int bu = B_T0U + 2 * j, bv = B_T0V + 2 * j;
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[t0] * k)), dim3(256), 0, s, ct.size[t0],
+                           ct.offset[t0], k, (const int64_t *)nullptr, Xs[u], (long)ldxs[u], z.env.buf[bu],
+                           z.d_bcols.p, bu);
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[s0] * k)), dim3(256), 0, s, ct.size[s0],
+                           ct.offset[s0], k, (const int64_t *)nullptr, Ys[u], (long)ldys[u], z.env.buf[bv],
+                           z.d_bcols.p, bv);
+        HIPCHK(hipGetLastError());
+        P.addlr(b, bu, bv);
+      }
+      upload_tasks_reuse(z.upd, tasks, P.aux);
+      sync_env(z);
+      items[i] = BatchItem{z.upd.d.p, z.d_env.p, z.upd.aux.p, z.upd.count, 0};
+      u0 += nupd[i];
+    }
+    struct ItemsGuard {
+      Dev<BatchItem> *d; hipStream_t s;
+      ~ItemsGuard() { (void)hipStreamSynchronize(s); items_release(d); }
+    } guard{items_acquire(count), s};
+    launch_batch(*guard.d, items, NT, s);
+    HIPCHK(hipStreamSynchronize(s));
+    batch_errors(ms, status);
   });
 }
 

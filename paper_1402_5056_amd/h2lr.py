@@ -89,6 +89,8 @@ _SIG = {
     "h2_matvec": [_vp, _i32, _d, _vp, _d, _vp, _i32],
     "h2_cholesky": [_vp, _P(h2_trunc)],
     "h2_cholesky_batched": [_P(_vp), _i32, _P(h2_trunc), _P(C.c_int)],
+    "h2_lowrank_update_batched": [_P(_vp), _i32, _P(_i32), _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp),
+                                  _P(_i64), _P(h2_trunc), _P(C.c_int)],
     "h2_cholesky_launch": [_P(_vp), _i32, _P(h2_trunc), _P(_vp)],
     "h2_job_query": [_vp, _P(_i32)],
     "h2_job_finish": [_vp, _P(C.c_int)],
@@ -364,6 +366,32 @@ def h2_mat_bytes(m: Mat) -> int:
     v = _i64()
     _check(_lib.h2_mat_bytes(m.h, C.byref(v)))
     return v.value
+
+
+def h2_lowrank_update_batched(mats, updates, tr: h2_trunc, check: bool = True):
+    """updates[i]: list of (block, X, Y) for mats[i] (at most 4), X, Y
+    column-major device tensors as for h2_lowrank_update.  Returns the
+    per-matrix status list."""
+    k = len(mats)
+    flat = [u for ups in updates for u in ups]
+    nu = len(flat)
+
+    def ld(T):
+        return T.stride(1) if T.shape[1] > 1 else T.shape[0]
+    arr = (_vp * k)(*[m.h for m in mats])
+    nupd = (_i32 * k)(*[len(u) for u in updates])
+    blocks = (_i64 * max(nu, 1))(*[int(b) for b, _, _ in flat])
+    ks = (_i32 * max(nu, 1))(*[int(X.shape[1]) for _, X, _ in flat])
+    Xs = (_vp * max(nu, 1))(*[_ptr(X) for _, X, _ in flat])
+    Ys = (_vp * max(nu, 1))(*[_ptr(Y) for _, _, Y in flat])
+    ldx = (_i64 * max(nu, 1))(*[ld(X) for _, X, _ in flat])
+    ldy = (_i64 * max(nu, 1))(*[ld(Y) for _, _, Y in flat])
+    st = (C.c_int * k)()
+    status = _lib.h2_lowrank_update_batched(arr, k, nupd, blocks, ks, Xs, ldx, Ys, ldy, C.byref(tr), st)
+    codes = list(st)
+    if check:
+        _check(status)
+    return codes
 
 
 def h2_cholesky_batched(mats, tr: h2_trunc):

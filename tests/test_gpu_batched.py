@@ -237,3 +237,70 @@ def test_pcg_batched_multi_rhs(lib):
             assert np.linalg.norm(B[:, c] - A @ X[:, c]) / np.linalg.norm(B[:, c]) < 1e-9
             pos += 1
     print(f"  iterations per column {its}", flush=True)
+
+
+def test_update_batched_equals_single_and_oracle(lib):
+    """Up to four local updates per matrix, all matrices in one launch: each
+    result equals the single h2_lowrank_update calls in the same order bit
+    for bit, and the oracle's sequence of updates within 1e-12."""
+    from oracle.update import addlr as o_addlr
+    from tests.helpers import to_dev_cols
+    print("case: batched low-rank updates (sides 24, 32, 40; 4, 3, 4 updates)", flush=True)
+    ctx = lib.h2_ctx_create(0)
+    eps = 1e-6
+    tr = lib.trunc(eps, "block_rel", 32)
+    tp = TruncParams(eps, "block_rel", 32)
+    mats, singles, updates, refs = [], [], [], []
+    for (side, sg, leaf), nup in zip(((24, 3, 16), (32, 4, 32), (40, 7, 24)), (4, 3, 4)):
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False)
+        mats.append(lib.h2_mat_from_csr(ctx, bt, A))
+        singles.append(lib.h2_mat_from_csr(ctx, bt, A))
+        oc = build_cluster_tree(p["coords"], leaf)
+        ob = build_block_tree(oc, 2.0)
+        sons = [b for b in range(ob.nb) if ob.parent[b] == 0]
+        ups, Z = [], o_from_csr(A, oc, ob)
+        for j in range(nup):
+            b = sons[j % len(sons)]
+            t, s = int(ob.row[b]), int(ob.col[b])
+            X = w.gaussian(int(oc.size[t]), 3 + j, 300 + side + j) * np.logspace(0, -3, 3 + j)
+            Y = w.gaussian(int(oc.size[s]), 3 + j, 400 + side + j)
+            margins = []
+            o_addlr(Z, b, X, Y, tp, margins)
+            assert not margins or min(margins) > 1e-8, "seed too close to the truncation threshold"
+            ups.append((b, to_dev_cols(X), to_dev_cols(Y)))
+        updates.append(ups)
+        refs.append((A.shape[0], oc, Z))
+    codes = lib.h2_lowrank_update_batched(mats, updates, tr)
+    assert codes == [0, 0, 0]
+    for M, Ms, ups, (n, oc, Z) in zip(mats, singles, updates, refs):
+        for b, X, Y in ups:
+            lib.h2_lowrank_update(Ms, b, X, Y, tr)
+        D = dense_via_matvec(lib, M, n)
+        assert np.array_equal(D, dense_via_matvec(lib, Ms, n))
+        err = rel2(D, to_original(o_to_dense(Z), oc.perm))
+        print(f"  n={n}: ||Z_batch - Z_oracle||_2 / ||Z_oracle||_2 = {err:.3e}", flush=True)
+        assert err < TOL
+
+
+def test_update_batched_argument_errors(lib):
+    print("case: batched update argument errors", flush=True)
+    from tests.helpers import to_dev_cols
+    ctx = lib.h2_ctx_create(0)
+    p, A, bt = _problem(lib, ctx, 16, 7, 8, 2.0, False)
+    M = lib.h2_mat_from_csr(ctx, bt, A)
+    L = lib.h2_mat_from_csr(ctx, bt, A, lower=True)
+    X = to_dev_cols(w.gaussian(225, 2, 1))
+    tr = lib.trunc(1e-6)
+    bad = [([M], [[(10 ** 6, X, X)]]),                 # block out of range
+           ([M], [[(0, X, X)] * 5]),                   # more than four updates
+           ([M, M], [[(0, X, X)], [(0, X, X)]])]      # same matrix twice
+    for mats, ups in bad:
+        with pytest.raises(lib.H2Error) as ei:
+            lib.h2_lowrank_update_batched(mats, ups, tr)
+        assert ei.value.name == "H2_ERR_ARG"
+    # above the diagonal of a lower-stored matrix
+    ex = lib.h2_btree_export(bt)
+    above = next(b for b in range(len(ex["row"])) if ex["row"][b] < ex["col"][b])
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_lowrank_update_batched([L], [[(above, X, X)]], tr)
+    assert ei.value.name == "H2_ERR_ARG"
