@@ -418,6 +418,12 @@ class Job:
         _check(_lib.h2_job_query(self.h, C.byref(v)))
         return bool(v.value)
 
+    def __del__(self):
+        # an unfinished job still holds its matrices: wait and release them
+        if getattr(self, "h", None) is not None and _lib is not None:
+            h, self.h = self.h, None
+            _lib.h2_job_finish(h, None)
+
     def finish(self, check: bool = True):
         """Per-matrix status list; raises H2Error for the first failure when
         check is true."""

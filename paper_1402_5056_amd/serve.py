@@ -169,7 +169,14 @@ class Server:
                 if len(admitted[slot]) >= self.max_batch:
                     break
                 waiting.pop(0)
-                self._materialise(r, slot)
+                try:
+                    self._materialise(r, slot)
+                except h2lr.H2Error as e:          # e.g. the device is out of memory
+                    r.status, r.error, r.t_done = "failed", str(e), time.perf_counter() - t0
+                    self._release(r)
+                    self.used += r.nbytes          # _release subtracted what was never added
+                    done += 1
+                    continue
                 self.used += r.nbytes
                 self.peak = max(self.peak, self.used)
                 r.status, r.t_admit = "admitted", time.perf_counter() - t0
