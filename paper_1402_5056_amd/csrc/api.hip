@@ -1122,6 +1122,7 @@ h2_status h2_mat_assign(h2_mat dst, h2_mat src) {
   return guarded([&] {
     REQUIRE(dst && src, "null argument");
     require_ok(src);
+    REQUIRE(!dst->busy, "matrix belongs to an unfinished batch (finish its job first)");
     REQUIRE(dst->bt == src->bt && dst->lower == src->lower, "matrices have different structure");
     hipStream_t s = dst->ctx->stream;
     auto cp = [&](auto &to, auto &from) {
