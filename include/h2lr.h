@@ -260,6 +260,13 @@ h2_status h2_mat_is_inverse(h2_mat m, int32_t *inverse);
  * r, z: device, n x nrhs, original order; r and z may alias. */
 h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs);
 
+/* One triangular solve with a Cholesky factor (Section 3, block forward
+ * substitution with vector right-hand sides): z = L^{-1} r (trans = 0) or
+ * z = L^{-*} r (trans = 1); h2_precond is the two in sequence.  r, z:
+ * device, n x nrhs, original order (may alias), 1 <= nrhs <= H2_MAX_COLS.
+ * H2_ERR_ARG for a matrix that is not a (non-inverted) lower factor. */
+h2_status h2_trsv(h2_mat l, int32_t trans, const double *r, double *z, int32_t nrhs);
+
 /* ------------------------------------------------------- sparse A and PCG */
 /* Device copy of a CSR matrix (host arrays, original order). */
 h2_status h2_csr_create(h2_ctx ctx, int64_t n, const int64_t *rowptr, const int32_t *col,

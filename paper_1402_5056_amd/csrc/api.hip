@@ -305,6 +305,7 @@ struct h2_mat_s {
   bool env_valid = false;
   TaskList chol, prec, tinv, prec_inv;
   TaskList upd;           // the last batched update's list (storage reused: no frees)
+  TaskList trsv[2];       // forward (L) and backward (L^*) substitution alone
   bool inverse = false;   // holds G ~ L^{-1} (h2_tri_invert) instead of a factor L
   DevEnv env{};
 };
@@ -365,7 +366,10 @@ static size_t mat_bytes_now(const h2_mat_s &m) {
   }
   add(m.d_bcols); add(m.d_err); add(m.d_S); add(m.d_N); add(m.d_xh); add(m.d_yh); add(m.d_buf);
   add(m.d_pcg); add(m.d_prof); add(m.d_flops); add(m.d_wscr); add(m.d_env);
-  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv, &m.upd}) { add(tl->d); add(tl->aux); }
+  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv, &m.upd, &m.trsv[0], &m.trsv[1]}) {
+    add(tl->d);
+    add(tl->aux);
+  }
   return b;
 }
 
@@ -1634,6 +1638,29 @@ h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs) {
     REQUIRE(r && z, "null vector");
     REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
     precond_device(l, r, z, nrhs);
+    check_device_error(*l);
+  });
+}
+
+h2_status h2_trsv(h2_mat l, int32_t trans, const double *r, double *z, int32_t nrhs) {
+  return guarded([&] {
+    require_ok(l);
+    REQUIRE(l->lower, "h2_trsv needs a Cholesky factor");
+    REQUIRE(!l->inverse, "h2_trsv on an inverted factor");
+    REQUIRE(trans == 0 || trans == 1, "trans must be 0 or 1");
+    REQUIRE(r && z, "null vector");
+    REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
+    TaskList &tl = l->trsv[trans];
+    if (!tl.built) {
+      std::vector<Task> tasks;
+      Planner P(*l, tasks);
+      if (trans) P.bsolve_h2(0, B_X);
+      else P.fsolve_h2(0, B_X);
+      upload_tasks(*l, tl, tasks, P.aux);
+    }
+    prec_gather(l, r, nrhs);
+    run_tasks(*l, tl, PREC_THREADS);
+    prec_scatter(l, z, nrhs);
     check_device_error(*l);
   });
 }

@@ -97,6 +97,7 @@ _SIG = {
     "h2_pcg_batched": [_P(_vp), _P(_vp), _P(_vp), _P(_vp), _P(_i32), _i32, _d, _i32, _P(_i32), _P(_d),
                        _P(C.c_int)],
     "h2_precond": [_vp, _vp, _vp, _i32],
+    "h2_trsv": [_vp, _i32, _vp, _vp, _i32],
     "h2_tri_invert": [_vp, _vp],
     "h2_mat_is_inverse": [_vp, _P(_i32)],
     "h2_csr_create": [_vp, _i64, _vp, _vp, _vp, _P(_vp)],
@@ -479,6 +480,12 @@ def h2_mat_is_inverse(m: Mat) -> bool:
     v = _i32()
     _check(_lib.h2_mat_is_inverse(m.h, C.byref(v)))
     return bool(v.value)
+
+
+def h2_trsv(m: Mat, r, z, trans: bool = False):
+    """z = L^{-1} r (or L^{-*} r); r, z as for h2_precond."""
+    nrhs = 1 if r.dim() == 1 else r.shape[0]
+    _check(_lib.h2_trsv(m.h, 1 if trans else 0, _ptr(r), _ptr(z), nrhs))
 
 
 def h2_precond(m: Mat, r, z):
