@@ -81,3 +81,27 @@ def test_serve_budget_and_rejection(serve):
     for r in reqs[:3]:
         x = r.result[:, 0]
         assert np.linalg.norm(r.B[:, 0] - r.A @ x) / np.linalg.norm(r.B[:, 0]) < 1e-7
+
+
+def test_estimate_equals_allocation():
+    """h2_estimate_bytes (used for admission) equals the device bytes a new
+    matrix holds; task lists and PCG vectors come on top afterwards."""
+    print("case: byte estimate vs allocation", flush=True)
+    torch = gpu()
+    from paper_1402_5056_amd import h2lr
+    ctx = h2lr.h2_ctx_create(0)
+    for side, leaf, lower in ((24, 16, True), (32, 32, False)):
+        p = w.problem(side, sigma_seed=3, rhs_seed=1)
+        ct = h2lr.h2_ctree_build(ctx, p["coords"], leaf)
+        bt = h2lr.h2_btree_build(ctx, ct, 2.0)
+        est = h2lr.h2_estimate_bytes(bt, lower)
+        M = h2lr.h2_mat_from_csr(ctx, bt, p["A"], lower=lower)
+        assert h2lr.h2_mat_bytes(M) == est
+        if lower:
+            h2lr.h2_cholesky(M, h2lr.trunc(1e-4))
+            after = h2lr.h2_mat_bytes(M)
+            assert after > est
+            b = torch.tensor(p["b"], device="cuda")
+            x = torch.zeros_like(b)
+            h2lr.h2_pcg(h2lr.h2_csr_create(ctx, p["A"]), M, b, x, 1e-8, 100)
+            assert h2lr.h2_mat_bytes(M) > after
