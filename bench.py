@@ -13,6 +13,16 @@ in HBM before the timed region; trees and H^2(A) are built once outside it.
 
 Prints one JSON line.  ``value`` is steps (setup + solve) per second;
 ``setup_s`` and ``solves_per_s`` give the two halves of the metric.
+
+Other forms (each prints its own JSON line):
+  --batch P   P independent problems of mixed grid sides: one batched
+              factorisation launch, batched low-rank updates of full-storage
+              copies concurrently on a second stream, batched PCG; the
+              sequential comparison is measured per grid side.
+  --serve R   R setup+solve requests with Poisson arrivals, admitted by an
+              HBM budget, factorised in batched launches on several streams
+              (continuous batching), p50/p99 latency.
+  --precond inverse   triangular inverse of the factor, PCG with G^* G.
 """
 
 from __future__ import annotations
