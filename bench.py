@@ -384,7 +384,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs one factorisation on one GPU; multi-GPU runs are not "
+        print("bench.py: the factorisation runs on one GPU; multi-GPU runs are not "
               "supported (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

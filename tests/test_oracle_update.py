@@ -135,7 +135,7 @@ def test_single_block_is_eckart_young():
 def test_truncation_error_blockwise_bound(sq32):
     """After a truncated global update every admissible block keeps the
     blockwise relative error ||(Z_new - Z~)|_b||_2 <= 2 (p+1) eps ||Z~|_b||_F
-    (p = depth; the constant is this build's check, the paper prints none),
+    (p = depth; the constant is chosen by this test, the paper prints none),
     and the total error decreases with eps."""
     p, ct, bt = sq32
     base = from_csr(p["A"], ct, bt)
