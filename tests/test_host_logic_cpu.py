@@ -78,6 +78,17 @@ CHILD = textwrap.dedent(r'''
     r1 = np.zeros(n1)
     assert lib.h2_trsv(L1, C.c_int32(2), r1.ctypes.data_as(vp), r1.ctypes.data_as(vp), C.c_int32(1)) == -1
     ok(lib.h2_trsv(L1, C.c_int32(1), r1.ctypes.data_as(vp), r1.ctypes.data_as(vp), C.c_int32(1)))
+    # batched PCG: per-system column counts within [1, H2_MAX_COLS]
+    A1 = w.problem(16, sigma_seed=3, rhs_seed=1)["A"].tocsr()
+    rp = np.ascontiguousarray(A1.indptr, np.int64); ci = np.ascontiguousarray(A1.indices, np.int32)
+    vv = np.ascontiguousarray(A1.data); keep.extend([rp, ci, vv])
+    csr = vp(); ok(lib.h2_csr_create(ctx, C.c_int64(n1), rp.ctypes.data_as(vp), ci.ctypes.data_as(vp), vv.ctypes.data_as(vp), C.byref(csr)))
+    b = np.zeros(n1 * 65); x = np.zeros(n1 * 65)
+    As = (vp * 1)(csr.value); Ls = (vp * 1)(L1.value); bs = (vp * 1)(b.ctypes.data); xs1 = (vp * 1)(x.ctypes.data)
+    for k, want in ((65, -1), (0, -1), (3, 0)):
+        nr = (C.c_int32 * 1)(k)
+        got = lib.h2_pcg_batched(As, Ls, bs, xs1, nr, 1, C.c_double(1e-8), C.c_int32(10), None, None, None)
+        assert got == want, (k, got, lib.h2_last_error())
     print("host logic ok")
 ''')
 
