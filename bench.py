@@ -438,13 +438,13 @@ def main():
         evs[0].record(stream)
         h2lr.h2_cholesky(L, tr)
         evs[3].record(stream)
+        # h2_cholesky returns after its device work has finished; the
+        # counters of the factor are read here (two small copies) so that
+        # the factorisation is not run a second time for them
+        inv_info["chol_flops"] = h2lr.h2_mat_flops(L, reset=True)
+        inv_info["stats"] = h2lr.h2_mat_stats(L)
+        print("[bench]   factorisation done", file=sys.stderr, flush=True)
         if inverse:
-            # h2_cholesky returns after its device work has finished; the
-            # counters of the factor are read here (two small copies) so that
-            # the inversion is not run a second time for them
-            inv_info["chol_flops"] = h2lr.h2_mat_flops(L, reset=True)
-            inv_info["stats"] = h2lr.h2_mat_stats(L)
-            print("[bench]   factorisation done, inverting", file=sys.stderr, flush=True)
             h2lr.h2_tri_invert(L, tr)
             inv_info["inv_flops"] = h2lr.h2_mat_flops(L, reset=True)
         evs[1].record(stream)
@@ -479,16 +479,10 @@ def main():
     # flops of the factorisation alone (the PCG solve adds substitution flops)
     xres = x.cpu().numpy()
     true_rel = float(np.linalg.norm(p["b"] - p["A"] @ xres) / np.linalg.norm(p["b"]))
+    chol_flops = inv_info["chol_flops"]
+    stored, kr, kc = inv_info["stats"]
     if inverse:
-        chol_flops = inv_info["chol_flops"]
         inv_flops = inv_info["inv_flops"]
-        stored, kr, kc = inv_info["stats"]
-    else:
-        h2lr.h2_mat_flops(L, reset=True)
-        h2lr.h2_mat_assign(L, A0)
-        h2lr.h2_cholesky(L, tr)
-        chol_flops = h2lr.h2_mat_flops(L, reset=True)
-        stored, kr, kc = h2lr.h2_mat_stats(L)
     setup_s = float(np.median(setup_ms)) / 1e3
     chol_s = float(np.median(chol_ms)) / 1e3
     achieved_tflops = chol_flops / chol_s / 1e12

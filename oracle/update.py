@@ -35,7 +35,8 @@ The steps, in the paper's order and notation:
 Readings where the paper is silent:
 
 * Row and column bases are both recompressed from the same extended matrix
-  Z~ (the paper handles the column basis "similarly, replacing Z~ by Z~^*").
+  Z~; the column basis comes from the same construction applied to the
+  adjoint of the extended matrix (Section 4).
 * The weights of the predecessors of t0 are recomputed from the current
   state on every call.
 * The stored R-factors rho_t (needed for R_{W,s} outside the subtrees and for

@@ -122,6 +122,37 @@ def test_rk_truncated_addition():
     assert np.allclose(tmp.U @ tmp.V.T, total, atol=1e-12)
 
 
+
+@pytest.mark.parametrize("mode, kept, err", [("block_rel", 16, 0.15), ("const_rel", 17, 0.09)])
+def test_rk_truncation_rule_prescribed_spectrum(mode, kept, err):
+    """Truncated addition of the product temporaries (the H-matrix rule at the
+    end of Section 3): with a prescribed spectrum of the sum, exactly the
+    singular values above eps * ||sum||_F (block_rel) or eps * sigma_1
+    (const_rel) are kept, and the spectral error is the first dropped singular
+    value (Eckart-Young).  The spectrum makes the two thresholds select
+    different ranks (||sum||_F = 4.004, sigma_1 = 1, eps = 0.1)."""
+    ct = build_cluster_tree(w.grid_points(16, 2), 32)
+    t, r = 1, 2
+    nt, nr = int(ct.size[t]), int(ct.size[r])
+    rng = np.random.Generator(np.random.PCG64(11))
+    Q, _ = np.linalg.qr(rng.standard_normal((nt, 20)))
+    P, _ = np.linalg.qr(rng.standard_normal((nr, 20)))
+    sig = np.array([1.0] * 16 + [0.15, 0.09, 0.05, 0.01])
+    tp = TruncParams(0.1, mode, 64)
+    tmp = RkTemp(ct, t, r)
+    # first term: the leading 16 directions (nothing below either threshold)
+    tmp.add(Q[:, :16] * sig[:16], P[:, :16], t, r, tp)
+    assert tmp.U.shape[1] == 16
+    # second term: the sum now has the singular values sig
+    tmp.add(Q[:, 16:] * sig[16:], P[:, 16:], t, r, tp)
+    exact = (Q * sig) @ P.T
+    assert tmp.U.shape[1] == kept
+    e2 = np.linalg.norm(tmp.U @ tmp.V.T - exact, 2)
+    assert abs(e2 - err) < 1e-12
+    # the kept part is the best approximation of that rank
+    best = (Q[:, :kept] * sig[:kept]) @ P[:, :kept].T
+    assert np.linalg.norm(tmp.U @ tmp.V.T - best, 2) < 1e-12
+
 # ------------------------------------------------------- triangular inverse
 # Remark "Inversion" (end of Section 6) specialised to a lower triangular
 # factor.  Pins: without truncation the result is the dense inverse of the
