@@ -124,7 +124,9 @@ class _Chol:
     # ---------------------------------------------------------------- update
     def _addlr(self, b, U, V):
         self._count("addlr_calls")
-        if addlr(self.L, b, U, V, self.tp):
+        # optional diagnostics: stats["margins"] (a list) receives the
+        # threshold margins of every recompression (no effect on the result)
+        if addlr(self.L, b, U, V, self.tp, self.stats.get("margins")):
             self._count("addlr_done")
 
     def _emit_block(self, t, r, U, V):

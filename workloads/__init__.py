@@ -13,6 +13,7 @@ from .fem import (  # noqa: F401
     sigma_blocks_3d,
     fem2d_p1,
     fem3d_q1,
+    convection_x,
     gaussian,
     problem,
 )

@@ -142,6 +142,24 @@ def fem3d_q1(N: int, sigma: np.ndarray) -> sp.csr_matrix:
     return A
 
 
+def convection_x(N: int, c: float) -> sp.csr_matrix:
+    """First-order upwind difference c (u_i - u_{i-1}) along +x on the
+    interior nodes of the N x N grid (zero Dirichlet values): added to the
+    stiffness matrix it gives a non-symmetric matrix with the same stencil
+    reach, diagonally dominant for c >= 0."""
+    m = N - 1
+    I, J = np.meshgrid(np.arange(1, N), np.arange(1, N), indexing="xy")
+    I = I.ravel(); J = J.ravel()
+    idx = (I - 1) + m * (J - 1)
+    mask = I > 1
+    rows = np.concatenate([idx, idx[mask]])
+    cols = np.concatenate([idx, idx[mask] - 1])
+    vals = np.concatenate([np.full(idx.size, c), np.full(int(mask.sum()), -c)])
+    B = sp.coo_matrix((vals, (rows, cols)), shape=(m * m, m * m)).tocsr()
+    B.sort_indices()
+    return B
+
+
 def gaussian(n: int, k: int, seed: int) -> np.ndarray:
     """n x k standard normal matrix, drawn row by row in original index order."""
     return _rng(seed).standard_normal((n, k))
