@@ -283,6 +283,22 @@ h2_status h2_spmv(h2_csr a, const double *x, double *y);
 h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit,
                  int32_t *iters, double *relres);
 
+/* h2_pcg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * arguments, arithmetic and results as h2_pcg, but the PCG vectors, dot
+ * product partial sums and scalars live in a fixed device area owned by the
+ * library (one per device, 8 MiB, held until the process ends) instead of
+ * memory the factor allocates, and x is cleared by a fill kernel.  No
+ * device memory is allocated or freed.  Requirements, each an H2_ERR_ARG
+ * otherwise: n <= H2_NOALLOC_MAX_N; the factor's preconditioner task list
+ * already exists (made by the first h2_precond or h2_pcg call on l).
+ * Every call on one device uses the same area and overwrites what the last
+ * call left there; calls that overlap on one device (other host threads,
+ * other streams) race and must be serialised by the caller. */
+#define H2_NOALLOC_MAX_N 262144
+h2_status h2_pcg_noalloc(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit,
+                         int32_t *iters, double *relres);
+
 /* h2_pcg for count independent systems A_i X_i = B_i in lockstep on one
  * stream, each with nrhs[i] right-hand sides (one CG iteration per column):
  * the products and vector updates of each column are launched one after

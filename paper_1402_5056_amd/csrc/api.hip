@@ -923,6 +923,34 @@ static void require_ok(h2_mat m) {
   REQUIRE(!m->busy, "matrix belongs to an unfinished batch (finish its job first)");
 }
 
+// Fixed device work area of h2_pcg_noalloc: the PCG vectors r, z, p, q,
+// the partial sums of the dot products and the scalars of one system of at
+// most H2_NOALLOC_MAX_N unknowns.  Every device the library runs on holds
+// its own copy until the process ends; calls on one device share it.
+constexpr size_t NOALLOC_DOUBLES = (size_t)4 * H2_NOALLOC_MAX_N + 512;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+// Device address of this device's copy of scratch (looked up once per
+// device, with that device current; the host-side name of the array is not
+// a device address).
+static double *noalloc_scratch(int device) {
+  static std::mutex mu;
+  static std::unordered_map<int, double *> ptrs;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptrs.find(device);
+  if (it != ptrs.end()) return it->second;
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != device) HIPCHK(hipSetDevice(device));
+  void *ptr = nullptr;
+  const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != device) HIPCHK(hipSetDevice(cur));
+  if (rc != hipSuccess || !ptr)
+    throw H2Error(H2_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(rc));
+  ptrs[device] = static_cast<double *>(ptr);
+  return static_cast<double *>(ptr);
+}
+
 static int grid_for(long work) {
   long g = (work + 255) / 256;
   return (int)std::max<long>(1, std::min<long>(g, 4096));
@@ -1861,63 +1889,93 @@ h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double
   });
 }
 
+// PCG body shared by h2_pcg and h2_pcg_noalloc.  work: 4n + PCG_PART + 8
+// doubles (r, z, p, q, dot partial sums, scalars).  fill_kernel: clear x
+// with a fill kernel instead of hipMemsetAsync.
+constexpr int PCG_PART = 256;
+static void pcg_run(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit, int32_t *iters,
+                    double *relres, double *work, bool fill_kernel) {
+  const int n = (int)a->n;
+  hipStream_t s = l->ctx->stream;
+  const int NP = PCG_PART;
+  double *r = work, *z = r + n, *p = z + n, *q = p + n, *part = q + n, *sc = part + NP;
+  const int g = grid_for(n);
+  auto dot = [&](const double *u, const double *v, double *dst) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, n, u, v, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, part, dst);
+  };
+  auto host_scalar = [&](const double *dsrc) {
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, dsrc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return v;
+  };
+  if (fill_kernel) hipLaunchKernelGGL(k_fill_double, dim3(g), dim3(256), 0, s, x, n, 0.0);
+  else HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  dot(b, b, sc + 4);
+  const double nb = std::sqrt(host_scalar(sc + 4));
+  int it = 0;
+  double rel = 0.0;
+  if (nb == 0.0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return;
+  }
+  precond_device(l, r, z, 1);
+  HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  dot(r, z, sc + 0);
+  bool conv = false;
+  while (it < maxit) {
+    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(256), 0, s, n, a->rp.p, a->ci.p, a->v.p, p, q);
+    ++it;
+    dot(p, q, sc + 1);
+    hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, sc, p, q, x, r);
+    dot(r, r, sc + 3);
+    rel = std::sqrt(host_scalar(sc + 3)) / nb;
+    if (rel <= rtol) { conv = true; break; }
+    precond_device(l, r, z, 1);
+    dot(r, z, sc + 2);
+    hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, sc, z, p);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, sc + 0, sc + 2);
+  }
+  HIPCHK(hipGetLastError());
+  check_device_error(*l);
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  if (!conv) throw H2Error(H2_ERR_NOT_CONVERGED, "PCG did not reach the tolerance");
+}
+
+static void pcg_check_args(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit) {
+  REQUIRE(a && b && x, "null argument");
+  require_ok(l);
+  REQUIRE(l->lower, "h2_pcg needs a Cholesky factor");
+  REQUIRE(a->n == l->bt->ct->n, "size mismatch");
+  REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
+}
+
 h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit, int32_t *iters,
                  double *relres) {
   return guarded([&] {
-    REQUIRE(a && b && x, "null argument");
-    require_ok(l);
-    REQUIRE(l->lower, "h2_pcg needs a Cholesky factor");
-    REQUIRE(a->n == l->bt->ct->n, "size mismatch");
-    REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
-    const int n = (int)a->n;
-    hipStream_t s = l->ctx->stream;
-    const int NP = 256;   // partial sums of the dot products
-    if (l->d_pcg.n < (size_t)4 * n + NP + 8) l->d_pcg.alloc((size_t)4 * n + NP + 8);
-    double *r = l->d_pcg.p, *z = r + n, *p = z + n, *q = p + n, *part = q + n, *sc = part + NP;
-    const int g = grid_for(n);
-    auto dot = [&](const double *u, const double *v, double *dst) {
-      hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, n, u, v, part);
-      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, part, dst);
-    };
-    auto host_scalar = [&](const double *dsrc) {
-      double v = 0.0;
-      HIPCHK(hipMemcpyAsync(&v, dsrc, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      return v;
-    };
-    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    dot(b, b, sc + 4);
-    const double nb = std::sqrt(host_scalar(sc + 4));
-    int it = 0;
-    double rel = 0.0;
-    if (nb == 0.0) {
-      if (iters) *iters = 0;
-      if (relres) *relres = 0.0;
-      return;
-    }
-    precond_device(l, r, z, 1);
-    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    dot(r, z, sc + 0);
-    bool conv = false;
-    while (it < maxit) {
-      hipLaunchKernelGGL(k_spmv, dim3(g), dim3(256), 0, s, n, a->rp.p, a->ci.p, a->v.p, p, q);
-      ++it;
-      dot(p, q, sc + 1);
-      hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, sc, p, q, x, r);
-      dot(r, r, sc + 3);
-      rel = std::sqrt(host_scalar(sc + 3)) / nb;
-      if (rel <= rtol) { conv = true; break; }
-      precond_device(l, r, z, 1);
-      dot(r, z, sc + 2);
-      hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, sc, z, p);
-      hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, sc + 0, sc + 2);
-    }
-    HIPCHK(hipGetLastError());
-    check_device_error(*l);
-    if (iters) *iters = it;
-    if (relres) *relres = rel;
-    if (!conv) throw H2Error(H2_ERR_NOT_CONVERGED, "PCG did not reach the tolerance");
+    pcg_check_args(a, l, b, x, rtol, maxit);
+    const size_t need = (size_t)4 * a->n + PCG_PART + 8;
+    if (l->d_pcg.n < need) l->d_pcg.alloc(need);
+    pcg_run(a, l, b, x, rtol, maxit, iters, relres, l->d_pcg.p, false);
+  });
+}
+
+h2_status h2_pcg_noalloc(h2_csr a, h2_mat l, const double *b, double *x, double rtol, int32_t maxit,
+                         int32_t *iters, double *relres) {
+  return guarded([&] {
+    pcg_check_args(a, l, b, x, rtol, maxit);
+    REQUIRE(a->n <= H2_NOALLOC_MAX_N, "h2_pcg_noalloc: n = " + std::to_string(a->n) +
+                                          " exceeds the fixed work area of H2_NOALLOC_MAX_N = " +
+                                          std::to_string((long)H2_NOALLOC_MAX_N) + " unknowns");
+    const bool planned = l->inverse ? l->prec_inv.built : l->prec.built;
+    REQUIRE(planned && l->d_env.p,
+            "h2_pcg_noalloc: the preconditioner of this factor is not planned yet (its task list is "
+            "allocated by the first h2_precond or h2_pcg call on the factor)");
+    pcg_run(a, l, b, x, rtol, maxit, iters, relres, noalloc_scratch(l->ctx->device), true);
   });
 }
 

@@ -1749,6 +1749,10 @@ __global__ void k_fill_int(int *p, int n, int v) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = v;
 }
 
+__global__ void k_fill_double(double *p, int n, double v) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = v;
+}
+
 // CSR product y = A x (one thread per row).
 __global__ void k_spmv(int n, const int64_t *__restrict__ rp, const int *__restrict__ ci,
                        const double *__restrict__ v, const double *__restrict__ x, double *__restrict__ y) {

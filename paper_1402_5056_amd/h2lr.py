@@ -42,6 +42,7 @@ MAX_RANK = 32
 MAX_LEAF = 32
 MAX_COLS = 64
 MAX_UPDATE_RANK = 32
+NOALLOC_MAX_N = 262144
 MODES = {"block_rel": 0, "const_rel": 1, "none": 2}
 
 
@@ -104,6 +105,7 @@ _SIG = {
     "h2_csr_destroy": [_vp],
     "h2_spmv": [_vp, _vp, _vp],
     "h2_pcg": [_vp, _vp, _vp, _vp, _d, _i32, _P(_i32), _P(_d)],
+    "h2_pcg_noalloc": [_vp, _vp, _vp, _vp, _d, _i32, _P(_i32), _P(_d)],
 }
 for _name, _args in _SIG.items():
     _f = getattr(_lib, _name)
@@ -507,6 +509,14 @@ def h2_spmv(a: Csr, x, y):
 def h2_pcg(a: Csr, m: Mat, b, x, rtol: float = 1e-8, maxit: int = 1000):
     it, rel = _i32(), _d()
     st = _lib.h2_pcg(a.h, m.h, _ptr(b), _ptr(x), float(rtol), int(maxit), C.byref(it), C.byref(rel))
+    if st != H2_OK and st != -7:
+        _check(st)
+    return it.value, rel.value, st == H2_OK
+
+
+def h2_pcg_noalloc(a: Csr, m: Mat, b, x, rtol: float = 1e-8, maxit: int = 1000):
+    it, rel = _i32(), _d()
+    st = _lib.h2_pcg_noalloc(a.h, m.h, _ptr(b), _ptr(x), float(rtol), int(maxit), C.byref(it), C.byref(rel))
     if st != H2_OK and st != -7:
         _check(st)
     return it.value, rel.value, st == H2_OK

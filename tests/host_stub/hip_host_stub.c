@@ -17,6 +17,11 @@ hipError_t hipMemsetAsync(void *d, int v, size_t n, void *st) { memset(d, v, n);
 hipError_t hipStreamSynchronize(void *s) { return 0; }
 hipError_t hipGetLastError(void) { return 0; }
 hipError_t hipSetDevice(int d) { return 0; }
+hipError_t hipGetDevice(int *d) { *d = 0; return 0; }
+/* a __device__ variable's host shadow has the variable's size: use it */
+hipError_t hipGetSymbolAddress(void **p, const void *sym) { *p = (void *)sym; return 0; }
+void __hipRegisterVar(void **m, void *var, char *hv, const char *dv, int ext, size_t size, int constant,
+                      int global) {}
 hipError_t hipFuncSetAttribute(const void *f, int a, int v) { return 0; }
 const char *hipGetErrorString(hipError_t e) { return "stub"; }
 hipError_t hipLaunchKernel(const void *f, dim3 g, dim3 b, void **a, size_t sh, void *st) { return 0; }
