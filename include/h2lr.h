@@ -42,7 +42,8 @@ typedef enum {
   H2_ERR_RANK_CAP = -5,         /* a recompressed rank exceeded the rank cap   */
   H2_ERR_NONZERO_FARFIELD = -6, /* sparse input has a non-zero in an admissible block */
   H2_ERR_NOT_CONVERGED = -7,    /* PCG reached maxit before the tolerance      */
-  H2_ERR_STATE = -8             /* object poisoned by an earlier failed update */
+  H2_ERR_STATE = -8,            /* object poisoned by an earlier failed update */
+  H2_ERR_ZERO_PIVOT = -9        /* zero pivot in a leaf of the LR factorisation */
 } h2_status;
 
 typedef struct h2_ctx_s *h2_ctx;
@@ -161,6 +162,10 @@ h2_status h2_mat_bytes(h2_mat m, int64_t *bytes);
  * and nearfield blocks at the current ranks; max ranks of both bases. */
 h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row,
                        int32_t *max_rank_col);
+/* Host copies of the current ranks k_t of the row basis (rank_row) and of
+ * the column basis (rank_col), nclusters entries each, cluster ids as in
+ * h2_ctree_export; either pointer may be NULL.  Synchronises the stream. */
+h2_status h2_mat_ranks(h2_mat m, int32_t *rank_row, int32_t *rank_col);
 /* Algorithmic floating point operations performed on m since the last reset
  * (products 2mnk, Householder R-factors 2mn^2-2n^3/3, SVDs 4ab^2+8b^3 with
  * a = max, b = min of the dimensions; vector substitutions n^2 per column);
@@ -217,6 +222,32 @@ h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, doub
  * preconditioner).  Fails with H2_ERR_NOT_SPD (message names the leaf) or
  * H2_ERR_RANK_CAP; the matrix is then poisoned. */
 h2_status h2_cholesky(h2_mat a, const h2_trunc *tr);
+
+/* In-place approximate LR factorisation A = L R of a matrix created with
+ * lower = 0 (Section 3: LR recursion with L unit lower and R upper
+ * triangular, leaves by Gaussian elimination without pivoting, the block
+ * forward substitutions L_11 R_12 = A_12 and L_21 R_11 = A_21, the Schur
+ * product A_22 - L_21 R_12 by the product recursion, all expressed by local
+ * low-rank updates).  Afterwards the matrix holds L - I below the diagonal
+ * and R on and above it in the same H^2 structure (h2_matvec applies that
+ * packed operator).  Fails with H2_ERR_ZERO_PIVOT (message names the leaf)
+ * or H2_ERR_RANK_CAP; the matrix is then poisoned. */
+h2_status h2_lr(h2_mat a, const h2_trunc *tr);
+
+/* z = R^{-1} L^{-1} r with the factors made by h2_lr (block forward
+ * substitution with L, then block backward substitution with R, Section 3,
+ * vector right-hand sides).  r, z: device, n x nrhs, original order (may
+ * alias), 1 <= nrhs <= H2_MAX_COLS.  H2_ERR_ARG if a holds no LR factors. */
+h2_status h2_lr_solve(h2_mat f, const double *r, double *z, int32_t nrhs);
+
+/* Z += alpha X Y for three distinct full-storage (lower = 0) matrices on one
+ * block tree and device (Section 3, product of H^2-matrices: Case 1
+ * recursion over the sons, with temporary low-rank matrices for admissible
+ * leaf targets added by local updates; Case 2 emissions of low-rank
+ * products when a factor is a leaf; Section 6 for the cost).  X and Y are
+ * only read; pending work on their streams is waited for.  Truncation per
+ * tr.  Fails with H2_ERR_RANK_CAP (Z then poisoned). */
+h2_status h2_product(h2_mat z, double alpha, h2_mat x, h2_mat y, const h2_trunc *tr);
 
 /* h2_cholesky of count independent matrices in one launch (one workgroup
  * per matrix; the same Section 3 recursion and arithmetic as h2_cholesky,

@@ -42,8 +42,12 @@ class TruncParams:
         are dropped (blockwise relative accuracy, Section 4 last paragraph and
         Section 7).
     mode 'const_rel': unit block scales, drop sigma_{r+1} <= eps * sigma_1.
-    mode 'none': keep every non-zero singular value (exact arithmetic up to
-        rounding).
+    mode 'none': keep every numerically non-zero singular value (exact
+        arithmetic up to rounding).
+    In every mode a basis recompression also drops singular values at the
+    rounding level, sigma <= max(m, n) * eps_mach * sigma_1 for an m x n
+    matrix (the usual numerical rank): they are indistinguishable from zero
+    and their singular vectors are not determined by the data.
     rank_cap: an update that would create a rank above this raises.
     """
     eps: float = 1e-6
@@ -59,11 +63,16 @@ class TruncParams:
             return 0.0
         raise ValueError(self.mode)
 
-    def rank(self, sig: np.ndarray) -> int:
-        """r = min{ r : sigma_{r+1} <= tau } for descending sig."""
+    def rank(self, sig: np.ndarray, shape: tuple[int, int] | None = None) -> int:
+        """r = min{ r : sigma_{r+1} <= tau } for descending sig; with the
+        matrix shape, tau is at least the rounding level
+        max(m, n) * eps_mach * sigma_1."""
         if len(sig) == 0:
             return 0
-        return int(np.count_nonzero(sig > self.tau(sig)))
+        tau = self.tau(sig)
+        if shape is not None:
+            tau = max(tau, max(shape) * np.finfo(np.float64).eps * sig[0])
+        return int(np.count_nonzero(sig > tau))
 
 
 class RankCapError(RuntimeError):

@@ -306,7 +306,12 @@ struct h2_mat_s {
   TaskList chol, prec, tinv, prec_inv;
   TaskList upd;           // the last batched update's list (storage reused: no frees)
   TaskList trsv[2];       // forward (L) and backward (L^*) substitution alone
+  TaskList lrf, lrsolve;  // LR factorisation, R^{-1} L^{-1} r
+  TaskList prod;          // Z += alpha X Y with X, Y read through d_env3[1], d_env3[2]
+  Dev<DevEnv> d_env3;     // this matrix's env and the product operands' envs
+  double prod_alpha = 0.0;  // alpha the product task list was planned with
   bool inverse = false;   // holds G ~ L^{-1} (h2_tri_invert) instead of a factor L
+  bool lr = false;        // holds the LR factors (h2_lr)
   DevEnv env{};
 };
 
@@ -365,8 +370,9 @@ static size_t mat_bytes_now(const h2_mat_s &m) {
     add(m.d_wR[side]);
   }
   add(m.d_bcols); add(m.d_err); add(m.d_S); add(m.d_N); add(m.d_xh); add(m.d_yh); add(m.d_buf);
-  add(m.d_pcg); add(m.d_prof); add(m.d_flops); add(m.d_wscr); add(m.d_env);
-  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv, &m.upd, &m.trsv[0], &m.trsv[1]}) {
+  add(m.d_pcg); add(m.d_prof); add(m.d_flops); add(m.d_wscr); add(m.d_env); add(m.d_env3);
+  for (const TaskList *tl : {&m.chol, &m.prec, &m.tinv, &m.prec_inv, &m.upd, &m.trsv[0], &m.trsv[1], &m.lrf,
+                             &m.lrsolve, &m.prod}) {
     add(tl->d);
     add(tl->aux);
   }
@@ -463,10 +469,15 @@ struct Planner {
   std::vector<int> aux;
   Planner(const h2_mat_s &m, std::vector<Task> &t) : M(m), ct(*m.bt->ct), bt(*m.bt), T(t) {}
 
+  // environment of the next emitted tasks: 0 = the target matrix; the
+  // product of three matrices reads X through 1 and Y through 2 (ex, ey)
+  int env = 0, ex = 0, ey = 0;
+
   void emit(int op, int a = 0, int b = 0, int c = 0, int d = 0, int e_ = 0, int f = 0, int g = 0,
             int h = 0, double alpha = 0.0, double beta = 0.0) {
     Task k{};
     k.op = op;
+    k.env = env;
     k.i[0] = a; k.i[1] = b; k.i[2] = c; k.i[3] = d; k.i[4] = e_; k.i[5] = f; k.i[6] = g; k.i[7] = h;
     k.alpha = alpha; k.beta = beta;
     T.push_back(k);
@@ -670,8 +681,9 @@ struct Planner {
         for (int c0 = 0; c0 < ns; c0 += BC) {
           const int nc = std::min(BC, ns - c0);
           emit(OP_IDENT, s, B_I, c0, nc);
-          bapply(bX, 0, B_I, B_A, 1.0, 0.0);
-          bapply(bY, 1, B_I, B_B, 1.0, 0.0);
+          env = ex; bapply(bX, 0, B_I, B_A, 1.0, 0.0);
+          env = ey; bapply(bY, 1, B_I, B_B, 1.0, 0.0);
+          env = 0;
           emit(OP_NEAR_ADD, bZ, B_A, B_B, 0, 0, 0, 0, 0, alpha);
         }
       } else {
@@ -690,24 +702,25 @@ struct Planner {
       return;
     }
     if (bt.kind[bY] == 1) {          // Y = V_s S W_r^*: U = alpha (X V_s) S, V = W_r
-      emit(OP_EXPAND, 0, s, B_W);
-      bapply(bX, 0, B_W, B_A, 1.0, 0.0);
-      emit(OP_RMUL_S, B_A, B_U, bY, 0, t, 0, 0, 0, alpha);
+      env = ey; emit(OP_EXPAND, 0, s, B_W);
+      env = ex; bapply(bX, 0, B_W, B_A, 1.0, 0.0);
+      env = ey; emit(OP_RMUL_S, B_A, B_U, bY, 0, t, 0, 0, 0, alpha);
       emit(OP_EXPAND, 1, r, B_V);
     } else if (bt.kind[bX] == 1) {   // X = V_t S W_s^*: U = alpha V_t S, V = Y^* W_s
-      emit(OP_EXPAND, 0, t, B_A);
+      env = ex; emit(OP_EXPAND, 0, t, B_A);
       emit(OP_RMUL_S, B_A, B_U, bX, 0, t, 0, 0, 0, alpha);
       emit(OP_EXPAND, 1, s, B_W);
-      bapply(bY, 1, B_W, B_V, 1.0, 0.0);
+      env = ey; bapply(bY, 1, B_W, B_V, 1.0, 0.0);
     } else if (bt.kind[bX] == 2) {   // U = alpha N_X, V = Y^* expanded
-      emit(OP_COPY_NEAR, bX, B_U, 0, 0, 0, 0, 0, 0, alpha);
-      emit(OP_IDENT, s, B_I, 0, ct.size[s]);
-      bapply(bY, 1, B_I, B_V, 1.0, 0.0);
+      env = ex; emit(OP_COPY_NEAR, bX, B_U, 0, 0, 0, 0, 0, 0, alpha);
+      env = 0; emit(OP_IDENT, s, B_I, 0, ct.size[s]);
+      env = ey; bapply(bY, 1, B_I, B_V, 1.0, 0.0);
     } else {                         // U = alpha X expanded, V = N_Y^*
       emit(OP_IDENT, s, B_I, 0, ct.size[s]);
-      bapply(bX, 0, B_I, B_U, alpha, 0.0);
-      emit(OP_COPY_NEAR, bY, B_V, 1, 0, 0, 0, 0, 0, 1.0);
+      env = ex; bapply(bX, 0, B_I, B_U, alpha, 0.0);
+      env = ey; emit(OP_COPY_NEAR, bY, B_V, 1, 0, 0, 0, 0, 0, 1.0);
     }
+    env = 0;
     if (tmp >= 0) {
       emit(OP_TEMP_ADD, TU(tmp), TV(tmp), t, r, B_U, B_V, tT, rT);
     } else {
@@ -715,6 +728,94 @@ struct Planner {
       if (bt.kind[bZ] == 2) emit(OP_NEAR_ADD, bZ, B_U, B_V, 0, 0, 0, 0, 0, 1.0);
       else addlr(bZ, B_U, B_V);
     }
+  }
+
+  // ---- LR factorisation (Section 3) of a full-storage matrix in place:
+  // unit lower L below the diagonal, R on and above it; no pivoting.
+  // Vector solves with the factors of the diagonal block (c, c):
+  // L_cc y = w (forward), R_cc^* y = w (forward), R_cc y = w (backward).
+  void fsolve_unit(int c, int buf) {
+    if (leaf(c)) { emit(OP_TRSV, find(c, c), buf, 0, TRI_L_UNIT); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    fsolve_unit(c1, buf);
+    bapply(find(c2, c1), 0, buf, buf, -1.0, 1.0);
+    fsolve_unit(c2, buf);
+  }
+  void fsolve_radj(int c, int buf) {
+    if (leaf(c)) { emit(OP_TRSV, find(c, c), buf, 0, TRI_R_ADJ); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    fsolve_radj(c1, buf);
+    bapply(find(c1, c2), 1, buf, buf, -1.0, 1.0);
+    fsolve_radj(c2, buf);
+  }
+  void bsolve_upper(int c, int buf) {
+    if (leaf(c)) { emit(OP_TRSV, find(c, c), buf, 0, TRI_R); return; }
+    const int c1 = ct.son0[c], c2 = ct.son1[c];
+    bsolve_upper(c2, buf);
+    bapply(find(c1, c2), 0, buf, buf, -1.0, 1.0);
+    bsolve_upper(c1, buf);
+  }
+  // L_cc X = Y on block b = (c, r), in place (block forward substitution).
+  void lsolve_lr(int c, int b) {
+    const int r = bt.col[b];
+    if (bt.kind[b] == 0) {
+      if (leaf(c)) {
+        for (int r2 : sons_plus(r)) lsolve_lr(c, find(c, r2));
+        return;
+      }
+      const int c1 = ct.son0[c], c2 = ct.son1[c];
+      const auto rs = sons_plus(r);
+      for (int r2 : rs) lsolve_lr(c1, find(c1, r2));
+      for (int r2 : rs) mm_n(c2, c1, r2, -1.0, -1, 0, 0);
+      for (int r2 : rs) lsolve_lr(c2, find(c2, r2));
+    } else if (bt.kind[b] == 2) {
+      emit(OP_TRSM, b, find(c, c), TRI_L_UNIT);
+    } else {
+      // L_cc^{-1} V_c S W_r^*, added as the update (L_cc^{-1} V_c - V_c)(W_r S^*)^*
+      emit(OP_EXPAND, 0, c, B_W);
+      emit(OP_COPY, B_W, B_WP, c);
+      fsolve_unit(c, B_WP);
+      emit(OP_SUB, B_WP, B_W, B_U, c);
+      emit(OP_EXPAND, 1, r, B_A);
+      emit(OP_RMUL_S, B_A, B_V, b, 1, r, 0, 0, 0, 1.0);
+      addlr(b, B_U, B_V);
+    }
+  }
+  // X R_cc = Y on block b = (r, c), in place.
+  void rsolve_lr(int c, int b) {
+    const int r = bt.row[b];
+    if (bt.kind[b] == 0) {
+      if (leaf(c)) {
+        for (int r2 : sons_plus(r)) rsolve_lr(c, find(r2, c));
+        return;
+      }
+      const int c1 = ct.son0[c], c2 = ct.son1[c];
+      const auto rs = sons_plus(r);
+      for (int r2 : rs) rsolve_lr(c1, find(r2, c1));
+      for (int r2 : rs) mm_n(r2, c1, c2, -1.0, -1, 0, 0);
+      for (int r2 : rs) rsolve_lr(c2, find(r2, c2));
+    } else if (bt.kind[b] == 2) {
+      emit(OP_TRSM, b, find(c, c), TRI_R_ADJ);
+    } else {
+      // V_r S W_c^* R_cc^{-1} = V_r S (R_cc^{-*} W_c)^*, added as the update
+      // (V_r S)(R_cc^{-*} W_c - W_c)^*
+      emit(OP_EXPAND, 1, c, B_W);
+      emit(OP_COPY, B_W, B_WP, c);
+      fsolve_radj(c, B_WP);
+      emit(OP_SUB, B_WP, B_W, B_V, c);
+      emit(OP_EXPAND, 0, r, B_A);
+      emit(OP_RMUL_S, B_A, B_U, b, 0, r, 0, 0, 0, 1.0);
+      addlr(b, B_U, B_V);
+    }
+  }
+  void lr(int t) {
+    if (leaf(t)) { emit(OP_GETRF, find(t, t), t); return; }
+    const int t1 = ct.son0[t], t2 = ct.son1[t];
+    lr(t1);
+    lsolve_lr(t1, find(t1, t2));
+    rsolve_lr(t1, find(t2, t1));
+    mm_n(t2, t1, t2, -1.0, -1, 0, 0);
+    lr(t2);
   }
 
   // buf|_c <- G_cc buf|_c (trans: G_cc^* buf|_c) in place, G lower
@@ -875,11 +976,12 @@ static void sync_env(h2_mat_s &m) {
 
 // nthreads: workgroup size of the launch (NT, or 256 for task lists whose
 // kinds distribute work by the run-time wave count).
-static void run_tasks(h2_mat_s &m, const TaskList &tl, int nthreads = NT) {
+static void run_tasks(h2_mat_s &m, const TaskList &tl, int nthreads = NT, const DevEnv *d_envs = nullptr) {
   const Task *d_tasks = tl.d.p;
   const int count = tl.count;
   const size_t lds = LDS_TOTAL_DOUBLES * sizeof(double);
   sync_env(m);
+  if (!d_envs) d_envs = m.d_env.p;
   if (!g_lds_attr_set) {
     HIPCHK(hipFuncSetAttribute((const void *)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     g_lds_attr_set = true;
@@ -887,8 +989,8 @@ static void run_tasks(h2_mat_s &m, const TaskList &tl, int nthreads = NT) {
   const int seg = 1 << 24;
   for (int off = 0; off < count; off += seg) {
     const int cnt = std::min(seg, count - off);
-    hipLaunchKernelGGL(k_interp, dim3(1), dim3(nthreads), lds, m.ctx->stream, d_tasks + off, cnt,
-                       (const DevEnv *)m.d_env.p, (const int *)tl.aux.p);
+    hipLaunchKernelGGL(k_interp, dim3(1), dim3(nthreads), lds, m.ctx->stream, d_tasks + off, cnt, d_envs,
+                       (const int *)tl.aux.p);
     HIPCHK(hipGetLastError());
   }
 }
@@ -903,6 +1005,10 @@ static void check_device_error(h2_mat_s &m) {
     if (err[0] == E_NOT_SPD) {
       snprintf(msg, sizeof msg, "leaf block of cluster %d is not positive definite", err[1]);
       throw H2Error(H2_ERR_NOT_SPD, msg);
+    }
+    if (err[0] == E_ZERO_PIVOT) {
+      snprintf(msg, sizeof msg, "zero pivot in the LR factorisation of the leaf block of cluster %d", err[1]);
+      throw H2Error(H2_ERR_ZERO_PIVOT, msg);
     }
     if (err[0] == E_RANK_CAP) {
       snprintf(msg, sizeof msg, "rank cap exceeded at cluster %d", err[1]);
@@ -1169,6 +1275,7 @@ h2_status h2_mat_assign(h2_mat dst, h2_mat src) {
     HIPCHK(hipMemsetAsync(dst->d_err.p, 0, dst->d_err.n * sizeof(int), s));
     dst->poisoned = false;
     dst->inverse = src->inverse;
+    dst->lr = src->lr;
   });
 }
 
@@ -1231,6 +1338,18 @@ h2_status h2_mat_bytes(h2_mat m, int64_t *bytes) {
   return guarded([&] {
     REQUIRE(m != nullptr && bytes != nullptr, "null argument");
     *bytes = (int64_t)mat_bytes_now(*m);
+  });
+}
+
+h2_status h2_mat_ranks(h2_mat m, int32_t *rank_row, int32_t *rank_col) {
+  return guarded([&] {
+    REQUIRE(m != nullptr, "null matrix");
+    const int nc = (int)m->bt->ct->nc;
+    int32_t *dst[2] = {rank_row, rank_col};
+    for (int side = 0; side < 2; ++side)
+      if (dst[side])
+        HIPCHK(hipMemcpyAsync(dst[side], m->d_k[side].p, nc * sizeof(int), hipMemcpyDeviceToHost, m->ctx->stream));
+    HIPCHK(hipStreamSynchronize(m->ctx->stream));
   });
 }
 
@@ -1331,6 +1450,73 @@ h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
     }
     run_tasks(*a, a->chol);
     check_device_error(*a);
+  });
+}
+
+h2_status h2_lr(h2_mat a, const h2_trunc *tr) {
+  return guarded([&] {
+    require_ok(a);
+    REQUIRE(!a->lower, "h2_lr needs a matrix created with lower = 0 (full storage)");
+    set_trunc(*a, tr);
+    if (!a->lrf.built) {
+      std::vector<Task> tasks;
+      Planner P(*a, tasks);
+      P.lr(0);
+      upload_tasks(*a, a->lrf, tasks, P.aux);
+    }
+    a->lr = false;
+    run_tasks(*a, a->lrf);
+    check_device_error(*a);
+    a->lr = true;
+  });
+}
+
+// Environment through which the product's tasks read the operand m: m's
+// matrix data with the target z's work areas, error flag, counters and
+// truncation parameters.
+static DevEnv operand_env(const h2_mat_s &m, const h2_mat_s &z) {
+  DevEnv e = m.env;
+  const DevEnv &t = z.env;
+  e.rank_cap = t.rank_cap; e.mode = t.mode; e.eps = t.eps;
+  for (int side = 0; side < 2; ++side) {
+    e.wrho[side] = t.wrho[side]; e.wrho_m[side] = t.wrho_m[side];
+    e.wB[side] = t.wB[side]; e.wB_m[side] = t.wB_m[side];
+    e.wR[side] = t.wR[side]; e.wnewk[side] = t.wnewk[side];
+  }
+  e.xh = t.xh; e.yh = t.yh;
+  for (int i = 0; i < NBUF; ++i) e.buf[i] = t.buf[i];
+  e.bcols = t.bcols; e.err = t.err; e.prof = t.prof; e.flops = t.flops; e.wscr = t.wscr;
+  return e;
+}
+
+h2_status h2_product(h2_mat z, double alpha, h2_mat x, h2_mat y, const h2_trunc *tr) {
+  return guarded([&] {
+    require_ok(z); require_ok(x); require_ok(y);
+    REQUIRE(z != x && z != y, "h2_product: the target must differ from both factors");
+    REQUIRE(!z->lower && !x->lower && !y->lower, "h2_product needs full-storage matrices (lower = 0)");
+    REQUIRE(x->bt == z->bt && y->bt == z->bt, "h2_product: the matrices must share one block tree");
+    REQUIRE(x->ctx->device == z->ctx->device && y->ctx->device == z->ctx->device,
+            "h2_product: the matrices must live on one device");
+    // the factors are read on z's stream: finish their own pending work
+    for (h2_mat m : {x, y})
+      if (m->stream != z->stream) HIPCHK(hipStreamSynchronize(m->stream));
+    set_trunc(*z, tr);
+    if (!z->prod.built || z->prod_alpha != alpha) {
+      // alpha is stored in the emitted tasks: planned again for another value
+      std::vector<Task> tasks;
+      Planner P(*z, tasks);
+      P.ex = 1;
+      P.ey = 2;
+      P.mm_n(0, 0, 0, alpha, -1, 0, 0);
+      upload_tasks(*z, z->prod, tasks, P.aux);
+      z->prod_alpha = alpha;
+    }
+    const DevEnv envs[3] = {z->env, operand_env(*x, *z), operand_env(*y, *z)};
+    if (!z->d_env3.p) z->d_env3.alloc(3);
+    HIPCHK(hipMemcpyAsync(z->d_env3.p, envs, sizeof envs, hipMemcpyHostToDevice, z->stream));
+    HIPCHK(hipStreamSynchronize(z->stream));
+    run_tasks(*z, z->prod, NT, z->d_env3.p);
+    check_device_error(*z);
   });
 }
 
@@ -1690,6 +1876,26 @@ h2_status h2_trsv(h2_mat l, int32_t trans, const double *r, double *z, int32_t n
     run_tasks(*l, tl, PREC_THREADS);
     prec_scatter(l, z, nrhs);
     check_device_error(*l);
+  });
+}
+
+h2_status h2_lr_solve(h2_mat f, const double *r, double *z, int32_t nrhs) {
+  return guarded([&] {
+    require_ok(f);
+    REQUIRE(f->lr, "h2_lr_solve needs a matrix factorised by h2_lr");
+    REQUIRE(r && z, "null vector");
+    REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
+    if (!f->lrsolve.built) {
+      std::vector<Task> tasks;
+      Planner P(*f, tasks);
+      P.fsolve_unit(0, B_X);
+      P.bsolve_upper(0, B_X);
+      upload_tasks(*f, f->lrsolve, tasks, P.aux);
+    }
+    prec_gather(f, r, nrhs);
+    run_tasks(*f, f->lrsolve);
+    prec_scatter(f, z, nrhs);
+    check_device_error(*f);
   });
 }
 

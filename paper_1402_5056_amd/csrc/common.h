@@ -13,7 +13,7 @@ constexpr int NT = 512;    // threads of the task interpreter workgroup
 constexpr int KPMAX = KM - KC;  // largest update rank k'
 
 // Device error codes written to err[0] (mirrors h2_status).
-enum : int { E_OK = 0, E_NOT_SPD = -4, E_RANK_CAP = -5, E_ARG = -1, E_SCRATCH = -100 };
+enum : int { E_OK = 0, E_NOT_SPD = -4, E_RANK_CAP = -5, E_ARG = -1, E_ZERO_PIVOT = -9, E_SCRATCH = -100 };
 
 // Work buffers: n x BC row-major arrays indexed by cluster-order rows.
 enum Buf : int {
@@ -33,8 +33,8 @@ enum Op : int {
   OP_TEMP_INIT,      // i0 U, i1 V, i2 row cluster, i3 col cluster
   OP_TEMP_ADD,       // i0 tU, i1 tV, i2 t', i3 r', i4 U, i5 V, i6 temp row cluster, i7 temp col cluster
   OP_POTRF,          // i0 leaf cluster
-  OP_TRSM,           // i0 near block, i1 diagonal leaf cluster
-  OP_TRSV,           // i0 leaf cluster, i1 buf, i2 trans
+  OP_TRSM,           // i0 near block, i1 diagonal leaf block, i2 kind (TRI_*)
+  OP_TRSV,           // i0 diagonal leaf block, i1 buf, i2 trans (kind TRI_CHOL), i3 kind (TRI_*)
   OP_SUB,            // i0 A, i1 B, i2 out, i3 cluster
   OP_COPY,           // i0 A, i1 out, i2 cluster
   OP_SV_ZERO,        // i0 cluster, i1 buf, i2 trans   substitution: clear the coupling sums of the subtree
@@ -46,12 +46,20 @@ enum Op : int {
   OP_TRMV,           // i0 diagonal leaf block, i1 buf, i2 trans   buf rows <- tril(N) (or its transpose) buf rows
   OP_NEG,            // i0 aux offset, i1 count        negate the stored leaf blocks listed in aux
   OP_NEAR_TRMUL,     // i0 near block, i1 diagonal leaf block, i2 side   N <- tril(N_cc) N (0) or N tril(N_cc) (1)
+  OP_GETRF,          // i0 diagonal leaf block, i1 cluster   LR of the leaf without pivoting
 };
+
+// Which triangle of a diagonal leaf a solve uses.  TRI_CHOL: the Cholesky
+// factor L (lower; trsv: L^{-1} or L^{-T} by trans, trsm: N <- N L^{-T});
+// the LR factor of a leaf holds unit lower L and upper R:
+// TRI_L_UNIT: L^{-1} x (trsm: N <- L^{-1} N); TRI_R_ADJ: R^{-T} x (trsm:
+// N <- N R^{-1}); TRI_R: R^{-1} x.
+enum : int { TRI_CHOL = 0, TRI_L_UNIT = 1, TRI_R_ADJ = 2, TRI_R = 3 };
 
 struct Task {
   int op;
   int i[8];
-  int pad;
+  int env;   // index of the environment whose matrix data the task reads (0: the target)
   double alpha, beta;
 };
 

@@ -923,6 +923,84 @@ __device__ __forceinline__ double wave_tri_solve(int n, const double (&row)[NMAX
   return b;
 }
 
+// Triangular solve by one wave, lane i holding row i of the triangular
+// matrix T in row[] (as loaded by wave_load_tri): forward substitution for
+// lower T (forward = true) or backward substitution for upper T; unit: the
+// diagonal is taken as 1 and not read.
+template <int NMAX>
+__device__ __forceinline__ double wave_tri_solve_ex(int n, const double (&row)[NMAX], bool forward, bool unit,
+                                                    double b) {
+  const int lane = lane_id();
+  if (forward) {
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+      if (j < n) {
+        const double bj = __shfl(b, j, 64);
+        const double xj = unit ? bj : bj / __shfl(row[j], j, 64);
+        if (lane == j) b = xj;
+        else if (lane > j) b = fma(-row[j], xj, b);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = NMAX - 1; j >= 0; --j) {
+      if (j < n) {
+        const double bj = __shfl(b, j, 64);
+        const double xj = unit ? bj : bj / __shfl(row[j], j, 64);
+        if (lane == j) b = xj;
+        else if (lane < j) b = fma(-row[j], xj, b);
+      }
+    }
+  }
+  return b;
+}
+
+// B (n x m) <- T^{-1} B, n <= LS, one wave per column of B.  T is the lower
+// (forward = true) or upper triangle of A (load_trans = 0) or of A^T
+// (load_trans = 1); unit: unit diagonal.  The LR factor of a leaf holds the
+// unit lower L below and R on and above the diagonal:
+//   L^{-1} B: load_trans 0, forward, unit;   R^{-1} B: load_trans 0, backward;
+//   R^{-T} B: load_trans 1, forward.
+__device__ void wg_trsv_ex(int n, int m, MV A, MV B, int load_trans, bool forward, bool unit) {
+  double row[LS];
+  wave_load_tri<LS>(n, A, load_trans, row);
+  const int lane = lane_id();
+  for (int c = wave_id(); c < m; c += num_waves()) {
+    double b = lane < n ? B(lane, c) : 0.0;
+    b = wave_tri_solve_ex<LS>(n, row, forward, unit, b);
+    if (lane < n) B(lane, c) = b;
+  }
+  __syncthreads();
+}
+
+// Gaussian elimination without pivoting of A (n x n) in place: A <- (L - I)
+// + R with L unit lower and R upper triangular.  Returns 0, or j + 1 for the
+// first zero pivot A(j, j) (that pivot is then replaced by 1 so that the
+// remaining steps stay finite).
+__device__ int wg_getrf_nopiv(int n, MV A, int *iflag) {
+  if (threadIdx.x == 0) *iflag = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double piv = A(j, j);
+    __syncthreads();
+    if (piv == 0.0) {
+      if (threadIdx.x == 0) { if (*iflag == 0) *iflag = j + 1; A(j, j) = 1.0; }
+    }
+    const double d = piv == 0.0 ? 1.0 : piv;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, j) /= d;
+    __syncthreads();
+    const int rem = n - j - 1;
+    for (int idx = threadIdx.x; idx < rem * rem; idx += blockDim.x) {
+      const int i = j + 1 + idx % rem, c = j + 1 + idx / rem;
+      A(i, c) = fma(-A(i, j), A(j, c), A(i, c));
+    }
+    __syncthreads();
+  }
+  const int r = *iflag;
+  __syncthreads();
+  return r;
+}
+
 // X (m x n) <- X L^{-T} for lower triangular L (n x n, n <= LS): every row x
 // of X solves L x^T = row^T; one wave per row.
 __device__ void wg_trsm_right_lt(int m, int n, MV L, MV X) {

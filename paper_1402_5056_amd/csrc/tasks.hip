@@ -574,7 +574,10 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
       atomicAdd(&e.prof[PROF_STAGE + 13], 1ull);
       atomicAdd(&e.prof[PROF_STAGE + 14], (unsigned long long)nG);
     }
-    const double tau = trunc_tau(e, nG > 0 ? W.sig[W.ord[0]] : 0.0);
+    // at least the rounding level max(m, n) eps sigma_1 (numerical rank):
+    // singular vectors of smaller values are not determined by the data
+    const double smax = nG > 0 ? W.sig[W.ord[0]] : 0.0;
+    const double tau = fmax(trunc_tau(e, smax), (double)(mr > mB ? mr : mB) * 2.220446049250313e-16 * smax);
     for (int j = 0; j < nG; ++j) r += W.sig[W.ord[j]] > tau ? 1 : 0;
     if (r > e.rank_cap) {
       if (lane == 0) { e.err[1] = c; e.err[0] = E_RANK_CAP; }
@@ -1554,16 +1557,47 @@ __device__ void task_potrf(const DevEnv &e, const Lds &L, int bcc, int t) {
   if (info) set_error(e, E_NOT_SPD, t);
 }
 
-__device__ void task_trsm(const DevEnv &e, int b, int bcc) {
-  const int r = e.brow[b], c = e.brow[bcc];
-  wg_trsm_right_lt(e.size[r], e.size[c], Nslot(e, bcc), Nslot(e, b));
-  count(e, (double)e.size[r] * e.size[c] * e.size[c]);
+// LR factorisation of a diagonal leaf without pivoting (leaf case of the
+// LR recursion of Section 3): N_cc <- (L - I) + R.
+__device__ void task_getrf(const DevEnv &e, const Lds &L, int bcc, int t) {
+  const int n = e.size[t];
+  const int info = wg_getrf_nopiv(n, Nslot(e, bcc), L.iw);
+  count(e, 2.0 * n * n * n / 3.0);
+  if (info) set_error(e, E_ZERO_PIVOT, t);
 }
 
-__device__ void task_trsv(const DevEnv &e, int bcc, int bi, int trans) {
+// Solve with a diagonal leaf on an inadmissible leaf b in place:
+// TRI_CHOL  b = (r, c): N_b <- N_b L_cc^{-T}  (Cholesky factor);
+// TRI_L_UNIT b = (c, r): N_b <- L_cc^{-1} N_b (unit lower LR factor);
+// TRI_R_ADJ b = (r, c): N_b <- N_b R_cc^{-1}  (upper LR factor), as
+//                        N_b^T <- R_cc^{-T} N_b^T.
+__device__ void task_trsm(const DevEnv &e, int b, int bcc, int kind) {
+  const int c = e.brow[bcc];
+  const int nc = e.size[c];
+  if (kind == TRI_CHOL) {
+    const int r = e.brow[b];
+    wg_trsm_right_lt(e.size[r], nc, Nslot(e, bcc), Nslot(e, b));
+    count(e, (double)e.size[r] * nc * nc);
+  } else if (kind == TRI_L_UNIT) {
+    const int m = e.size[e.bcol[b]];
+    wg_trsv_ex(nc, m, Nslot(e, bcc), Nslot(e, b), 0, true, true);
+    count(e, (double)m * nc * nc);
+  } else {
+    const int m = e.size[e.brow[b]];
+    wg_trsv_ex(nc, m, Nslot(e, bcc), mv_t(Nslot(e, b)), 1, true, false);
+    count(e, (double)m * nc * nc);
+  }
+}
+
+// buf|_c <- T^{-1} buf|_c with the triangle of the diagonal leaf named by
+// kind (TRI_CHOL: L^{-1}, or L^{-T} if trans).
+__device__ void task_trsv(const DevEnv &e, int bcc, int bi, int trans, int kind) {
   if (e.bcols[bi] == 0) return;   // no columns
   const int c = e.brow[bcc];
-  wg_trsv_lower(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), trans);
+  if (kind == TRI_CHOL) wg_trsv_lower(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), trans);
+  else if (kind == TRI_L_UNIT) wg_trsv_ex(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), 0, true, true);
+  else if (kind == TRI_R_ADJ) wg_trsv_ex(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), 1, true, false);
+  else wg_trsv_ex(e.size[c], e.bcols[bi], Nslot(e, bcc), bufrows(e, bi, c), 0, false, false);
   count(e, (double)e.size[c] * e.size[c] * e.bcols[bi]);
 }
 
@@ -1638,14 +1672,17 @@ __device__ void task_neg(const DevEnv &e, const int *aux, int off, int cnt) {
 __device__ __forceinline__ void interp_run(const Task *__restrict__ tasks, int ntask,
                                            const DevEnv *__restrict__ env, const int *__restrict__ aux) {
   extern __shared__ double lds_raw[];
-  const DevEnv &e = *env;
+  const DevEnv &e0 = *env;
   const Lds L = lds_layout(lds_raw);
-  if (e.err[0] != 0) return;
+  if (e0.err[0] != 0) return;
   Task nxt = ntask > 0 ? tasks[0] : Task{};
   for (int it = 0; it < ntask; ++it) {
     __syncthreads();
     const Task tk = nxt;
     if (it + 1 < ntask) nxt = tasks[it + 1];   // fetched while this task runs
+    // the matrix whose data the task reads; every environment of one list
+    // shares the target's work areas, error flag and counters
+    const DevEnv &e = env[tk.env];
     const unsigned long long t0 = e.prof ? wall_clock64() : 0ull;
     switch (tk.op) {
       case OP_ADDLR: task_addlr(e, L, lds_raw, tk.i[0], tk.i[1], tk.i[2]); break;
@@ -1679,8 +1716,9 @@ __device__ __forceinline__ void interp_run(const Task *__restrict__ tasks, int n
         break;
       }
       case OP_POTRF: task_potrf(e, L, tk.i[0], tk.i[1]); break;
-      case OP_TRSM: task_trsm(e, tk.i[0], tk.i[1]); break;
-      case OP_TRSV: task_trsv(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_TRSM: task_trsm(e, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_TRSV: task_trsv(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
+      case OP_GETRF: task_getrf(e, L, tk.i[0], tk.i[1]); break;
       case OP_SUB: task_sub(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_COPY: task_copy(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_SV_ZERO: task_sv_zero(e, tk.i[0], tk.i[1], tk.i[2]); break;
@@ -1699,9 +1737,10 @@ __device__ __forceinline__ void interp_run(const Task *__restrict__ tasks, int n
       e.prof[PROF_TICKS + tk.op] += wall_clock64() - t0;
     }
     // only these kinds can record an error (set_error ends with a barrier)
-    if (tk.op == OP_ADDLR || tk.op == OP_POTRF || tk.op == OP_TEMP_ADD || tk.op <= 0 || tk.op >= 32) {
+    if (tk.op == OP_ADDLR || tk.op == OP_POTRF || tk.op == OP_GETRF || tk.op == OP_TEMP_ADD || tk.op <= 0 ||
+        tk.op >= 32) {
       __syncthreads();
-      if (e.err[0] != 0) return;
+      if (e0.err[0] != 0) return;
     }
   }
 }

@@ -37,7 +37,7 @@ _lib = C.CDLL(LIB_PATH)
 H2_OK = 0
 STATUS = {0: "H2_OK", -1: "H2_ERR_ARG", -2: "H2_ERR_NOMEM", -3: "H2_ERR_HIP", -4: "H2_ERR_NOT_SPD",
           -5: "H2_ERR_RANK_CAP", -6: "H2_ERR_NONZERO_FARFIELD", -7: "H2_ERR_NOT_CONVERGED",
-          -8: "H2_ERR_STATE"}
+          -8: "H2_ERR_STATE", -9: "H2_ERR_ZERO_PIVOT"}
 MAX_RANK = 32
 MAX_LEAF = 32
 MAX_COLS = 64
@@ -82,6 +82,7 @@ _SIG = {
     "h2_mat_assign": [_vp, _vp],
     "h2_mat_destroy": [_vp],
     "h2_mat_stats": [_vp, _P(_i64), _P(_i32), _P(_i32)],
+    "h2_mat_ranks": [_vp, _vp, _vp],
     "h2_estimate_bytes": [_vp, _i32, _P(_i64)],
     "h2_mat_bytes": [_vp, _P(_i64)],
     "h2_profile": [_vp, _i32, _vp, _i32],
@@ -89,6 +90,9 @@ _SIG = {
     "h2_lowrank_update": [_vp, _i64, _i32, _vp, _i64, _vp, _i64, _P(h2_trunc)],
     "h2_matvec": [_vp, _i32, _d, _vp, _d, _vp, _i32],
     "h2_cholesky": [_vp, _P(h2_trunc)],
+    "h2_lr": [_vp, _P(h2_trunc)],
+    "h2_lr_solve": [_vp, _vp, _vp, _i32],
+    "h2_product": [_vp, _d, _vp, _vp, _P(h2_trunc)],
     "h2_cholesky_batched": [_P(_vp), _i32, _P(h2_trunc), _P(C.c_int)],
     "h2_lowrank_update_batched": [_P(_vp), _i32, _P(_i32), _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp),
                                   _P(_i64), _P(h2_trunc), _P(C.c_int)],
@@ -294,6 +298,14 @@ def h2_mat_stats(m: Mat):
     return v.value, kr.value, kc.value
 
 
+def h2_mat_ranks(m: Mat, nclusters: int):
+    """(row ranks, column ranks) as int32 arrays of nclusters entries."""
+    kr = np.zeros(nclusters, dtype=np.int32)
+    kc = np.zeros(nclusters, dtype=np.int32)
+    _check(_lib.h2_mat_ranks(m.h, kr.ctypes.data, kc.ctypes.data))
+    return kr, kc
+
+
 def h2_mat_flops(m: Mat, reset: bool = False) -> float:
     f = _d()
     _check(_lib.h2_mat_flops(m.h, C.byref(f), 1 if reset else 0))
@@ -357,6 +369,20 @@ def h2_matvec(m: Mat, x, y, trans: bool = False, alpha: float = 1.0, beta: float
 
 def h2_cholesky(m: Mat, tr: h2_trunc):
     _check(_lib.h2_cholesky(m.h, C.byref(tr)))
+
+
+def h2_lr(m: Mat, tr: h2_trunc):
+    _check(_lib.h2_lr(m.h, C.byref(tr)))
+
+
+def h2_lr_solve(m: Mat, r, z):
+    """z = R^{-1} L^{-1} r with the factors of h2_lr; r, z as for h2_precond."""
+    nrhs = 1 if r.dim() == 1 else r.shape[0]
+    _check(_lib.h2_lr_solve(m.h, _ptr(r), _ptr(z), nrhs))
+
+
+def h2_product(z: Mat, alpha: float, x: Mat, y: Mat, tr: h2_trunc):
+    _check(_lib.h2_product(z.h, float(alpha), x.h, y.h, C.byref(tr)))
 
 
 def h2_estimate_bytes(bt: BTree, lower: bool = True) -> int:
