@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--sigma-seed", type=str, default="10",
                     help="seed of the piecewise-constant coefficient, or 'none' for sigma = 1")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="fp64, or mixed: coupling and transfer products of the local updates in "
+                         "float on the matrix cores (QR, SVD, weights and PCG in FP64)")
     ap.add_argument("--precond", choices=("substitution", "inverse"), default="substitution",
                     help="preconditioner: substitutions with the factor L, or products with "
                          "G ~ L^{-1} formed by the triangular inversion after the factorisation")
@@ -428,7 +431,7 @@ def main():
     csr = h2lr.h2_csr_create(ctx, p["A"])
     b = torch.tensor(p["b"], device="cuda")
     x = torch.zeros_like(b)
-    tr = h2lr.trunc(args.eps, "block_rel", 32)
+    tr = h2lr.trunc(args.eps, "block_rel", 32, precision=args.precision)
 
     inverse = args.precond == "inverse"
     inv_info = {}
@@ -509,7 +512,7 @@ def main():
                                f"block-relative eps {args.eps}, H2-Cholesky"
                                + (" + triangular inverse" if inverse else "")
                                + f" + PCG 1 Gaussian RHS to {args.rtol}",
-                   "n": n, "precision": "fp64", "parallelism": "1 GPU"},
+                   "n": n, "precision": args.precision, "parallelism": "1 GPU"},
         "setup_s": setup_s,
         "cholesky_s": chol_s,
         "inverse_s": (setup_s - chol_s) if inverse else None,

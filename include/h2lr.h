@@ -57,13 +57,22 @@ typedef struct h2_job_s *h2_job;
  * accuracy").  mode 0 = block-relative: every block entering a weight stack is
  * scaled by 1/||block||_F and singular values <= eps are dropped; mode 1 =
  * constant relative: drop sigma <= eps*sigma_1; mode 2 = no truncation (keep
- * all non-zero singular values).  rank_cap: 1..H2_MAX_RANK, exceeding it
- * fails with H2_ERR_RANK_CAP. */
+ * all numerically non-zero singular values).  In every mode a basis
+ * recompression of an m x n matrix also drops sigma <= max(m,n) eps_mach
+ * sigma_1 (rounding noise).  rank_cap: 1..H2_MAX_RANK, exceeding it fails
+ * with H2_ERR_RANK_CAP.  precision: H2_PREC_FP64, or H2_PREC_MIXED: the
+ * coupling projections S_b <- R_t S_b R_s^* and the transfer / basis-change
+ * products (R_t' E_t', R_t = Q_t^* V_t, R_t0 E_t0) of every local update take
+ * float operands and accumulate in float on the matrix cores; QR, SVD,
+ * weights, nearfield and all vector solves stay FP64 (results stored FP64). */
 typedef struct {
   double eps;
   int32_t mode;
   int32_t rank_cap;
+  int32_t precision;
 } h2_trunc;
+#define H2_PREC_FP64 0
+#define H2_PREC_MIXED 1
 
 #define H2_MAX_RANK 32       /* rank capacity of every basis slot            */
 #define H2_MAX_LEAF 32       /* largest leaf cluster                          */

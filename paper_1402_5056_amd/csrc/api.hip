@@ -954,11 +954,12 @@ static void upload_tasks_reuse(TaskList &tl, const std::vector<Task> &tasks, con
 }
 
 static void set_trunc(h2_mat_s &m, const h2_trunc *tr) {
-  if (!tr) { m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; return; }
+  if (!tr) { m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; m.env.prec = 0; return; }
   REQUIRE(tr->mode >= 0 && tr->mode <= 2, "truncation mode must be 0, 1 or 2");
   REQUIRE(tr->rank_cap >= 1 && tr->rank_cap <= KC, "rank_cap must be in [1, H2_MAX_RANK]");
   REQUIRE(tr->eps >= 0.0 && std::isfinite(tr->eps), "eps must be finite and >= 0");
-  m.env.eps = tr->eps; m.env.mode = tr->mode; m.env.rank_cap = tr->rank_cap;
+  REQUIRE(tr->precision == H2_PREC_FP64 || tr->precision == H2_PREC_MIXED, "precision must be 0 or 1");
+  m.env.eps = tr->eps; m.env.mode = tr->mode; m.env.rank_cap = tr->rank_cap; m.env.prec = tr->precision;
 }
 
 static bool g_lds_attr_set = false;
@@ -1477,7 +1478,7 @@ h2_status h2_lr(h2_mat a, const h2_trunc *tr) {
 static DevEnv operand_env(const h2_mat_s &m, const h2_mat_s &z) {
   DevEnv e = m.env;
   const DevEnv &t = z.env;
-  e.rank_cap = t.rank_cap; e.mode = t.mode; e.eps = t.eps;
+  e.rank_cap = t.rank_cap; e.mode = t.mode; e.eps = t.eps; e.prec = t.prec;
   for (int side = 0; side < 2; ++side) {
     e.wrho[side] = t.wrho[side]; e.wrho_m[side] = t.wrho_m[side];
     e.wB[side] = t.wB[side]; e.wB_m[side] = t.wB_m[side];

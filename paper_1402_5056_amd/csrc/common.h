@@ -68,6 +68,8 @@ struct DevEnv {
   int n, nc, depth, nlev;          // nlev = depth + 1
   int rank_cap, mode;              // truncation
   double eps;
+  int prec;                        // 0: FP64 products; 1: coupling/transfer products in FP32
+  int pad_prec;
   // cluster tree
   const int *offset, *size, *son0, *son1, *parent, *level;
   const int *desc_lo, *desc_hi;    // nc x nlev: descendants of t at level l = [lo, hi)

@@ -554,18 +554,111 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// C (m x n) = alpha * A (m x k) * B (k x n) + beta * C (no aliasing).
-__device__ void wv_gemm(int m, int n, int k, double alpha, MV A, MV B, double beta, MV C) {
+// ------------------------------------------------ products on the matrix cores
+// One wave forms an m x n product sum_l a(i, l) b(l, j), 0 <= l < k, in
+// 16 x 16 tiles on the matrix cores and hands every entry to store(i, j, v).
+// The operands are accessors (a(i, l), b(l, j) may compute an entry, e.g.
+// of an implicitly extended coupling); they are only called with
+// 0 <= i < m, 0 <= l < k, 0 <= j < n (indices past the end are clamped and
+// the loaded value replaced by zero).  Per v_mfma_f64_16x16x4f64 lane l
+// supplies a(i0 + l%16, k0 + l/16) and b(k0 + l/16, j0 + l%16), and result
+// register r of lane l is entry (i0 + l/16 + 4r, j0 + l%16).  Four k-steps
+// are loaded together before their four matrix instructions.
+typedef double h2_d4 __attribute__((ext_vector_type(4)));
+typedef float h2_f4 __attribute__((ext_vector_type(4)));
+
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void wv_mm_f64(int m, int n, int k, FA a, FB b, FS store) {
+  const int lane = lane_id();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int i0 = 0; i0 < m; i0 += 16) {
+    const int ia = i0 + li;
+    const bool iok = ia < m;
+    const int ic = iok ? ia : m - 1;
+    for (int j0 = 0; j0 < n; j0 += 16) {
+      const int jb = j0 + li;
+      const bool jok = jb < n;
+      const int jc = jok ? jb : n - 1;
+      h2_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k0 + 4 * u + lk;
+          const bool kok = kk < k;
+          const int kc = kok ? kk : k - 1;
+          const double av = a(ic, kc), bv = b(kc, jc);
+          x[u] = (iok && kok) ? av : 0.0;
+          y[u] = (jok && kok) ? bv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], y[u], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r;
+        if (i < m && jok) store(i, jb, acc[r]);
+      }
+    }
+  }
+}
+
+// The same product with the operands rounded to float and accumulated in
+// float (v_mfma_f32_16x16x4f32: same operand layout, result register r of
+// lane l is entry (i0 + 4(l/16) + r, j0 + l%16)); store receives the float
+// result widened to double.  The mixed-precision form of the coupling and
+// transfer products.
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void wv_mm_f32(int m, int n, int k, FA a, FB b, FS store) {
+  const int lane = lane_id();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int i0 = 0; i0 < m; i0 += 16) {
+    const int ia = i0 + li;
+    const bool iok = ia < m;
+    const int ic = iok ? ia : m - 1;
+    for (int j0 = 0; j0 < n; j0 += 16) {
+      const int jb = j0 + li;
+      const bool jok = jb < n;
+      const int jc = jok ? jb : n - 1;
+      h2_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int k0 = 0; k0 < k; k0 += 16) {
+        float x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k0 + 4 * u + lk;
+          const bool kok = kk < k;
+          const int kc = kok ? kk : k - 1;
+          const double av = a(ic, kc), bv = b(kc, jc);
+          x[u] = (iok && kok) ? (float)av : 0.0f;
+          y[u] = (jok && kok) ? (float)bv : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], y[u], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 4 * lk + r;
+        if (i < m && jok) store(i, jb, (double)acc[r]);
+      }
+    }
+  }
+}
+
+// Precision switch: f32 selects the float form.
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void wv_mm(bool f32, int m, int n, int k, FA a, FB b, FS store) {
+  if (f32) wv_mm_f32(m, n, k, a, b, store);
+  else wv_mm_f64(m, n, k, a, b, store);
+}
+
+// C (m x n) = alpha * A (m x k) * B (k x n) + beta * C (no aliasing), on
+// the matrix cores (float operands and accumulation if f32).
+__device__ void wv_gemm(int m, int n, int k, double alpha, MV A, MV B, double beta, MV C, bool f32 = false) {
   if (m > 0 && n > 0) {
-    const int lane = lane_id();
-    int i = lane % m, j = lane / m;
-    const int di = 64 % m, dj = 64 / m;
-    while (j < n) {
-      double s = 0.0;
-      s = dotc(0, k, [&](int l) { return A(i, l); }, [&](int l) { return B(l, j); }, s);
-      C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * s;
-      i += di; j += dj;
-      if (i >= m) { i -= m; ++j; }
+    auto st = [&](int i, int j, double v) { C(i, j) = (beta == 0.0 ? 0.0 : beta * C(i, j)) + alpha * v; };
+    if (k > 0) wv_mm(f32, m, n, k, [&](int i, int l) { return A(i, l); }, [&](int l, int j) { return B(l, j); }, st);
+    else {
+      for (int q = lane_id(); q < m * n; q += 64) st(q % m, q / m, 0.0);
     }
   }
   wave_sync();

@@ -386,22 +386,14 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
         wave_sync();
         wc_add(e, WC_W_NONEMPTY, 1);
         // G_b = rho_o T^* into rows m .. m+mo of the stack
-        for (int q = lane; q < mob * Kt; q += 64) {
-          const int i = q % mob, j = q / mob;
-          double acc = 0.0;
-          acc = dotc(0, Ko, [&](int c) { return Ro(i, c); }, [&](int c) { return T(j, c); }, acc);
-          A(m + i, j) = acc;
-        }
+        wv_mm_f64(mob, Kt, Ko, [&](int i, int c) { return Ro(i, c); }, [&](int c, int j) { return T(j, c); },
+                  [&](int i, int j, double v) { A(m + i, j) = v; });
         wave_sync();
         fl += fl_gemm(mob, Kt, Ko);
         if (e.mode == 0) {
           double f2 = 0.0;
-          for (int q = lane; q < mob * mown; q += 64) {
-            const int i = q % mob, a = q / mob;
-            double acc = 0.0;
-            acc = dotc(0, Kt, [&](int j) { return A(m + i, j); }, [&](int j) { return Rown(a, j); }, acc);
-            f2 = fma(acc, acc, f2);
-          }
+          wv_mm_f64(mob, mown, Kt, [&](int i, int j) { return A(m + i, j); }, [&](int j, int a) { return Rown(a, j); },
+                    [&](int, int, double v) { f2 = fma(v, v, f2); });
           f2 = wave_sum64(f2);
           fl += fl_gemm(mob, mown, Kt);
           if (f2 == 0.0) { wt_add(e, WT_W_OMEGA, tw); continue; }
@@ -429,12 +421,15 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
       }
       MV Bp = wslot(e.wB[side], par), Et = Eslot(e, side, t);
       const bool root_of_sub = insub && t == u.r0[side];
-      for (int q = lane; q < mp * Kt; q += 64) {
-        const int i = q % mp, j = q / mp;
-        double acc = 0.0;
-        if (j < kt) { acc = dotc(0, kpar, [&](int l) { return Bp(i, l); }, [&](int l) { return Et(j, l); }, acc); }
-        else if (!root_of_sub) acc = Bp(i, kpar + (j - kt));   // identity part of diag(E_t, I)
-        A(m + i, j) = acc;
+      // B~_parent diag(E_t, I)^*: the transfer product, then the identity part
+      if (kpar > 0)
+        wv_mm_f64(mp, kt, kpar, [&](int i, int l) { return Bp(i, l); }, [&](int l, int j) { return Et(j, l); },
+                  [&](int i, int j, double v) { A(m + i, j) = v; });
+      else
+        for (int q = lane; q < mp * kt; q += 64) A(m + q % mp, q / mp) = 0.0;
+      for (int q = lane; q < mp * (Kt - kt); q += 64) {
+        const int i = q % mp, j = kt + q / mp;
+        A(m + i, j) = root_of_sub ? 0.0 : Bp(i, kpar + (j - kt));   // identity part of diag(E_t, I)
       }
       wave_sync();
       fl += fl_gemm(mp, kt, kpar);
@@ -489,12 +484,15 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
       const int ch = sn == 0 ? c1 : c2, rc = sn == 0 ? rc1 : rc2, off = sn == 0 ? 0 : rc1;
       const int kch = e.k[side][ch];
       MV Rc = wslot(e.wR[side], ch), Ec = Eslot(e, side, ch);
-      for (int q = lane; q < rc * K; q += 64) {
-        const int i = q % rc, j = q / rc;
-        double acc = 0.0;
-        if (j < kc) { acc = dotc(0, kch, [&](int l) { return Rc(i, l); }, [&](int l) { return Ec(l, j); }, acc); }
-        else acc = Rc(i, kch + (j - kc));
-        Vt(off + i, j) = acc;
+      // [R_ch E_ch, R_ch's update columns]: the transfer product, then a copy
+      if (kch > 0)
+        wv_mm(e.prec != 0, rc, kc, kch, [&](int i, int l) { return Rc(i, l); }, [&](int l, int j) { return Ec(l, j); },
+              [&](int i, int j, double v) { Vt(off + i, j) = v; });
+      else
+        for (int q = lane; q < rc * kc; q += 64) Vt(off + q % rc, q / rc) = 0.0;
+      for (int q = lane; q < rc * (K - kc); q += 64) {
+        const int i = q % rc, j = kc + q / rc;
+        Vt(off + i, j) = Rc(i, kch + (j - kc));
       }
       fl += fl_gemm(rc, kc, kch);
     }
@@ -600,7 +598,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     wv_apply_q(mr, mB, M, qtau, Q, r);
     fl += fl_gemm(mr, r, mB);
   }
-  wv_gemm(r, K, mr, 1.0, mv_t(Q), Vt, 0.0, wslot(e.wR[side], c));   // R_c = Q^* V~_c
+  wv_gemm(r, K, mr, 1.0, mv_t(Q), Vt, 0.0, wslot(e.wR[side], c), e.prec != 0);   // R_c = Q^* V~_c
   fl += fl_gemm(r, K, mr);
   if (lane == 0) e.wnewk[side][c] = r;
   if (is_leaf(e, c)) {
@@ -618,7 +616,7 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     const int kpar = e.k[side][e.parent[c]];
     MV T = al.take(r, kpar);
     MV Ec = Eslot(e, side, c);
-    wv_gemm(r, kpar, kc, 1.0, wslot(e.wR[side], c), Ec, 0.0, T);
+    wv_gemm(r, kpar, kc, 1.0, wslot(e.wR[side], c), Ec, 0.0, T, e.prec != 0);
     for (int q = lane; q < r * kpar; q += 64) Ec(q % r, q / r) = T(q % r, q / r);
     fl += fl_gemm(r, kpar, kc);
   }
@@ -639,14 +637,14 @@ __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
   const int rows = St.tin ? e.wnewk[0][t] : St.kt;
   MV P = al.take(rows, St.Ks);
   double fl = 0.0;
+  const bool f32 = e.prec != 0;
   if (St.tin) {
     MV Rt = wslot(e.wR[0], t);
-    for (int q = lane; q < rows * St.Ks; q += 64) {
-      const int i = q % rows, j = q / rows;
-      double acc = 0.0;
-      acc = dotc(0, St.Kt, [&](int l) { return Rt(i, l); }, [&](int l) { return St(l, j); }, acc);
-      P(i, j) = acc;
-    }
+    if (St.Kt > 0)
+      wv_mm(f32, rows, St.Ks, St.Kt, [&](int i, int l) { return Rt(i, l); }, [&](int l, int j) { return St(l, j); },
+            [&](int i, int j, double v) { P(i, j) = v; });
+    else
+      for (int q = lane; q < rows * St.Ks; q += 64) P(q % rows, q / rows) = 0.0;
     fl += fl_gemm(rows, St.Ks, St.Kt);
   } else {
     for (int q = lane; q < rows * St.Ks; q += 64) P(q % rows, q / rows) = St(q % rows, q / rows);
@@ -655,7 +653,7 @@ __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
   MV Sd = Sslot(e, b);
   if (St.sin) {
     const int rs = e.wnewk[1][s];
-    wv_gemm(rows, rs, St.Ks, 1.0, P, mv_t(wslot(e.wR[1], s)), 0.0, Sd);
+    wv_gemm(rows, rs, St.Ks, 1.0, P, mv_t(wslot(e.wR[1], s)), 0.0, Sd, f32);
     fl += fl_gemm(rows, rs, St.Ks);
   } else {
     for (int q = lane; q < rows * St.Ks; q += 64) Sd(q % rows, q / rows) = P(q % rows, q / rows);

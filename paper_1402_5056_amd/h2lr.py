@@ -54,7 +54,7 @@ class H2Error(RuntimeError):
 
 
 class h2_trunc(C.Structure):
-    _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32)]
+    _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -135,8 +135,13 @@ def _np(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
-def trunc(eps: float = 1e-4, mode: str = "block_rel", rank_cap: int = MAX_RANK) -> h2_trunc:
-    return h2_trunc(float(eps), MODES[mode] if isinstance(mode, str) else int(mode), int(rank_cap))
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+def trunc(eps: float = 1e-4, mode: str = "block_rel", rank_cap: int = MAX_RANK,
+          precision: str = "fp64") -> h2_trunc:
+    return h2_trunc(float(eps), MODES[mode] if isinstance(mode, str) else int(mode), int(rank_cap),
+                    PRECISIONS[precision] if isinstance(precision, str) else int(precision))
 
 
 _LIVE = weakref.WeakSet()
