@@ -81,8 +81,9 @@ def parse():
     ap.add_argument("--serve-sides", type=str, default="64,96,128")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=3)
-    ap.add_argument("--serve-release", choices=("idle", "eager"), default="idle",
-                    help="free finished requests only when no launch is in flight, or at once")
+    ap.add_argument("--serve-release", choices=("idle", "eager"), default="eager",
+                    help="free finished requests at once (stream-ordered frees), or only when no "
+                         "launch is in flight")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="only copy a float64 device buffer of this size once and exit: the "
                          "reference dispatch for scaling the HBM byte counters of a profile")
@@ -372,6 +373,7 @@ def bench_serve(args):
         "p50_ms": 1e3 * lat["p50_s"], "p99_ms": 1e3 * lat["p99_s"], "mean_ms": 1e3 * lat["mean_s"],
         "rhs_solved": int(sum(r.B.shape[1] for r in out)),
         "launches": srv.launches, "max_launches_in_flight": srv.max_inflight,
+        "admitted_while_launch_in_flight": srv.admitted_in_flight,
         "peak_budget_gib": srv.peak / 2**30,
         "release": args.serve_release, "release_host_s": srv.release_s,
         "worst_true_relres": worst,

@@ -22,6 +22,11 @@
  * - All device work is issued on the stream given to h2_ctx_create.  Calls
  *   that return host values (info/stats/export, h2_pcg counters) synchronise
  *   that stream; every other call may return before the device work ends.
+ * - Device memory of matrices, sparse matrices and tree tables is allocated
+ *   and released in the order of that stream (hipMallocAsync/hipFreeAsync),
+ *   so destroying an object does not wait for other streams; the stream
+ *   must therefore outlive every object created on the context, and a tree
+ *   must outlive the matrices built on it.
  * - Objects are not thread safe; use one context per host thread.
  */
 #ifndef H2LR_H

@@ -55,25 +55,67 @@ h2_status guarded(F &&f) {
   }
 }
 
-// Owning device allocation.
+// The device's default memory pool keeps freed memory for reuse instead of
+// returning it to the system (set once per device before its first
+// stream-ordered allocation).
+static void keep_pool_memory(hipStream_t s) {
+  static std::mutex mu;
+  static std::vector<int> done;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  (void)s;
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return;
+  hipMemPool_t pool;
+  HIPCHK(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = ~0ull;
+  HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  done.push_back(dev);
+}
+
+// Owning device allocation.  alloc(): hipMalloc / hipFree.  alloc_on(n, s):
+// stream-ordered (hipMallocAsync on s, complete when the call returns;
+// hipFreeAsync on s when released), so that freeing a matrix does not wait
+// for the work of other streams on the device.
 template <class T>
 struct Dev {
   T *p = nullptr;
   size_t n = 0;
+  hipStream_t s = nullptr;
+  bool ordered = false;
   Dev() = default;
   Dev(const Dev &) = delete;
   Dev &operator=(const Dev &) = delete;
-  ~Dev() { if (p) (void)hipFree(p); }
+  ~Dev() { release(); }
+  void release() {
+    if (p) {
+      if (ordered) (void)hipFreeAsync(p, s);
+      else (void)hipFree(p);
+      p = nullptr;
+    }
+  }
   void alloc(size_t count) {
-    if (p) { (void)hipFree(p); p = nullptr; }
+    release();
     n = count;
+    ordered = false;
     if (count) HIPCHK(hipMalloc(&p, count * sizeof(T)));
   }
-  void upload(const std::vector<T> &h, hipStream_t s) {
-    alloc(h.size());
-    if (n) HIPCHK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+  void alloc_on(size_t count, hipStream_t st) {
+    release();
+    n = count;
+    s = st;
+    ordered = true;
+    if (count) {
+      keep_pool_memory(st);
+      HIPCHK(hipMallocAsync(reinterpret_cast<void **>(&p), count * sizeof(T), st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
   }
-  void zero(hipStream_t s) { if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
+  void upload(const std::vector<T> &h, hipStream_t st) {
+    alloc_on(h.size(), st);
+    if (n) HIPCHK(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+  void zero(hipStream_t st) { if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), st)); }
 };
 
 }  // namespace
@@ -336,25 +378,25 @@ static void mat_alloc(h2_mat_s &m) {
   const size_t nc = ct.nc;
   hipStream_t s = m.ctx->stream;
   for (int side = 0; side < 2; ++side) {
-    m.d_k[side].alloc(nc); m.d_k[side].zero(s);
-    m.d_rho_m[side].alloc(nc); m.d_rho_m[side].zero(s);
-    m.d_wrho_m[side].alloc(nc); m.d_wB_m[side].alloc(nc); m.d_wnewk[side].alloc(nc);
-    m.d_leaf[side].alloc(nc * LS * KC);
-    m.d_E[side].alloc(nc * KC * KC);
-    m.d_rho[side].alloc(nc * KC * KC);
-    m.d_wrho[side].alloc(nc * KM * KM);
-    m.d_wB[side].alloc(nc * KM * KM);
-    m.d_wR[side].alloc(nc * KM * KM);
+    m.d_k[side].alloc_on(nc, s); m.d_k[side].zero(s);
+    m.d_rho_m[side].alloc_on(nc, s); m.d_rho_m[side].zero(s);
+    m.d_wrho_m[side].alloc_on(nc, s); m.d_wB_m[side].alloc_on(nc, s); m.d_wnewk[side].alloc_on(nc, s);
+    m.d_leaf[side].alloc_on(nc * LS * KC, s);
+    m.d_E[side].alloc_on(nc * KC * KC, s);
+    m.d_rho[side].alloc_on(nc * KC * KC, s);
+    m.d_wrho[side].alloc_on(nc * KM * KM, s);
+    m.d_wB[side].alloc_on(nc * KM * KM, s);
+    m.d_wR[side].alloc_on(nc * KM * KM, s);
   }
-  m.d_S.alloc((size_t)std::max(m.nadm, 1) * KC * KC);
-  m.d_N.alloc((size_t)std::max(m.nnear, 1) * LS * LS);
-  m.d_xh.alloc(nc * KC * BC);
-  m.d_yh.alloc(nc * KC * BC);
-  m.d_buf.alloc((size_t)NBUF * ct.n * BC);
-  m.d_bcols.alloc(NBUF); m.d_bcols.zero(s);
-  m.d_err.alloc(4); m.d_err.zero(s);
-  m.d_flops.alloc(1 + NWAVE); m.d_flops.zero(s);
-  m.d_wscr.alloc((size_t)NWAVE * WGLOB);
+  m.d_S.alloc_on((size_t)std::max(m.nadm, 1) * KC * KC, s);
+  m.d_N.alloc_on((size_t)std::max(m.nnear, 1) * LS * LS, s);
+  m.d_xh.alloc_on(nc * KC * BC, s);
+  m.d_yh.alloc_on(nc * KC * BC, s);
+  m.d_buf.alloc_on((size_t)NBUF * ct.n * BC, s);
+  m.d_bcols.alloc_on(NBUF, s); m.d_bcols.zero(s);
+  m.d_err.alloc_on(4, s); m.d_err.zero(s);
+  m.d_flops.alloc_on(1 + NWAVE, s); m.d_flops.zero(s);
+  m.d_wscr.alloc_on((size_t)NWAVE * WGLOB, s);
 }
 
 // Device bytes a matrix holds now: storage, work areas, task lists, PCG
@@ -930,10 +972,10 @@ struct Planner {
 static void upload_tasks(h2_mat_s &m, TaskList &tl, const std::vector<Task> &tasks,
                          const std::vector<int> &aux) {
   (void)m;
-  tl.d.alloc(tasks.size());
+  tl.d.alloc_on(tasks.size(), m.stream);
   if (!tasks.empty())
     HIPCHK(hipMemcpy(tl.d.p, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
-  tl.aux.alloc(aux.size());
+  tl.aux.alloc_on(aux.size(), m.stream);
   if (!aux.empty())
     HIPCHK(hipMemcpy(tl.aux.p, aux.data(), aux.size() * sizeof(int), hipMemcpyHostToDevice));
   tl.count = (int)tasks.size();
@@ -967,7 +1009,7 @@ static bool g_lds_attr_set = false;
 // Upload env when it changed since the last upload (blocking copy, so the
 // host struct may change afterwards).
 static void sync_env(h2_mat_s &m) {
-  if (!m.d_env.p) m.d_env.alloc(1);
+  if (!m.d_env.p) m.d_env.alloc_on(1, m.stream);
   if (!m.env_valid || std::memcmp(&m.env_uploaded, &m.env, sizeof(DevEnv)) != 0) {
     HIPCHK(hipMemcpy(m.d_env.p, &m.env, sizeof(DevEnv), hipMemcpyHostToDevice));
     m.env_uploaded = m.env;
@@ -1308,7 +1350,7 @@ h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n) {
       for (int i = 0; i < n; ++i) counters[i] = (int64_t)h[i];
     }
     if (enable) {
-      if (!m->d_prof.p) m->d_prof.alloc(PROF_LEN);
+      if (!m->d_prof.p) m->d_prof.alloc_on(PROF_LEN, m->stream);
       m->d_prof.zero(s);
       m->env.prof = m->d_prof.p;
     } else {
@@ -1513,7 +1555,7 @@ h2_status h2_product(h2_mat z, double alpha, h2_mat x, h2_mat y, const h2_trunc 
       z->prod_alpha = alpha;
     }
     const DevEnv envs[3] = {z->env, operand_env(*x, *z), operand_env(*y, *z)};
-    if (!z->d_env3.p) z->d_env3.alloc(3);
+    if (!z->d_env3.p) z->d_env3.alloc_on(3, z->stream);
     HIPCHK(hipMemcpyAsync(z->d_env3.p, envs, sizeof envs, hipMemcpyHostToDevice, z->stream));
     HIPCHK(hipStreamSynchronize(z->stream));
     run_tasks(*z, z->prod, NT, z->d_env3.p);
@@ -1962,7 +2004,7 @@ h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double
       REQUIRE(y.k >= 1 && y.k <= BC, "nrhs must be in [1, H2_MAX_COLS]");
       y.g = grid_for(y.n);
       const size_t need = (size_t)(4 * y.n + NP + 8) * y.k;
-      if (y.l->d_pcg.n < need) y.l->d_pcg.alloc(need);
+      if (y.l->d_pcg.n < need) y.l->d_pcg.alloc_on(need, y.l->stream);
       double *base = y.l->d_pcg.p;
       y.R = base;
       y.Z = y.R + (size_t)y.n * y.k;
@@ -2166,7 +2208,7 @@ h2_status h2_pcg(h2_csr a, h2_mat l, const double *b, double *x, double rtol, in
   return guarded([&] {
     pcg_check_args(a, l, b, x, rtol, maxit);
     const size_t need = (size_t)4 * a->n + PCG_PART + 8;
-    if (l->d_pcg.n < need) l->d_pcg.alloc(need);
+    if (l->d_pcg.n < need) l->d_pcg.alloc_on(need, l->stream);
     pcg_run(a, l, b, x, rtol, maxit, iters, relres, l->d_pcg.p, false);
   });
 }

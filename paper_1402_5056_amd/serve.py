@@ -19,9 +19,12 @@ Scheduling (host side only; every numerical step runs in the h2lr library):
   requests are solved by one batched PCG (``h2_pcg_batched``: one CG
   iteration per column; per iteration the preconditioner applications of
   all requests, all columns of a request at once, in one launch);
-* release: device memory of finished requests returns to the budget when it
-  is freed: when no launch is in flight ("idle", the default: freeing device
-  memory may wait for the whole device), or at once ("eager").
+* release: a request's device memory returns to the budget as soon as its
+  own results are back ("eager", the default): the library frees matrix
+  memory in stream order (hipFreeAsync on the matrix's stream), so a release
+  does not wait for launches still running on other streams and requests
+  are admitted into the freed memory while those launches continue.
+  "idle" frees only when no launch is in flight (for comparison).
 
 Latency of a request = completion time - arrival time.
 """
@@ -67,7 +70,7 @@ class Request:
 class Server:
     def __init__(self, budget_bytes: int, eps: float = 1e-4, eta: float = 2.0, leaf: int = 32,
                  rtol: float = 1e-8, maxit: int = 500, slots: int = 2, max_batch: int = 32,
-                 device: int = 0, release: str = "idle"):
+                 device: int = 0, release: str = "eager"):
         self.budget = int(budget_bytes)
         self.tr = h2lr.trunc(eps, "block_rel", 32)
         self.eta, self.leaf, self.rtol, self.maxit = eta, leaf, rtol, maxit
@@ -79,6 +82,7 @@ class Server:
         self.peak = 0
         self.launches = 0
         self.max_inflight = 0
+        self.admitted_in_flight = 0    # requests admitted while another launch was running
         if release not in ("idle", "eager"):
             raise ValueError("release must be 'idle' or 'eager'")
         self.release = release
@@ -147,7 +151,7 @@ class Server:
             while nxt < len(pending) and pending[nxt].arrival <= now:
                 waiting.append(pending[nxt])
                 nxt += 1
-            # release finished requests when nothing is in flight
+            # release finished requests (at once, or when nothing is in flight)
             if to_release and (not jobs or self.release == "eager"):
                 for r in to_release:
                     self._release(r)
@@ -179,6 +183,8 @@ class Server:
                     continue
                 self.used += r.nbytes
                 self.peak = max(self.peak, self.used)
+                if jobs:
+                    self.admitted_in_flight += 1
                 r.status, r.t_admit = "admitted", time.perf_counter() - t0
                 admitted[slot].append(r)
             # launch every free slot that holds admitted requests

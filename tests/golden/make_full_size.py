@@ -10,8 +10,14 @@ the smallest truncation margin over all recompressions of the
 factorisation, norms of z = (L L^*)^{-1} b and of the PCG solution x, and
 z, x at 512 seeded sample indices (original index order).
 
-    python tests/golden/make_full_size.py 256 10 11
-    python tests/golden/make_full_size.py 512 20 21
+With --spread the factorisation is repeated with LAPACK's gesvd instead of
+gesdd in the recompression SVDs (same definition, other rounding) and the
+relative differences of z and x that this causes are stored as well: the
+rounding sensitivity of the method itself at this size, against which
+another implementation's deviation is judged.
+
+    python tests/golden/make_full_size.py 256 10 11 --spread
+    python tests/golden/make_full_size.py 512 20 21 --spread
 """
 import json
 import os
@@ -32,7 +38,15 @@ from oracle.trees import build_block_tree, build_cluster_tree  # noqa: E402
 NSAMPLE = 512
 
 
-def main(side: int, sseed: int, rseed: int):
+def _gesvd(M):
+    import scipy.linalg as sl
+    if M.shape[0] == 0 or M.shape[1] == 0:
+        return np.zeros((M.shape[0], 0)), np.zeros(0)
+    U, sig, _ = sl.svd(M, full_matrices=False, lapack_driver="gesvd")
+    return U, sig
+
+
+def main(side: int, sseed: int, rseed: int, spread: bool = False):
     p = w.problem(side, sigma_seed=sseed, rhs_seed=rseed)
     ct = build_cluster_tree(p["coords"], 32)
     bt = build_block_tree(ct, 2.0)
@@ -62,6 +76,25 @@ def main(side: int, sseed: int, rseed: int):
         "x": [float(v) for v in x[idx]],
         "oracle_setup_s": t1 - t0, "oracle_solve_s": t2 - t1,
     }
+    if spread:
+        import oracle.update as o_update
+        saved = o_update.svd_left
+        o_update.svd_left = _gesvd
+        try:
+            L2 = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(1e-4, "block_rel", 32), {})
+        finally:
+            o_update.svd_left = saved
+        z2 = precond_apply(L2, p["b"])
+        x2, it2, _ = pcg(p["A"], p["b"], lambda r: precond_apply(L2, r), rtol=1e-8)
+        out["spread_svd_routine"] = {
+            "what": "relative change of z and x when the recompression SVDs use gesvd instead of gesdd",
+            "z": float(np.linalg.norm(z2 - z) / np.linalg.norm(z)),
+            "z_sampled": float(np.linalg.norm((z2 - z)[idx]) / np.linalg.norm(z[idx])),
+            "x": float(np.linalg.norm(x2 - x) / np.linalg.norm(x)),
+            "x_sampled": float(np.linalg.norm((x2 - x)[idx]) / np.linalg.norm(x[idx])),
+            "pcg_iters": int(it2),
+            "ranks_equal": bool(np.array_equal(L.k[0], L2.k[0]) and np.array_equal(L.k[1], L2.k[1])),
+        }
     path = os.path.join(HERE, f"p1_square_{side}_sigma.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=0)
@@ -69,4 +102,4 @@ def main(side: int, sseed: int, rseed: int):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]), int(sys.argv[2]), int(sys.argv[3]))
+    main(int(sys.argv[1]), int(sys.argv[2]), int(sys.argv[3]), "--spread" in sys.argv[4:])

@@ -2,7 +2,8 @@
  * host logic (argument checks, planning, job and busy bookkeeping, byte
  * accounting): "device" memory is host memory, copies are memmove, kernel
  * launches and events do nothing.  No numerical result is meaningful under
- * it.  Exports the runtime symbols the library imports, versioned hip_4.2. */
+ * it.  Exports the runtime symbols the library imports, versioned hip_4.2
+ * (the stream-ordered allocator hip_5.1). */
 #include <stdlib.h>
 #include <string.h>
 #include <stddef.h>
@@ -11,6 +12,10 @@ typedef struct { unsigned x, y, z; } dim3;
 static char dummy[64];
 hipError_t hipMalloc(void **p, size_t n) { *p = calloc(1, n ? n : 1); return *p ? 0 : 2; }
 hipError_t hipFree(void *p) { free(p); return 0; }
+hipError_t hipMallocAsync(void **p, size_t n, void *st) { return hipMalloc(p, n); }
+hipError_t hipFreeAsync(void *p, void *st) { free(p); return 0; }
+hipError_t hipDeviceGetDefaultMemPool(void **pool, int dev) { *pool = (void *)dummy; return 0; }
+hipError_t hipMemPoolSetAttribute(void *pool, int attr, void *value) { return 0; }
 hipError_t hipMemcpy(void *d, const void *s, size_t n, int k) { memmove(d, s, n); return 0; }
 hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, int k, void *st) { memmove(d, s, n); return 0; }
 hipError_t hipMemsetAsync(void *d, int v, size_t n, void *st) { memset(d, v, n); return 0; }

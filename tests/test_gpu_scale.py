@@ -1,0 +1,183 @@
+"""Parity at the benchmarked tree shapes (P1 FEM with sigma piecewise
+constant on 8 x 8 subdomains, bisection tree, leaf 32, eta 2,
+block-relative 1e-4, Sections 3-7).
+
+* 128 x 128 grid (n = 16,129, depth 9): against the live oracle with the
+  protocol for large n: equal rank vectors (the oracle's smallest truncation
+  margin must exceed 1e-8), the factor difference L_gpu - L_oracle by 30
+  power iterations on its normal operator and by 8 seeded probe vectors,
+  (L L^*)^{-1} r on the probes, PCG iteration counts and solutions.
+* 256 x 256 (n = 65,025) and 511^2 (n = 261,121, the largest single-problem
+  workload): against stored oracle results (tests/golden/, written by
+  make_full_size.py from oracle/ only; the oracle takes 4 and 40 minutes
+  there): z = (L L^*)^{-1} b and the PCG solution x at 512 sampled indices,
+  their norms, the iteration count and the largest ranks.
+
+At these sizes rounding inside the recompression SVDs moves the factor by
+more than 1e-12 (thousands of dependent truncations): the oracle's own
+factor changes by that much when its SVDs use another LAPACK routine.  The
+bar is therefore the larger of 1e-12 and that measured spread."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.arith import cholesky as o_cholesky, precond_apply as o_precond
+from oracle.h2 import TruncParams, from_csr as o_from_csr, matvec as o_matvec
+from oracle.solve import pcg as o_pcg
+from oracle.trees import build_block_tree, build_cluster_tree
+from tests.helpers import gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    gpu()
+    from paper_1402_5056_amd import h2lr
+    return h2lr
+
+
+def _gpu_factor(lib, p):
+    ctx = lib.h2_ctx_create(0)
+    ct = lib.h2_ctree_build(ctx, p["coords"], 32)
+    bt = lib.h2_btree_build(ctx, ct, 2.0)
+    L = lib.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
+    lib.h2_cholesky(L, lib.trunc(1e-4, "block_rel", 32))
+    return ctx, ct, L
+
+
+def _gesvd(M):
+    import scipy.linalg as sl
+    if M.shape[0] == 0 or M.shape[1] == 0:
+        return np.zeros((M.shape[0], 0)), np.zeros(0)
+    U, sig, _ = sl.svd(M, full_matrices=False, lapack_driver="gesvd")
+    return U, sig
+
+
+def _spec_rel(apply_diff, apply_ref, n, seed=31, iters=30):
+    """||D||_2 / ||R||_2 by power iteration on D^* D and R^* R; apply_*(v,
+    trans) applies the operator or its adjoint."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(n)
+    vl = v.copy()
+    sd = sl = 0.0
+    for _ in range(iters):
+        v /= np.linalg.norm(v)
+        v = apply_diff(apply_diff(v, False), True)
+        sd = np.sqrt(np.linalg.norm(v))
+        vl /= np.linalg.norm(vl)
+        vl = apply_ref(apply_ref(vl, False), True)
+        sl = np.sqrt(np.linalg.norm(vl))
+    return sd / sl
+
+
+def test_parity_128(lib, monkeypatch):
+    """The bar: at this size the factor is sensitive to rounding inside the
+    recompression SVDs - computing the oracle's own SVDs with LAPACK's gesvd
+    instead of gesdd (same definition) moves its factor by ~5e-10 - so the
+    GPU factor must be no farther from the oracle than that spread (and than
+    1e-12), with equal rank vectors and equal PCG iteration counts."""
+    import oracle.update as o_update
+    print("case: parity 128x128 (n = 16129) against the oracle", flush=True)
+    torch = gpu()
+    p = w.problem(128, sigma_seed=10, rhs_seed=11)
+    n = p["A"].shape[0]
+    oc = build_cluster_tree(p["coords"], 32)
+    ob = build_block_tree(oc, 2.0)
+    tp = TruncParams(1e-4, "block_rel", 32)
+    stats = {"margins": []}
+    Lo = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), tp, stats)
+    margin = min(stats["margins"])
+    print(f"  oracle smallest truncation margin {margin:.2e}", flush=True)
+    assert margin > 1e-8
+    with monkeypatch.context() as mp:
+        mp.setattr(o_update, "svd_left", _gesvd)
+        Lo2 = o_cholesky(o_from_csr(p["A"], oc, ob, lower=True), tp)
+    assert np.array_equal(Lo2.k[0], Lo.k[0]) and np.array_equal(Lo2.k[1], Lo.k[1])
+    ctx, ct, L = _gpu_factor(lib, p)
+    kr, kc = lib.h2_mat_ranks(L, oc.nc)
+    assert np.array_equal(kr, Lo.k[0]) and np.array_equal(kc, Lo.k[1])
+    assert lib.h2_mat_stats(L)[0] == Lo.storage_values()
+
+    def gpu_apply(v, trans):
+        x = torch.tensor(v, device="cuda")
+        y = torch.zeros_like(x)
+        lib.h2_matvec(L, x, y, trans=trans)
+        return y.cpu().numpy()
+
+    ref = lambda v, t: o_matvec(Lo, v, trans=t)
+    spread = _spec_rel(lambda v, t: o_matvec(Lo2, v, trans=t) - ref(v, t), ref, n)
+    rel_op = _spec_rel(lambda v, t: gpu_apply(v, t) - ref(v, t), ref, n)
+    bar = max(TOL, spread)
+    print(f"  ||L_gpu - L_oracle||_2 / ||L_oracle||_2 ~ {rel_op:.2e}; oracle gesdd -> gesvd spread "
+          f"{spread:.2e} (30 power iterations)", flush=True)
+    assert rel_op <= bar
+    probes = w.gaussian(n, 8, 41)
+    worst = max(np.linalg.norm(gpu_apply(probes[:, i], False) - ref(probes[:, i], False)) /
+                np.linalg.norm(ref(probes[:, i], False)) for i in range(8))
+    print(f"  probes: max ||(L_gpu - L_oracle) v|| / ||L_oracle v|| = {worst:.2e}", flush=True)
+    assert worst <= bar
+    R = torch.tensor(np.ascontiguousarray(probes.T), device="cuda")
+    Z = torch.zeros_like(R)
+    lib.h2_precond(L, R, Z)
+    zo = np.stack([o_precond(Lo, probes[:, i]) for i in range(8)])
+    zo2 = np.stack([o_precond(Lo2, probes[:, i]) for i in range(8)])
+    zerr = np.linalg.norm(Z.cpu().numpy() - zo) / np.linalg.norm(zo)
+    zspread = np.linalg.norm(zo2 - zo) / np.linalg.norm(zo)
+    print(f"  (L L^*)^-1 r on the probes: {zerr:.2e} (spread {zspread:.2e})", flush=True)
+    assert zerr <= max(TOL, zspread)
+    A = lib.h2_csr_create(ctx, p["A"])
+    b = torch.tensor(p["b"], device="cuda")
+    x = torch.zeros_like(b)
+    it, rel, ok = lib.h2_pcg(A, L, b, x, 1e-8, 100)
+    xo, ito, relo = o_pcg(p["A"], p["b"], lambda r: o_precond(Lo, r))
+    xo2, ito2, _ = o_pcg(p["A"], p["b"], lambda r: o_precond(Lo2, r))
+    xerr = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    xspread = np.linalg.norm(xo2 - xo) / np.linalg.norm(xo)
+    print(f"  PCG: iterations {it} (oracle {ito}), ||x_gpu - x_oracle|| / ||x_oracle|| = {xerr:.2e} "
+          f"(spread {xspread:.2e}; reported against 1e-12)", flush=True)
+    assert ok and it == ito == ito2
+    assert xerr <= max(TOL, xspread)
+
+
+@pytest.mark.parametrize("side", [256, 512])
+def test_full_size_against_stored_oracle(lib, side):
+    path = os.path.join(GOLDEN, f"p1_square_{side}_sigma.json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle results {os.path.basename(path)} not generated")
+    with open(path) as f:
+        g = json.load(f)
+    print(f"case: {g['workload']} (n = {g['n']}) against stored oracle results", flush=True)
+    torch = gpu()
+    p = w.problem(side, sigma_seed=g["sigma_seed"], rhs_seed=g["rhs_seed"])
+    assert p["A"].shape[0] == g["n"]
+    ctx, ct, L = _gpu_factor(lib, p)
+    print("  factorisation done", flush=True)
+    _, kr, kc = lib.h2_mat_stats(L)
+    assert [kr, kc] == g["max_rank"]
+    idx = np.asarray(g["idx"])
+    b = torch.tensor(p["b"], device="cuda")
+    z = torch.zeros_like(b)
+    lib.h2_precond(L, b, z)
+    zh = z.cpu().numpy()
+    zerr = np.linalg.norm(zh[idx] - np.asarray(g["z"])) / np.linalg.norm(g["z"])
+    nerr = abs(np.linalg.norm(zh) - g["z_norm"]) / g["z_norm"]
+    sp = g["spread_svd_routine"]
+    zbar = max(TOL, sp["z_sampled"])
+    print(f"  z = (L L^*)^-1 b: sampled {zerr:.2e}, norm {nerr:.2e} (oracle gesdd -> gesvd spread "
+          f"{sp['z_sampled']:.2e} sampled, {sp['z']:.2e} whole)", flush=True)
+    assert zerr <= zbar and nerr <= max(TOL, sp["z"])
+    A = lib.h2_csr_create(ctx, p["A"])
+    x = torch.zeros_like(b)
+    it, rel, ok = lib.h2_pcg(A, L, b, x, 1e-8, 100)
+    xh = x.cpu().numpy()
+    xerr = np.linalg.norm(xh[idx] - np.asarray(g["x"])) / np.linalg.norm(g["x"])
+    print(f"  PCG: iterations {it} (oracle {g['pcg_iters']}), x sampled {xerr:.2e}, "
+          f"relres {rel:.2e} (oracle {g['pcg_relres']:.2e})", flush=True)
+    assert ok and it == g["pcg_iters"]
+    assert xerr <= max(TOL, sp["x_sampled"])

@@ -46,6 +46,7 @@ def test_serve_mix_equals_alone(serve):
     print(f"  launches {server.launches}, max in flight {server.max_inflight}, latency "
           f"{serve.latency_summary(reqs)}", flush=True)
     assert server.launches >= 2
+    assert server.max_inflight >= 2
     assert server.used == 0
     for r in reqs:
         alone = serve.Server(8 << 30, eps=1e-5, leaf=16, rtol=1e-10, slots=1)
@@ -63,6 +64,28 @@ def test_serve_mix_equals_alone(serve):
             xo, ito, _ = o_pcg(r.A, r.B[:, j], lambda v: o_precond(L, v), rtol=1e-10)
             assert ito == r.iters[j]
             assert np.linalg.norm(r.result[:, j] - xo) / np.linalg.norm(xo) < 1e-10
+
+
+def test_serve_admits_while_running(serve):
+    """Continuous batching: a large request occupies one launch slot; small
+    requests arriving later are admitted, factorised, solved and released on
+    the other slot while the large launch is still running."""
+    print("case: small requests served while a large one runs", flush=True)
+    specs = [(0.0, 96, 1, 1), (0.05, 16, 2, 1), (0.1, 16, 3, 2), (0.15, 24, 4, 1)]
+    server = serve.Server(8 << 30, leaf=32, slots=2, max_batch=1)
+    reqs = server.run(_requests(serve, specs), log=lambda m: print("  " + m, flush=True))
+    assert all(r.status == "done" for r in reqs), [(r.rid, r.status, r.error) for r in reqs]
+    big = reqs[0]
+    early = [r.rid for r in reqs[1:] if r.t_done < big.t_done]
+    print(f"  large request done at {big.t_done:.2f}s; small ones done before it: {early}; "
+          f"admitted while a launch ran: {server.admitted_in_flight}", flush=True)
+    assert len(early) >= 2
+    assert server.admitted_in_flight >= 2 and server.max_inflight == 2
+    assert server.used == 0
+    for r in reqs:
+        for j in range(r.B.shape[1]):
+            x = r.result[:, j]
+            assert np.linalg.norm(r.B[:, j] - r.A @ x) / np.linalg.norm(r.B[:, j]) < 1e-8
 
 
 def test_serve_budget_and_rejection(serve):
