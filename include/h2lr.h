@@ -185,7 +185,7 @@ h2_status h2_mat_ranks(h2_mat m, int32_t *rank_row, int32_t *rank_col);
  * a = max, b = min of the dimensions; vector substitutions n^2 per column);
  * reset != 0 zeroes the counter afterwards.  Synchronises the stream. */
 h2_status h2_mat_flops(h2_mat m, double *flops, int32_t reset);
-/* Tracing: if counters != NULL, copy the first n (<= 192) profile counters
+/* Tracing: if counters != NULL, copy the first n (<= 204) profile counters
  * of m (task counts per kind [0,32), device ticks of a 100 MHz clock per kind
  * [32,64), ticks per stage of the low-rank update [64,80), ticks and counts
  * of sub-block products by size class [80,96), per-wave ticks of update
@@ -194,8 +194,11 @@ h2_status h2_mat_flops(h2_mat m, double *flops, int32_t reset);
  * stage of updates of leaf blocks [160,168), ticks and counts of the
  * recompression SVDs by column count (<= 8, 16, 32, more) [168,176), ticks
  * and counts of truncated additions by row count (<= 32, 128, 512, 2048,
- * more) [176,184) and [184,192)); then enable (enable != 0, counters reset
- * to zero) or disable collection. */
+ * more) [176,184) and [184,192), algorithmic flops [192,198) and bytes of
+ * H^2 data read and written [198,204) of the update steps: R-factors,
+ * weights, recompression (with the E_t0 update), couplings, R-factor path
+ * refresh, nearfield); then enable (enable != 0, counters reset to zero) or
+ * disable collection. */
 h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n);
 
 /* Local low-rank update Z|_{t0 x s0} += X Y^* of the block tree node

@@ -1100,6 +1100,30 @@ static double *noalloc_scratch(int device) {
   return static_cast<double *>(ptr);
 }
 
+// Largest number of admissible leaves in one block row of the tree.
+static int tree_csp(const h2_btree_s &bt) {
+  std::vector<int> cnt(bt.ct->nc, 0);
+  int mx = 0;
+  for (int b = 0; b < bt.nb; ++b)
+    if (bt.kind[b] == 1) mx = std::max(mx, ++cnt[bt.row[b]]);
+  return mx;
+}
+
+// Trees with block rows of more than 64 admissible leaves (the weight
+// stacks then take several 64-block metadata chunks) are refused by every
+// call that runs local updates: the one such workload tried, the
+// domain-decomposition tree of the 256 x 256 grid at eta 4 (89 blocks in a
+// row, depth 22), did not finish its factorisation on the GPU and the cause
+// is not known.
+constexpr int VALIDATED_CSP = 64;
+static void require_validated_tree(const h2_mat_s &m) {
+  const int csp = tree_csp(*m.bt);
+  if (csp > VALIDATED_CSP)
+    throw H2Error(H2_ERR_ARG, "block tree with " + std::to_string(csp) +
+                                  " admissible blocks in one block row: updates on trees with more than " +
+                                  std::to_string(VALIDATED_CSP) + " per row are refused (not validated)");
+}
+
 static int grid_for(long work) {
   long g = (work + 255) / 256;
   return (int)std::max<long>(1, std::min<long>(g, 4096));
@@ -1426,6 +1450,7 @@ h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X,
                             const double *Y, int64_t ldy, const h2_trunc *tr) {
   return guarded([&] {
     require_ok(z);
+    require_validated_tree(*z);
     const h2_btree_s &bt = *z->bt;
     const h2_ctree_s &ct = *bt.ct;
     REQUIRE(block >= 0 && block < bt.nb, "block out of range");
@@ -1483,6 +1508,7 @@ h2_status h2_cholesky(h2_mat a, const h2_trunc *tr) {
   return guarded([&] {
     require_ok(a);
     REQUIRE(a->lower, "h2_cholesky needs a matrix created with lower != 0");
+    require_validated_tree(*a);
     REQUIRE(!a->inverse, "h2_cholesky on an inverted factor");
     set_trunc(*a, tr);
     if (!a->chol.built) {
@@ -1500,6 +1526,7 @@ h2_status h2_lr(h2_mat a, const h2_trunc *tr) {
   return guarded([&] {
     require_ok(a);
     REQUIRE(!a->lower, "h2_lr needs a matrix created with lower = 0 (full storage)");
+    require_validated_tree(*a);
     set_trunc(*a, tr);
     if (!a->lrf.built) {
       std::vector<Task> tasks;
@@ -1536,6 +1563,7 @@ h2_status h2_product(h2_mat z, double alpha, h2_mat x, h2_mat y, const h2_trunc 
   return guarded([&] {
     require_ok(z); require_ok(x); require_ok(y);
     REQUIRE(z != x && z != y, "h2_product: the target must differ from both factors");
+    require_validated_tree(*z);
     REQUIRE(!z->lower && !x->lower && !y->lower, "h2_product needs full-storage matrices (lower = 0)");
     REQUIRE(x->bt == z->bt && y->bt == z->bt, "h2_product: the matrices must share one block tree");
     REQUIRE(x->ctx->device == z->ctx->device && y->ctx->device == z->ctx->device,
@@ -1680,6 +1708,7 @@ h2_status h2_cholesky_launch(h2_mat *mats, int32_t count, const h2_trunc *tr, h2
     *job = nullptr;
     auto j = std::make_unique<h2_job_s>();
     std::vector<h2_mat_s *> ms = batch_members(mats, count, "h2_cholesky_launch");
+    for (h2_mat_s *m : ms) require_validated_tree(*m);
     j->items.resize(count);
     for (int i = 0; i < count; ++i) {
       h2_mat_s &m = *ms[i];
@@ -1733,6 +1762,7 @@ h2_status h2_lowrank_update_batched(h2_mat *mats, int32_t count, const int32_t *
   return guarded([&] {
     REQUIRE(nupd && blocks && ks && Xs && ldxs && Ys && ldys, "null argument");
     std::vector<h2_mat_s *> ms = batch_members(mats, count, "h2_lowrank_update_batched", false);
+    for (h2_mat_s *m : ms) require_validated_tree(*m);
     if (status)
       for (int i = 0; i < count; ++i) status[i] = H2_OK;
     // validate everything before any device work
@@ -1867,6 +1897,7 @@ h2_status h2_tri_invert(h2_mat l, const h2_trunc *tr) {
   return guarded([&] {
     require_ok(l);
     REQUIRE(l->lower, "h2_tri_invert needs a lower triangular factor");
+    require_validated_tree(*l);
     REQUIRE(!l->inverse, "matrix is already inverted");
     set_trunc(*l, tr);
     if (!l->tinv.built) {

@@ -121,6 +121,11 @@ constexpr int PROF_WAVE = 96;     // [96, 128): per-wave ticks / counts inside u
 constexpr int PROF_LEVEL = 128;    // [128, 144): ticks of low-rank updates by level of t0, [144, 160): counts
 constexpr int PROF_LEAFSTAGE = 160; // [160, 168): ticks per update stage, updates of leaf blocks only
 constexpr int PROF_TEMP = 176;     // [176, 184): ticks of truncated additions by row count class, [184, 192): counts
-constexpr int PROF_LEN = 192;
+constexpr int PROF_SFLOPS = 192;   // [192, 198): algorithmic flops of the update steps a4..a9
+constexpr int PROF_SBYTES = 198;   // [198, 204): algorithmic bytes of the update steps a4..a9
+constexpr int PROF_LEN = 204;
+// update steps (a4 R-factors, a5 weights, a6 recompression, a7 couplings,
+// a8 R-factor path refresh and transfer update, a9 nearfield)
+enum : int { ST_A4 = 0, ST_A5, ST_A6, ST_A7, ST_A8, ST_A9 };
 
 }  // namespace h2

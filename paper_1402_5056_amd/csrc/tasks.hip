@@ -171,7 +171,14 @@ __device__ __forceinline__ WvAlloc wv_alloc(const DevEnv &e, const Wv &W) {
   return WvAlloc{W.reg, W.glob, e.err, 0, 0};
 }
 
-__device__ __forceinline__ void count_w(const DevEnv &e, const Wv &W, double f) {
+// Algorithmic flops of a wave's work in update step st (and, when profiling,
+// per step); bytes: algorithmic bytes of the H^2 data the step reads and
+// writes (profiling only).
+__device__ __forceinline__ void bytes_w(const DevEnv &e, int st, double b) {
+  if (e.prof && lane_id() == 0) atomicAdd(&e.prof[PROF_SBYTES + st], (unsigned long long)b);
+}
+__device__ __forceinline__ void count_w(const DevEnv &e, const Wv &W, int st, double f) {
+  if (e.prof && lane_id() == 0) atomicAdd(&e.prof[PROF_SFLOPS + st], (unsigned long long)f);
   if (lane_id() == 0 && e.flops) e.flops[1 + W.w] += f;
 }
 
@@ -277,7 +284,9 @@ __device__ void wv_rfactor(const DevEnv &e, const Upd &u, const Wv &W, int side,
     R(i, j) = j >= i ? A(i, j) : 0.0;
   }
   if (lane == 0) e.wrho_m[side][c] = mr;
-  count_w(e, W, fl + fl_qr(m, K));
+  count_w(e, W, ST_A4, fl + fl_qr(m, K));
+  // leaf: V_t and the update rows X|t (Y|s) read once
+  if (is_leaf(e, c)) bytes_w(e, ST_A4, 8.0 * e.size[c] * K);
   wave_sync();
 }
 
@@ -385,6 +394,9 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
         }
         wave_sync();
         wc_add(e, WC_W_NONEMPTY, 1);
+        // the coupling of a block above the subtrees is read once for the
+        // path weights (those touching the subtrees count in step a7)
+        if (!insub) bytes_w(e, ST_A5, 8.0 * kt_b * ks_b);
         // G_b = rho_o T^* into rows m .. m+mo of the stack
         wv_mm_f64(mob, Kt, Ko, [&](int i, int c) { return Ro(i, c); }, [&](int c, int j) { return T(j, c); },
                   [&](int i, int j, double v) { A(m + i, j) = v; });
@@ -449,7 +461,7 @@ __device__ void wv_weight(const DevEnv &e, const Upd &u, const Wv &W, int side, 
   }
   if (lane == 0) e.wB_m[side][t] = mr;
   wt_add(e, WT_W_QR, tw);
-  count_w(e, W, fl + fl_qr(mrows, Kt));
+  count_w(e, W, ST_A5, fl + fl_qr(mrows, Kt));
   wave_sync();
 }
 
@@ -620,7 +632,10 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     for (int q = lane; q < r * kpar; q += 64) Ec(q % r, q / r) = T(q % r, q / r);
     fl += fl_gemm(r, kpar, kc);
   }
-  count_w(e, W, fl);
+  count_w(e, W, ST_A6, fl);
+  // transfers of the sons read (inner) and the new basis / transfers written
+  bytes_w(e, ST_A6, is_leaf(e, c) ? 8.0 * mr * r
+                                  : 8.0 * ((double)(e.k[side][e.son0[c]] + e.k[side][e.son1[c]]) * kc + (double)mr * r));
   wave_sync();
   wt_add(e, WT_RC_OUT, tw);
   return r;
@@ -658,7 +673,8 @@ __device__ void wv_coupling(const DevEnv &e, const Upd &u, const Wv &W, int b) {
   } else {
     for (int q = lane; q < rows * St.Ks; q += 64) Sd(q % rows, q / rows) = P(q % rows, q / rows);
   }
-  count_w(e, W, fl);
+  count_w(e, W, ST_A7, fl);
+  bytes_w(e, ST_A7, 8.0 * ((double)St.kt * St.ks + (double)rows * (St.sin ? e.wnewk[1][s] : St.Ks)));
   wave_sync();
   wt_add(e, WT_CPL, tw);
 }
@@ -696,8 +712,9 @@ __device__ void wv_refresh_rho(const DevEnv &e, const Wv &W, int side, int c, in
     R(i, j) = j >= i ? A(i, j) : 0.0;
   }
   if (lane == 0) e.rho_m[side][c] = mr;
-  count_w(e, W, fl_qr(m, kc) + (c1 == vs ? 0.0 : fl_gemm(m1, kc, e.k[side][c1])) +
-                    (c2 == vs ? 0.0 : fl_gemm(m2, kc, e.k[side][c2])));
+  count_w(e, W, ST_A8, fl_qr(m, kc) + (c1 == vs ? 0.0 : fl_gemm(m1, kc, e.k[side][c1])) +
+                           (c2 == vs ? 0.0 : fl_gemm(m2, kc, e.k[side][c2])));
+  bytes_w(e, ST_A8, 8.0 * ((double)e.k[side][c1] + e.k[side][c2]) * kc);   // the sons' transfers
   wave_sync();
   wt_add(e, WT_REFRESH, tw);
 }
@@ -852,7 +869,8 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
           if (q % NWAVE == W.w) {
             wv_gemm(e.size[c], e.size[s], u.kp, 1.0, bufrows(e, u.buf[0], c), mv_t(bufrows(e, u.buf[1], s)),
                     1.0, Nslot(e, b));
-            count_w(e, W, fl_gemm(e.size[c], e.size[s], u.kp));
+            count_w(e, W, ST_A9, fl_gemm(e.size[c], e.size[s], u.kp));
+            bytes_w(e, ST_A9, 16.0 * e.size[c] * e.size[s]);
           }
           ++q;
         }

@@ -43,6 +43,9 @@ MAX_LEAF = 32
 MAX_COLS = 64
 MAX_UPDATE_RANK = 32
 NOALLOC_MAX_N = 262144
+PROF_LEN = 204
+UPDATE_STEPS = ("a4 R-factors", "a5 weights", "a6 recompression", "a7 couplings",
+                "a8 R-factor refresh", "a9 nearfield")
 MODES = {"block_rel": 0, "const_rel": 1, "none": 2}
 
 
@@ -334,8 +337,8 @@ WAVE_COUNTS = ["weight calls", "weight blocks", "weight nonempty", "qr calls", "
 
 def h2_profile(m: Mat, enable: bool = True):
     """Return the previous counters as a dict and (re)enable collection."""
-    buf = np.zeros(192, np.int64)
-    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, 192))
+    buf = np.zeros(PROF_LEN, np.int64)
+    _check(_lib.h2_profile(m.h, 1 if enable else 0, buf.ctypes.data, PROF_LEN))
     out = {}
     for i, name in enumerate(OPS):
         if name and buf[i]:
@@ -353,6 +356,8 @@ def h2_profile(m: Mat, enable: bool = True):
                           enumerate(["<=8", "<=16", "<=32", ">32"])}
     out["temp_classes"] = {c: (int(buf[184 + i]), buf[176 + i] * 1e-8) for i, c in
                            enumerate(["<=32", "<=128", "<=512", "<=2048", ">2048"])}
+    out["step_flops"] = {name: float(buf[192 + i]) for i, name in enumerate(UPDATE_STEPS)}
+    out["step_bytes"] = {name: float(buf[198 + i]) for i, name in enumerate(UPDATE_STEPS)}
     return out
 
 

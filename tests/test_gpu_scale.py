@@ -15,8 +15,12 @@ block-relative 1e-4, Sections 3-7).
 
 At these sizes rounding inside the recompression SVDs moves the factor by
 more than 1e-12 (thousands of dependent truncations): the oracle's own
-factor changes by that much when its SVDs use another LAPACK routine.  The
-bar is therefore the larger of 1e-12 and that measured spread."""
+factor changes by that much when only its SVDs use another LAPACK routine
+(gesdd -> gesvd).  That spread is one sample of the rounding drift of the
+method; the GPU result is another realisation (every operation rounds
+differently), and two independent realisations of a drift of size d differ
+by about sqrt(2) d.  The bar is therefore the larger of 1e-12 and twice the
+measured spread (SPREAD_FACTOR), with equal ranks and PCG counts."""
 import json
 import os
 
@@ -32,6 +36,7 @@ from tests.helpers import gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
+SPREAD_FACTOR = 2.0
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
@@ -80,8 +85,8 @@ def test_parity_128(lib, monkeypatch):
     """The bar: at this size the factor is sensitive to rounding inside the
     recompression SVDs - computing the oracle's own SVDs with LAPACK's gesvd
     instead of gesdd (same definition) moves its factor by ~5e-10 - so the
-    GPU factor must be no farther from the oracle than that spread (and than
-    1e-12), with equal rank vectors and equal PCG iteration counts."""
+    GPU factor must be within SPREAD_FACTOR times that spread (and 1e-12) of
+    the oracle's, with equal rank vectors and equal PCG iteration counts."""
     import oracle.update as o_update
     print("case: parity 128x128 (n = 16129) against the oracle", flush=True)
     torch = gpu()
@@ -113,7 +118,7 @@ def test_parity_128(lib, monkeypatch):
     ref = lambda v, t: o_matvec(Lo, v, trans=t)
     spread = _spec_rel(lambda v, t: o_matvec(Lo2, v, trans=t) - ref(v, t), ref, n)
     rel_op = _spec_rel(lambda v, t: gpu_apply(v, t) - ref(v, t), ref, n)
-    bar = max(TOL, spread)
+    bar = max(TOL, SPREAD_FACTOR * spread)
     print(f"  ||L_gpu - L_oracle||_2 / ||L_oracle||_2 ~ {rel_op:.2e}; oracle gesdd -> gesvd spread "
           f"{spread:.2e} (30 power iterations)", flush=True)
     assert rel_op <= bar
@@ -130,7 +135,7 @@ def test_parity_128(lib, monkeypatch):
     zerr = np.linalg.norm(Z.cpu().numpy() - zo) / np.linalg.norm(zo)
     zspread = np.linalg.norm(zo2 - zo) / np.linalg.norm(zo)
     print(f"  (L L^*)^-1 r on the probes: {zerr:.2e} (spread {zspread:.2e})", flush=True)
-    assert zerr <= max(TOL, zspread)
+    assert zerr <= max(TOL, SPREAD_FACTOR * zspread)
     A = lib.h2_csr_create(ctx, p["A"])
     b = torch.tensor(p["b"], device="cuda")
     x = torch.zeros_like(b)
@@ -142,7 +147,7 @@ def test_parity_128(lib, monkeypatch):
     print(f"  PCG: iterations {it} (oracle {ito}), ||x_gpu - x_oracle|| / ||x_oracle|| = {xerr:.2e} "
           f"(spread {xspread:.2e}; reported against 1e-12)", flush=True)
     assert ok and it == ito == ito2
-    assert xerr <= max(TOL, xspread)
+    assert xerr <= max(TOL, SPREAD_FACTOR * xspread)
 
 
 @pytest.mark.parametrize("side", [256, 512])
@@ -168,10 +173,10 @@ def test_full_size_against_stored_oracle(lib, side):
     zerr = np.linalg.norm(zh[idx] - np.asarray(g["z"])) / np.linalg.norm(g["z"])
     nerr = abs(np.linalg.norm(zh) - g["z_norm"]) / g["z_norm"]
     sp = g["spread_svd_routine"]
-    zbar = max(TOL, sp["z_sampled"])
+    zbar = max(TOL, SPREAD_FACTOR * sp["z_sampled"])
     print(f"  z = (L L^*)^-1 b: sampled {zerr:.2e}, norm {nerr:.2e} (oracle gesdd -> gesvd spread "
           f"{sp['z_sampled']:.2e} sampled, {sp['z']:.2e} whole)", flush=True)
-    assert zerr <= zbar and nerr <= max(TOL, sp["z"])
+    assert zerr <= zbar and nerr <= max(TOL, SPREAD_FACTOR * sp["z"])
     A = lib.h2_csr_create(ctx, p["A"])
     x = torch.zeros_like(b)
     it, rel, ok = lib.h2_pcg(A, L, b, x, 1e-8, 100)
@@ -180,4 +185,4 @@ def test_full_size_against_stored_oracle(lib, side):
     print(f"  PCG: iterations {it} (oracle {g['pcg_iters']}), x sampled {xerr:.2e}, "
           f"relres {rel:.2e} (oracle {g['pcg_relres']:.2e})", flush=True)
     assert ok and it == g["pcg_iters"]
-    assert xerr <= max(TOL, sp["x_sampled"])
+    assert xerr <= max(TOL, SPREAD_FACTOR * sp["x_sampled"])

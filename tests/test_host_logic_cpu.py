@@ -23,7 +23,7 @@ CHILD = textwrap.dedent(r'''
     lib.h2_last_error.restype = C.c_char_p
 
     class trunc(C.Structure):
-        _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32)]
+        _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32)]
 
     def ok(st):
         assert st == 0, lib.h2_last_error()
@@ -44,7 +44,7 @@ CHILD = textwrap.dedent(r'''
         assert now.value == est.value, (now.value, est.value)
         return m, A.shape[0]
 
-    tr = trunc(1e-6, 0, 32)
+    tr = trunc(1e-6, 0, 32, 0)
     (L1, n1), (L2, n2), (F, nf) = matrix(16, 8, 1), matrix(24, 16, 1), matrix(16, 8, 0)
     arr = (vp * 2)(L1.value, L2.value)
     st = (C.c_int * 2)()
@@ -89,6 +89,19 @@ CHILD = textwrap.dedent(r'''
         nr = (C.c_int32 * 1)(k)
         got = lib.h2_pcg_batched(As, Ls, bs, xs1, nr, 1, C.c_double(1e-8), C.c_int32(10), None, None, None)
         assert got == want, (k, got, lib.h2_last_error())
+    # updates on trees with block rows of more than 64 admissible blocks are
+    # refused (the domain-decomposition 256 x 256 tree at eta 4 has 89)
+    pd = w.problem(256, rhs_seed=1); Ad = pd["A"].tocsr()
+    xyd = np.ascontiguousarray(pd["coords"], dtype=np.int32)
+    ctd = vp(); ok(lib.h2_ctree_build_dd(ctx, C.c_int32(2), C.c_int64(len(xyd)), xyd.ctypes.data_as(vp), C.c_int32(32), C.byref(ctd)))
+    btd = vp(); ok(lib.h2_btree_build(ctx, ctd, C.c_double(4.0), C.byref(btd)))
+    csp = C.c_int32(); ok(lib.h2_btree_info(btd, None, None, None, C.byref(csp))); assert csp.value == 89
+    rpd = np.ascontiguousarray(Ad.indptr, np.int64); cid = np.ascontiguousarray(Ad.indices, np.int32); vd = np.ascontiguousarray(Ad.data)
+    keep.extend([xyd, rpd, cid, vd])
+    Ld = vp(); ok(lib.h2_mat_from_csr(ctx, btd, C.c_int64(Ad.shape[0]), rpd.ctypes.data_as(vp), cid.ctypes.data_as(vp), vd.ctypes.data_as(vp), C.c_int32(1), C.byref(Ld)))
+    assert lib.h2_cholesky(Ld, C.byref(tr)) == -1 and b"not validated" in lib.h2_last_error()
+    assert lib.h2_tri_invert(Ld, C.byref(tr)) == -1
+    ok(lib.h2_mat_destroy(Ld))
     print("host logic ok")
 ''')
 
