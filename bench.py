@@ -99,7 +99,7 @@ def measured_traffic(args):
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), for the
     default workload only; None otherwise or when the summary is absent."""
     default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
-               and args.sigma_seed == "10")
+               and args.sigma_seed == "10" and args.precision == "fp64")
     if not default:
         return None
     try:
@@ -110,6 +110,34 @@ def measured_traffic(args):
     except OSError:
         return None
     return None
+
+
+STAGES_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_stages.md")
+
+
+def measured_step_roofline(args):
+    """Roofline per update step (a4..a9) of the default workload from the
+    committed device-counter summary: algorithmic flops and bytes of each
+    step over the wall time of its stage; None for other workloads."""
+    default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
+               and args.sigma_seed == "10" and args.precision == "fp64")
+    if not default:
+        return None
+    steps = []
+    try:
+        with open(STAGES_PROFILE) as f:
+            for line in f:
+                if line.startswith("step_roofline:"):
+                    name, t, fl, by = [v.strip() for v in line.split(":", 1)[1].split("|")]
+                    t, fl, by = float(t), float(fl), float(by)
+                    steps.append({"step": name, "seconds": t, "flops": fl, "bytes": by,
+                                  "gflops_s": fl / t / 1e9,
+                                  "frac_fp64_chip": fl / t / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
+                                  "frac_fp64_one_cu": fl / t / (FP64_VECTOR_PEAK_TFLOPS * 1e12 / 256),
+                                  "gb_s": by / t / 1e9, "frac_hbm": by / t / (HBM_PEAK_GBS * 1e9)})
+    except OSError:
+        return None
+    return steps or None
 
 
 def sigma_seed(args):
@@ -565,6 +593,8 @@ def main():
             "traffic": measured_traffic(args),
             "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT) if measured_traffic(args) else None,
             "flops_per_launch": chol_flops,
+            "steps": measured_step_roofline(args),
+            "steps_source": os.path.relpath(STAGES_PROFILE, ROOT) if measured_step_roofline(args) else None,
         },
     }
     if inverse:
