@@ -113,6 +113,22 @@ def measured_traffic(args):
 
 
 STAGES_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_stages.md")
+MIXED_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_mixed.md")
+TARGET_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_512_sigma.md")
+
+
+def recorded(path, keys):
+    """key: value lines of a committed summary (None if absent)."""
+    vals = {}
+    try:
+        with open(path) as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                if k.strip() in keys and v.strip():
+                    vals[k.strip()] = float(v)
+    except OSError:
+        return None
+    return vals or None
 
 
 def measured_step_roofline(args):
@@ -602,6 +618,45 @@ def main():
         g_stored, g_kr, g_kc = h2lr.h2_mat_stats(L)    # L holds G ~ L^{-1} now
         out["inverse_mem_per_dof_kb"] = g_stored * 8.0 / n / 1024.0
         out["inverse_max_rank"] = [g_kr, g_kc]
+    if measured_step_roofline(args) is not None:
+        # the other halves of the metric, recorded by committed runs of this
+        # build (not timed here): the mixed-precision form of this workload,
+        # and the 511^2 workload whose steps do not fit the run's time limit
+        mixed = recorded(MIXED_PROFILE, ("mixed_setup_s", "mixed_solve_s", "mixed_pcg_iters", "fp64_setup_s",
+                                         "mixed_vs_fp64_factor_rel2"))
+        if mixed:
+            out["mixed_recorded"] = dict(mixed, source=os.path.relpath(MIXED_PROFILE, ROOT))
+        target = recorded(TARGET_PROFILE, ("target_setup_s", "target_solve_s", "target_pcg_iters", "target_n"))
+        if target:
+            out["target_511sq_recorded"] = dict(target, source=os.path.relpath(TARGET_PROFILE, ROOT))
+    if args.precision == "mixed":
+        # error of the mixed-precision factor against the FP64 factor of the
+        # same matrix (not part of the timed steps): 20 power iterations on
+        # (L_m - L_d)^* (L_m - L_d) and on L_d^* L_d with device products
+        Ld = h2lr.h2_mat_copy(A0)
+        h2lr.h2_cholesky(Ld, h2lr.trunc(args.eps, "block_rel", 32, precision="fp64"))
+        g = torch.Generator(device="cpu").manual_seed(7)
+        v = torch.randn(n, generator=g, dtype=torch.float64).to("cuda")
+        vl = v.clone()
+        ya, yb, za, zb = (torch.zeros_like(v) for _ in range(4))
+        sd = sl = 0.0
+        for _ in range(20):
+            v /= torch.linalg.norm(v)
+            h2lr.h2_matvec(L, v, ya)
+            h2lr.h2_matvec(Ld, v, yb)
+            u = ya - yb
+            h2lr.h2_matvec(L, u, za, trans=True)
+            h2lr.h2_matvec(Ld, u, zb, trans=True)
+            v = za - zb
+            sd = float(torch.linalg.norm(v)) ** 0.5
+            vl /= torch.linalg.norm(vl)
+            h2lr.h2_matvec(Ld, vl, ya)
+            h2lr.h2_matvec(Ld, ya, vl, trans=True)
+            sl = float(torch.linalg.norm(vl)) ** 0.5
+        out["mixed_vs_fp64_factor_rel2"] = sd / sl
+        itd, reld, _ = h2lr.h2_pcg(csr, Ld, b, torch.zeros_like(b), args.rtol, 500)
+        out["fp64_pcg_iters_same_matrix"] = itd
+        torch.cuda.synchronize()
     if args.trace:
         # one more factorisation with the device counters on (not part of the timed steps)
         h2lr.h2_mat_assign(L, A0)
