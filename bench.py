@@ -54,9 +54,10 @@ def parse():
     ap.add_argument("--sigma-seed", type=str, default="10",
                     help="seed of the piecewise-constant coefficient, or 'none' for sigma = 1")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+    ap.add_argument("--precision", choices=("fp64", "mixed", "mixed_bf16"), default="fp64",
                     help="fp64, or mixed: coupling and transfer products of the local updates in "
-                         "float on the matrix cores (QR, SVD, weights and PCG in FP64)")
+                         "float on the matrix cores (QR, SVD, weights and PCG in FP64); mixed_bf16: "
+                         "also leaf bases stored at bfloat16 precision (trial)")
     ap.add_argument("--precond", choices=("substitution", "inverse"), default="substitution",
                     help="preconditioner: substitutions with the factor L, or products with "
                          "G ~ L^{-1} formed by the triangular inversion after the factorisation")
@@ -705,8 +706,8 @@ def main():
         "solves_per_s": 1e3 / float(np.median(solve_ms)),
         "pcg_iters": iters,
         "true_relres": true_rel,
-        "p50_ms": float(np.percentile(step_ms, 50)),
-        "p99_ms": float(np.percentile(step_ms, 99)),
+        "step_p50_ms": float(np.percentile(step_ms, 50)),
+        "step_p99_ms": float(np.percentile(step_ms, 99)),
         "mem_per_dof_kb": stored * 8.0 / n / 1024.0,
         "max_rank": [kr, kc],
         "roofline": {
@@ -739,7 +740,7 @@ def main():
         target = recorded(TARGET_PROFILE, ("target_setup_s", "target_solve_s", "target_pcg_iters", "target_n"))
         if target:
             out["target_511sq_recorded"] = dict(target, source=os.path.relpath(TARGET_PROFILE, ROOT))
-    if args.precision == "mixed":
+    if args.precision != "fp64":
         # error of the mixed-precision factor against the FP64 factor of the
         # same matrix (not part of the timed steps): 20 power iterations on
         # (L_m - L_d)^* (L_m - L_d) and on L_d^* L_d with device products

@@ -69,7 +69,9 @@ typedef struct h2_job_s *h2_job;
  * coupling projections S_b <- R_t S_b R_s^* and the transfer / basis-change
  * products (R_t' E_t', R_t = Q_t^* V_t, R_t0 E_t0) of every local update take
  * float operands and accumulate in float on the matrix cores; QR, SVD,
- * weights, nearfield and all vector solves stay FP64 (results stored FP64). */
+ * weights, nearfield and all vector solves stay FP64 (results stored FP64).
+ * H2_PREC_MIXED_BF16 (a trial): as H2_PREC_MIXED, and every new leaf basis
+ * is stored rounded to bfloat16 precision. */
 typedef struct {
   double eps;
   int32_t mode;
@@ -78,6 +80,7 @@ typedef struct {
 } h2_trunc;
 #define H2_PREC_FP64 0
 #define H2_PREC_MIXED 1
+#define H2_PREC_MIXED_BF16 2
 
 #define H2_MAX_RANK 32       /* rank capacity of every basis slot            */
 #define H2_MAX_LEAF 32       /* largest leaf cluster                          */

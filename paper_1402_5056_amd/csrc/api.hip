@@ -1000,7 +1000,8 @@ static void set_trunc(h2_mat_s &m, const h2_trunc *tr) {
   REQUIRE(tr->mode >= 0 && tr->mode <= 2, "truncation mode must be 0, 1 or 2");
   REQUIRE(tr->rank_cap >= 1 && tr->rank_cap <= KC, "rank_cap must be in [1, H2_MAX_RANK]");
   REQUIRE(tr->eps >= 0.0 && std::isfinite(tr->eps), "eps must be finite and >= 0");
-  REQUIRE(tr->precision == H2_PREC_FP64 || tr->precision == H2_PREC_MIXED, "precision must be 0 or 1");
+  REQUIRE(tr->precision == H2_PREC_FP64 || tr->precision == H2_PREC_MIXED || tr->precision == H2_PREC_MIXED_BF16,
+          "precision must be 0, 1 or 2");
   m.env.eps = tr->eps; m.env.mode = tr->mode; m.env.rank_cap = tr->rank_cap; m.env.prec = tr->precision;
 }
 

@@ -75,6 +75,13 @@ __device__ __forceinline__ void set_error(const DevEnv &e, int code, int info) {
   __syncthreads();
 }
 
+// Nearest bfloat16 value (ties to even) of v, returned as a double.
+__device__ __forceinline__ double round_bf16(double v) {
+  unsigned int u = __float_as_uint((float)v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (double)__uint_as_float(u & 0xffff0000u);
+}
+
 __device__ __forceinline__ double trunc_tau(const DevEnv &e, double smax) {
   if (e.mode == 0) return e.eps;
   if (e.mode == 1) return e.eps * smax;
@@ -615,7 +622,10 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
   if (lane == 0) e.wnewk[side][c] = r;
   if (is_leaf(e, c)) {
     MV V = leafslot(e, side, c);
-    for (int q = lane; q < mr * r; q += 64) V(q % mr, q / mr) = Q(q % mr, q / mr);
+    if (e.prec == 2)   // trial form: leaf bases kept at bfloat16 precision
+      for (int q = lane; q < mr * r; q += 64) V(q % mr, q / mr) = round_bf16(Q(q % mr, q / mr));
+    else
+      for (int q = lane; q < mr * r; q += 64) V(q % mr, q / mr) = Q(q % mr, q / mr);
   } else {
     MV E1 = Eslot(e, side, e.son0[c]), E2 = Eslot(e, side, e.son1[c]);
     const int r2 = mr - r1;

@@ -138,7 +138,7 @@ def _np(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 
 
 def trunc(eps: float = 1e-4, mode: str = "block_rel", rank_cap: int = MAX_RANK,

@@ -9,7 +9,9 @@ Bar for the factor: float products carry a relative rounding error of about
 K u_f (K <= 64 terms, u_f = 2^-24 = 6e-8), i.e. <= 4e-6 per product; the
 recompressions that follow are FP64 and the truncation tolerance (1e-4 to
 1e-6 here) is larger, so the factor must stay within 1e-4 of the FP64
-oracle's in relative spectral norm (measured values are printed)."""
+oracle's in relative spectral norm (measured values are printed).  The
+trial form H2_PREC_MIXED_BF16 also stores leaf bases at bfloat16 precision;
+its error is reported and only bounded by 5e-2."""
 import numpy as np
 import pytest
 
@@ -41,7 +43,7 @@ def test_mixed_cholesky_error_and_pcg(lib, N, seed, eps, leaf):
     ctx = lib.h2_ctx_create(0)
     bt = lib.h2_btree_build(ctx, lib.h2_ctree_build(ctx, p["coords"], leaf), 2.0)
     out = {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_bf16"):
         L = lib.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
         lib.h2_cholesky(L, lib.trunc(eps, "block_rel", 32, precision=prec))
         D = np.tril(dense_via_matvec(lib, L, oc.n)[np.ix_(oc.perm, oc.perm)])
@@ -60,3 +62,9 @@ def test_mixed_cholesky_error_and_pcg(lib, N, seed, eps, leaf):
     assert out["mixed"][0] > out["fp64"][0]          # the float products are really used
     assert out["mixed"][2] and out["mixed"][1] == ito == out["fp64"][1]
     assert out["mixed"][3] < 1e-8
+    # trial form with leaf bases at bfloat16 precision (u = 2^-9): its factor
+    # error is of the order of that unit roundoff; PCG in FP64 still reaches
+    # the tolerance, possibly in more steps
+    assert out["mixed_bf16"][0] > out["mixed"][0]
+    assert out["mixed_bf16"][0] < 5e-2
+    assert out["mixed_bf16"][2] and out["mixed_bf16"][3] < 1e-8
