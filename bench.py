@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--precond", choices=("substitution", "inverse"), default="substitution",
                     help="preconditioner: substitutions with the factor L, or products with "
                          "G ~ L^{-1} formed by the triangular inversion after the factorisation")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shape of the substitutions (no autotuning)")
+    ap.add_argument("--tune-cache", type=str, default=None,
+                    help="text file of launch-shape tuning results, read and appended")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-sides", type=str, default="64,128",
                     help="grid sides the oracle is timed on (bounded sample; the last one gives value)")
@@ -254,11 +258,12 @@ def cpu_baseline(args, n_target: int):
 def bench_batch(args):
     """Batched form: independent problems of mixed sizes, one workgroup each
     in one interpreter launch.  A step resets every factor to its H^2(A),
-    factorises all of them in one launch (setup) while the low-rank updates
-    of full-storage copies run in a second launch on another stream, and solves every system by
-    PCG in lockstep (the preconditioner applications of all systems in one
-    launch per iteration).  The sequential comparison is measured too: one single-problem
-    factorisation per distinct grid side, summed over the batch's sides."""
+    runs the low-rank updates of full-storage copies and factorises all the
+    factors in ONE launch (setup), and solves every system by PCG in
+    lockstep (the preconditioner applications of all systems in one launch
+    per iteration).  The sequential comparison is measured too: one
+    single-problem factorisation per distinct grid side, summed over the
+    batch's sides."""
     import numpy as np
     import torch
     import workloads as w
@@ -272,21 +277,16 @@ def bench_batch(args):
     stream = torch.cuda.Stream()
     ctx = h2lr.h2_ctx_create(0, stream.cuda_stream)
     tr = h2lr.trunc(args.eps, "block_rel", 32)
-    # the low-rank updates work on full-storage copies of H^2(A) on a second
-    # stream, concurrently with the factorisations
-    ustream = torch.cuda.Stream()
-    uctx = h2lr.h2_ctx_create(0, ustream.cuda_stream)
     probs = []
     for i, side in enumerate(sides):
         p = w.problem(side, sigma_seed=1000 + i, rhs_seed=2000 + i)
         ct = h2lr.h2_ctree_build(ctx, p["coords"], 32)
         bt = h2lr.h2_btree_build(ctx, ct, args.eta)
         A0 = h2lr.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
-        uct = h2lr.h2_ctree_build(uctx, p["coords"], 32)
-        ubt = h2lr.h2_btree_build(uctx, uct, args.eta)
-        U0 = h2lr.h2_mat_from_csr(uctx, ubt, p["A"], lower=False)
-        ex = h2lr.h2_btree_export(ubt)
-        tree = h2lr.h2_ctree_export(uct)
+        # the low-rank updates work on full-storage copies of H^2(A)
+        U0 = h2lr.h2_mat_from_csr(ctx, bt, p["A"], lower=False)
+        ex = h2lr.h2_btree_export(bt)
+        tree = h2lr.h2_ctree_export(ct)
         sons = [b for b in range(len(ex["parent"])) if ex["parent"][b] == 0]
         ups = []
         for j, b in enumerate(sons[:args.batch_updates]):
@@ -312,26 +312,23 @@ def bench_batch(args):
             h2lr.h2_mat_assign(q["U"], q["U0"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        job = h2lr.h2_cholesky_launch(mats, tr)             # factorisations, stream 1
-        if args.batch_updates > 0:                         # updates, stream 2, meanwhile
-            h2lr.h2_lowrank_update_batched(umats, [q["ups"] for q in probs], tr)
-        tu = time.perf_counter()
+        if args.batch_updates > 0:     # updates and factorisations, one launch
+            job = h2lr.h2_update_cholesky_launch(umats, [q["ups"] for q in probs], mats, tr)
+        else:
+            job = h2lr.h2_cholesky_launch(mats, tr)
         job.finish()
         t1 = time.perf_counter()
-        times["updates"].append(tu - t0)
         # all systems in lockstep, preconditioner applications in one launch
         # (the solver clears x itself)
         its, _, _ = h2lr.h2_pcg_batched([q["csr"] for q in probs], mats, [q["b"] for q in probs],
-                                        [q["x"] for q in probs], args.rtol, 500)
+                                        [q["x"] for q in probs], args.rtol, 500, graph=True)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, its
 
-    times = {"updates": []}
     for i in range(args.warmup):
         step()
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
-    times["updates"].clear()
     setup, solve, iters = [], [], None
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -346,6 +343,13 @@ def bench_batch(args):
         A = q["p"]["A"]
         xr = q["x"].cpu().numpy()
         worst = max(worst, float(np.linalg.norm(q["p"]["b"] - A @ xr) / np.linalg.norm(q["p"]["b"])))
+    # the same batched solve launch by launch (not replayed from a graph)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    h2lr.h2_pcg_batched([q["csr"] for q in probs], mats, [q["b"] for q in probs],
+                        [torch.zeros_like(q["x"]) for q in probs], args.rtol, 500)
+    torch.cuda.synchronize()
+    solve_eager = time.perf_counter() - te
     # sequential comparison: one factorisation alone per distinct side
     single = {}
     for side in sorted(set(sides)):
@@ -371,12 +375,11 @@ def bench_batch(args):
                                f"log-uniform [1e-2,1e2] (seed 1000+i), bisection cluster tree leaf 32, "
                                f"eta {args.eta:g}, block-relative eps {args.eps}; per problem {args.batch_updates} "
                                f"rank-{args.batch_update_rank} Gaussian updates of the root's son blocks of a "
-                               f"full-storage copy (one launch, concurrent with) the batched H2-Cholesky "
-                               f"(one launch), then batched PCG 1 Gaussian RHS each to {args.rtol}",
+                               f"full-storage copy and the H2-Cholesky of A, all in one launch, then batched "
+                               f"PCG (graph form) 1 Gaussian RHS each to {args.rtol}",
                    "problems": args.batch, "total_n": ntot, "precision": "fp64", "parallelism": "1 GPU"},
         "updates_per_problem": min(args.batch_updates, 4),
         "update_rank": args.batch_update_rank,
-        "updates_done_s": float(np.median(times["updates"])) if times["updates"] else None,
         "update_max_rank": max(h2lr.h2_mat_stats(q["U"])[1] for q in probs),
         "batched_setup_s": setup_s,
         "setup_problems_per_s": args.batch / setup_s,
@@ -384,6 +387,8 @@ def bench_batch(args):
         "single_setup_s_by_side": {str(k): v for k, v in single.items()},
         "batch_speedup_setup": seq / setup_s,
         "solve_s_all": float(np.median(solve)),
+        "solve_form": "iterations replayed from a captured HIP graph (h2_pcg_batched_graph)",
+        "solve_s_all_launch_by_launch": solve_eager,
         "pcg_iters": iters,
         "worst_true_relres": worst,
     }
@@ -646,6 +651,13 @@ def main():
     for i in range(args.warmup):
         step([torch.cuda.Event(enable_timing=True) for _ in range(4)])
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+    tune = None
+    if args.warmup >= 1 and not inverse and not args.no_tune:
+        # launch shape of the substitutions, tuned once on the factor the
+        # warmup made (the timed steps refactorise the same problem)
+        tune = h2lr.h2_autotune_precond(L, 1, 3, args.tune_cache)
+        print(f"[bench] substitution launch shape: {tune[0]} threads ({tune[1]:.2f} ms per application"
+              f"{', from the cache' if tune[2] else ''}; by shape {tune[3]})", file=sys.stderr, flush=True)
     h2lr.h2_mat_flops(L, reset=True)
     torch.cuda.synchronize()
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
@@ -702,6 +714,8 @@ def main():
         "cholesky_s": chol_s,
         "inverse_s": (setup_s - chol_s) if inverse else None,
         "precond": args.precond,
+        "precond_threads": tune[0] if tune else None,
+        "precond_ms_by_threads": ({str(k): v for k, v in tune[3].items()} or None) if tune else None,
         "solve_s": float(np.median(solve_ms)) / 1e3,
         "solves_per_s": 1e3 / float(np.median(solve_ms)),
         "pcg_iters": iters,

@@ -285,6 +285,21 @@ h2_status h2_cholesky_batched(h2_mat *mats, int32_t count, const h2_trunc *tr, h
  * with H2_ERR_ARG (h2_mat_destroy with H2_ERR_STATE).  Launches on different
  * streams run concurrently on the device. */
 h2_status h2_cholesky_launch(h2_mat *mats, int32_t count, const h2_trunc *tr, h2_job *job);
+/* Local low-rank updates and Cholesky factorisations of distinct matrices
+ * in ONE launch (one workgroup per matrix): matrices umats[0..ucount)
+ * receive their updates as in h2_lowrank_update_batched (same argument
+ * arrays and checks, the same arithmetic, so each result equals the single
+ * calls), matrices cmats[0..ccount) (lower-stored) are factorised as in
+ * h2_cholesky_launch (Section 3 recursion).  ucount or ccount may be 0, not
+ * both; no matrix may appear twice; all share one device and stream.
+ * Returns at once with a job (h2_job_query, h2_job_finish); the factors X, Y
+ * are read on that stream before the launch, so they must stay valid until
+ * the stream reaches it (h2_job_finish waits for it).  h2_job_finish's status
+ * array has ucount + ccount entries, updated matrices first. */
+h2_status h2_update_cholesky_launch(h2_mat *umats, int32_t ucount, const int32_t *nupd, const int64_t *blocks,
+                                    const int32_t *ks, const double *const *Xs, const int64_t *ldxs,
+                                    const double *const *Ys, const int64_t *ldys, h2_mat *cmats,
+                                    int32_t ccount, const h2_trunc *tr, h2_job *job);
 /* *done = 1 once the launched work has finished (does not block). */
 h2_status h2_job_query(h2_job job, int32_t *done);
 /* Waits for the job, checks every matrix as h2_cholesky_batched does (status
@@ -317,6 +332,28 @@ h2_status h2_precond(h2_mat l, const double *r, double *z, int32_t nrhs);
  * device, n x nrhs, original order (may alias), 1 <= nrhs <= H2_MAX_COLS.
  * H2_ERR_ARG for a matrix that is not a (non-inverted) lower factor. */
 h2_status h2_trsv(h2_mat l, int32_t trans, const double *r, double *z, int32_t nrhs);
+
+/* Launch shape of the substitutions with a Cholesky factor (h2_precond,
+ * h2_trsv, the preconditioner of h2_pcg and h2_pcg_batched) for nrhs
+ * columns: threads per workgroup, 128, 256 or 512 (0 restores the default,
+ * 256).  The substitutions compute every column, cluster and block group in
+ * one wave in a fixed order, so the shape changes the time, never the
+ * result.  h2_pcg_batched launches all systems with the largest shape of
+ * its members.  H2_ERR_ARG for another value or a non-factor. */
+h2_status h2_precond_config(h2_mat l, int32_t nrhs, int32_t threads);
+
+/* Autotuner of that launch shape: times reps applications of the
+ * substitution pair (z = (L L^*)^{-1} r on a work vector it allocates) for
+ * each shape with events on the matrix's stream, keeps the fastest for
+ * this matrix and nrhs, and reports it (threads, ms_per_apply).  With a
+ * cache_path (may be NULL), a result recorded there for the same key (the
+ * device architecture, n, cluster and block counts, stored values and nrhs)
+ * is applied without timing (*from_cache = 1); a new result is appended as
+ * one text line "key threads ms".  ms_by_shape: 3 entries, the time per
+ * application at 128, 256 and 512 threads (zeros when taken from the
+ * cache).  Output pointers may be NULL. */
+h2_status h2_autotune_precond(h2_mat l, int32_t nrhs, int32_t reps, const char *cache_path, int32_t *threads,
+                              double *ms_per_apply, int32_t *from_cache, double *ms_by_shape);
 
 /* ------------------------------------------------------- sparse A and PCG */
 /* Device copy of a CSR matrix (host arrays, original order). */
@@ -365,6 +402,17 @@ h2_status h2_pcg_noalloc(h2_csr a, h2_mat l, const double *b, double *x, double 
 h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
                          const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
                          double *relres, h2_status *status);
+
+/* h2_pcg_batched with the iterations replayed from a HIP graph: one CG
+ * iteration of every column (product, dot products, updates, convergence
+ * test, the preconditioner launch, the next direction) is captured once,
+ * with all columns in each launch and the convergence test on the device
+ * switching columns and systems off; the host replays it and reads one
+ * counter per iteration.  Same arguments, arithmetic and results (bit for
+ * bit) as h2_pcg_batched; at most 65535 columns in all. */
+h2_status h2_pcg_batched_graph(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
+                               const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
+                               double *relres, h2_status *status);
 
 #ifdef __cplusplus
 }

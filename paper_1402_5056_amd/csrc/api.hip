@@ -354,6 +354,9 @@ struct h2_mat_s {
   double prod_alpha = 0.0;  // alpha the product task list was planned with
   bool inverse = false;   // holds G ~ L^{-1} (h2_tri_invert) instead of a factor L
   bool lr = false;        // holds the LR factors (h2_lr)
+  // threads per workgroup of the substitution launches by column count
+  // (h2_autotune_precond, h2_precond_config; 0: the default)
+  int prec_nt[BC + 1] = {};
   DevEnv env{};
 };
 
@@ -1131,6 +1134,31 @@ static int grid_for(long work) {
 }
 
 // =================================================================== C ABI
+// Stored values of the H^2 representation (leaf bases, transfer, coupling
+// and nearfield matrices) and the largest ranks; reads the ranks back.
+static int64_t mat_stored_values(h2_mat_s &m, int *kmax_row, int *kmax_col) {
+  const h2_ctree_s &ct = *m.bt->ct;
+  const h2_btree_s &bt = *m.bt;
+  std::vector<int> k[2];
+  for (int side = 0; side < 2; ++side) {
+    k[side].resize(ct.nc);
+    HIPCHK(hipMemcpyAsync(k[side].data(), m.d_k[side].p, ct.nc * sizeof(int), hipMemcpyDeviceToHost,
+                          m.ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(m.ctx->stream));
+  int64_t vals = 0;
+  for (int side = 0; side < 2; ++side)
+    for (int c = 0; c < ct.nc; ++c) {
+      if (ct.son0[c] < 0) vals += (int64_t)ct.size[c] * k[side][c];
+      if (ct.parent[c] >= 0) vals += (int64_t)k[side][c] * k[side][ct.parent[c]];
+    }
+  for (int b : m.adm) vals += (int64_t)k[0][bt.row[b]] * k[1][bt.col[b]];
+  for (int b : m.nearb) vals += (int64_t)ct.size[bt.row[b]] * ct.size[bt.col[b]];
+  if (kmax_row) *kmax_row = *std::max_element(k[0].begin(), k[0].end());
+  if (kmax_col) *kmax_col = *std::max_element(k[1].begin(), k[1].end());
+  return vals;
+}
+
 extern "C" {
 
 const char *h2_last_error(void) { return g_last_error.c_str(); }
@@ -1306,6 +1334,7 @@ h2_status h2_mat_copy(h2_mat src, h2_mat *out) {
     auto m = std::make_unique<h2_mat_s>();
     m->ctx = src->ctx; m->stream = src->stream; m->bt = src->bt; m->lower = src->lower;
     m->inverse = src->inverse;
+    std::copy(src->prec_nt, src->prec_nt + BC + 1, m->prec_nt);
     mat_lists(*m);
     mat_alloc(*m);
     hipStream_t s = src->ctx->stream;
@@ -1424,26 +1453,11 @@ h2_status h2_mat_ranks(h2_mat m, int32_t *rank_row, int32_t *rank_col) {
 h2_status h2_mat_stats(h2_mat m, int64_t *stored_values, int32_t *max_rank_row, int32_t *max_rank_col) {
   return guarded([&] {
     REQUIRE(m != nullptr, "null matrix");
-    const h2_ctree_s &ct = *m->bt->ct;
-    const h2_btree_s &bt = *m->bt;
-    std::vector<int> k[2];
-    for (int side = 0; side < 2; ++side) {
-      k[side].resize(ct.nc);
-      HIPCHK(hipMemcpyAsync(k[side].data(), m->d_k[side].p, ct.nc * sizeof(int), hipMemcpyDeviceToHost,
-                            m->ctx->stream));
-    }
-    HIPCHK(hipStreamSynchronize(m->ctx->stream));
-    int64_t vals = 0;
-    for (int side = 0; side < 2; ++side)
-      for (int c = 0; c < ct.nc; ++c) {
-        if (ct.son0[c] < 0) vals += (int64_t)ct.size[c] * k[side][c];
-        if (ct.parent[c] >= 0) vals += (int64_t)k[side][c] * k[side][ct.parent[c]];
-      }
-    for (int b : m->adm) vals += (int64_t)k[0][bt.row[b]] * k[1][bt.col[b]];
-    for (int b : m->nearb) vals += (int64_t)ct.size[bt.row[b]] * ct.size[bt.col[b]];
+    int kr = 0, kc = 0;
+    const int64_t vals = mat_stored_values(*m, &kr, &kc);
     if (stored_values) *stored_values = vals;
-    if (max_rank_row) *max_rank_row = *std::max_element(k[0].begin(), k[0].end());
-    if (max_rank_col) *max_rank_col = *std::max_element(k[1].begin(), k[1].end());
+    if (max_rank_row) *max_rank_row = kr;
+    if (max_rank_col) *max_rank_col = kc;
   });
 }
 
@@ -1683,6 +1697,91 @@ static void batch_errors(const std::vector<h2_mat_s *> &ms, h2_status *status) {
 
 }  // extern "C"
 
+// Argument checks of a batch of local updates (before any device work):
+// matrix i receives nupd[i] updates from the flat arrays.
+static void check_update_batch(const std::vector<h2_mat_s *> &ms, const int32_t *nupd, const int64_t *blocks,
+                               const int32_t *ks, const double *const *Xs, const int64_t *ldxs,
+                               const double *const *Ys, const int64_t *ldys) {
+  int u0 = 0;
+  for (size_t i = 0; i < ms.size(); ++i) {
+    const h2_mat_s &z = *ms[i];
+    const h2_btree_s &bt = *z.bt;
+    const h2_ctree_s &ct = *bt.ct;
+    REQUIRE(nupd[i] >= 0 && nupd[i] <= H2_MAX_BATCH_UPDATES, "updates per matrix out of range");
+    for (int u = u0; u < u0 + nupd[i]; ++u) {
+      REQUIRE(blocks[u] >= 0 && blocks[u] < bt.nb, "block out of range");
+      REQUIRE(ks[u] >= 0 && ks[u] <= H2_MAX_UPDATE_RANK, "update rank out of range");
+      const int t0 = bt.row[blocks[u]], s0 = bt.col[blocks[u]];
+      if (z.lower) REQUIRE(t0 == s0 || ct.offset[t0] > ct.offset[s0], "block above the diagonal of a lower matrix");
+      if (ks[u] == 0) continue;
+      REQUIRE(Xs[u] && Ys[u], "null factor");
+      REQUIRE(ldxs[u] >= ct.size[t0] && ldys[u] >= ct.size[s0], "leading dimension too small");
+    }
+    u0 += nupd[i];
+  }
+}
+
+// Plans the updates of every matrix of a checked batch into its own task
+// list and gathers the factors on the batch's stream; returns one launch
+// descriptor per matrix.  Update j's factors go to the j-th pair of product
+// temporaries, which the local update itself leaves untouched; a matrix's
+// updates run in order.
+static std::vector<BatchItem> plan_update_batch(const std::vector<h2_mat_s *> &ms, const int32_t *nupd,
+                                                const int64_t *blocks, const int32_t *ks,
+                                                const double *const *Xs, const int64_t *ldxs,
+                                                const double *const *Ys, const int64_t *ldys,
+                                                const h2_trunc *tr) {
+  hipStream_t s = ms[0]->ctx->stream;
+  std::vector<BatchItem> items(ms.size());
+  int u0 = 0;
+  for (size_t i = 0; i < ms.size(); ++i) {
+    h2_mat_s &z = *ms[i];
+    const h2_btree_s &bt = *z.bt;
+    const h2_ctree_s &ct = *bt.ct;
+    set_trunc(z, tr);
+    std::vector<Task> tasks;
+    Planner P(z, tasks);
+    for (int j = 0; j < nupd[i]; ++j) {
+      const int u = u0 + j, k = ks[u];
+      if (k == 0) continue;
+      const int b = (int)blocks[u], t0 = bt.row[b], s0 = bt.col[b];
+      const int bu = B_T0U + 2 * j, bv = B_T0V + 2 * j;
+      hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[t0] * k)), dim3(256), 0, s, ct.size[t0],
+                         ct.offset[t0], k, (const int64_t *)nullptr, Xs[u], (long)ldxs[u], z.env.buf[bu],
+                         z.d_bcols.p, bu);
+      hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[s0] * k)), dim3(256), 0, s, ct.size[s0],
+                         ct.offset[s0], k, (const int64_t *)nullptr, Ys[u], (long)ldys[u], z.env.buf[bv],
+                         z.d_bcols.p, bv);
+      HIPCHK(hipGetLastError());
+      P.addlr(b, bu, bv);
+    }
+    upload_tasks_reuse(z.upd, tasks, P.aux);
+    sync_env(z);
+    items[i] = BatchItem{z.upd.d.p, z.d_env.p, z.upd.aux.p, z.upd.count, 0};
+    u0 += nupd[i];
+  }
+  return items;
+}
+
+// Plans (first call per matrix) the Cholesky factorisation of every matrix
+// of a batch; returns one launch descriptor per matrix.
+static std::vector<BatchItem> plan_cholesky_batch(const std::vector<h2_mat_s *> &ms, const h2_trunc *tr) {
+  std::vector<BatchItem> items(ms.size());
+  for (size_t i = 0; i < ms.size(); ++i) {
+    h2_mat_s &m = *ms[i];
+    set_trunc(m, tr);
+    if (!m.chol.built) {
+      std::vector<Task> tasks;
+      Planner P(m, tasks);
+      P.chol(0);
+      upload_tasks(m, m.chol, tasks, P.aux);
+    }
+    sync_env(m);
+    items[i] = BatchItem{m.chol.d.p, m.d_env.p, m.chol.aux.p, m.chol.count, 0};
+  }
+  return items;
+}
+
 struct h2_job_s {
   std::vector<h2_mat_s *> ms;
   std::vector<BatchItem> items;
@@ -1701,36 +1800,69 @@ struct h2_job_s {
   }
 };
 
+// One launch of k_interp_batch over the local updates of the matrices us
+// (a matrix's updates in order) and the Cholesky factorisations of the
+// matrices cs, one workgroup each.
+static void update_cholesky_launch(h2_mat *umats, int32_t ucount, const int32_t *nupd, const int64_t *blocks,
+                                   const int32_t *ks, const double *const *Xs, const int64_t *ldxs,
+                                   const double *const *Ys, const int64_t *ldys, h2_mat *cmats, int32_t ccount,
+                                   const h2_trunc *tr, h2_job *job, const char *what) {
+  REQUIRE(job != nullptr, "null output");
+  *job = nullptr;
+  REQUIRE(ucount >= 0 && ccount >= 0 && ucount + ccount >= 1, "need at least one matrix");
+  std::vector<h2_mat_s *> us, cs;
+  if (ucount > 0) {
+    REQUIRE(nupd && blocks && ks && Xs && ldxs && Ys && ldys, "null argument");
+    us = batch_members(umats, ucount, what, false);
+  }
+  if (ccount > 0) cs = batch_members(cmats, ccount, what);
+  std::vector<h2_mat_s *> all(us);
+  all.insert(all.end(), cs.begin(), cs.end());
+  for (h2_mat_s *m : all) {
+    REQUIRE(m->ctx->device == all[0]->ctx->device && m->ctx->stream == all[0]->ctx->stream,
+            "all matrices of a batch must share one device and stream");
+    require_validated_tree(*m);
+  }
+  {
+    std::vector<h2_mat_s *> sorted(all);
+    std::sort(sorted.begin(), sorted.end());
+    REQUIRE(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(),
+            "a matrix appears twice in the batch");
+  }
+  if (ucount > 0) check_update_batch(us, nupd, blocks, ks, Xs, ldxs, Ys, ldys);
+  auto j = std::make_unique<h2_job_s>();
+  if (ucount > 0) j->items = plan_update_batch(us, nupd, blocks, ks, Xs, ldxs, Ys, ldys, tr);
+  if (ccount > 0) {
+    const std::vector<BatchItem> ci = plan_cholesky_batch(cs, tr);
+    j->items.insert(j->items.end(), ci.begin(), ci.end());
+  }
+  j->stream = all[0]->ctx->stream;
+  j->d_items = items_acquire(j->items.size());
+  launch_batch(*j->d_items, j->items, NT, j->stream);
+  HIPCHK(hipEventCreateWithFlags(&j->done, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(j->done, j->stream));
+  j->ms = all;
+  for (h2_mat_s *m : all) m->busy = true;
+  *job = j.release();
+}
+
 extern "C" {
 
 h2_status h2_cholesky_launch(h2_mat *mats, int32_t count, const h2_trunc *tr, h2_job *job) {
   return guarded([&] {
-    REQUIRE(job != nullptr, "null output");
-    *job = nullptr;
-    auto j = std::make_unique<h2_job_s>();
-    std::vector<h2_mat_s *> ms = batch_members(mats, count, "h2_cholesky_launch");
-    for (h2_mat_s *m : ms) require_validated_tree(*m);
-    j->items.resize(count);
-    for (int i = 0; i < count; ++i) {
-      h2_mat_s &m = *ms[i];
-      set_trunc(m, tr);
-      if (!m.chol.built) {
-        std::vector<Task> tasks;
-        Planner P(m, tasks);
-        P.chol(0);
-        upload_tasks(m, m.chol, tasks, P.aux);
-      }
-      sync_env(m);
-      j->items[i] = BatchItem{m.chol.d.p, m.d_env.p, m.chol.aux.p, m.chol.count, 0};
-    }
-    j->stream = ms[0]->ctx->stream;
-    j->d_items = items_acquire(count);
-    launch_batch(*j->d_items, j->items, NT, j->stream);
-    HIPCHK(hipEventCreateWithFlags(&j->done, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(j->done, j->stream));
-    j->ms = ms;
-    for (h2_mat_s *m : ms) m->busy = true;
-    *job = j.release();
+    REQUIRE(mats != nullptr && count >= 1, "need at least one matrix");
+    update_cholesky_launch(nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, mats, count,
+                           tr, job, "h2_cholesky_launch");
+  });
+}
+
+h2_status h2_update_cholesky_launch(h2_mat *umats, int32_t ucount, const int32_t *nupd, const int64_t *blocks,
+                                    const int32_t *ks, const double *const *Xs, const int64_t *ldxs,
+                                    const double *const *Ys, const int64_t *ldys, h2_mat *cmats,
+                                    int32_t ccount, const h2_trunc *tr, h2_job *job) {
+  return guarded([&] {
+    update_cholesky_launch(umats, ucount, nupd, blocks, ks, Xs, ldxs, Ys, ldys, cmats, ccount, tr, job,
+                           "h2_update_cholesky_launch");
   });
 }
 
@@ -1766,55 +1898,9 @@ h2_status h2_lowrank_update_batched(h2_mat *mats, int32_t count, const int32_t *
     for (h2_mat_s *m : ms) require_validated_tree(*m);
     if (status)
       for (int i = 0; i < count; ++i) status[i] = H2_OK;
-    // validate everything before any device work
-    int u0 = 0;
-    for (int i = 0; i < count; ++i) {
-      const h2_mat_s &z = *ms[i];
-      const h2_btree_s &bt = *z.bt;
-      const h2_ctree_s &ct = *bt.ct;
-      REQUIRE(nupd[i] >= 0 && nupd[i] <= H2_MAX_BATCH_UPDATES, "updates per matrix out of range");
-      for (int u = u0; u < u0 + nupd[i]; ++u) {
-        REQUIRE(blocks[u] >= 0 && blocks[u] < bt.nb, "block out of range");
-        REQUIRE(ks[u] >= 0 && ks[u] <= H2_MAX_UPDATE_RANK, "update rank out of range");
-        const int t0 = bt.row[blocks[u]], s0 = bt.col[blocks[u]];
-        if (z.lower) REQUIRE(t0 == s0 || ct.offset[t0] > ct.offset[s0], "block above the diagonal of a lower matrix");
-        if (ks[u] == 0) continue;
-        REQUIRE(Xs[u] && Ys[u], "null factor");
-        REQUIRE(ldxs[u] >= ct.size[t0] && ldys[u] >= ct.size[s0], "leading dimension too small");
-      }
-      u0 += nupd[i];
-    }
+    check_update_batch(ms, nupd, blocks, ks, Xs, ldxs, Ys, ldys);
     hipStream_t s = ms[0]->ctx->stream;
-    std::vector<BatchItem> items(count);
-    u0 = 0;
-    for (int i = 0; i < count; ++i) {
-      h2_mat_s &z = *ms[i];
-      const h2_btree_s &bt = *z.bt;
-      const h2_ctree_s &ct = *bt.ct;
-      set_trunc(z, tr);
-      std::vector<Task> tasks;
-      Planner P(z, tasks);
-      // update j's factors go to the j-th pair of product temporaries, which
-      // the local update itself leaves untouched; the updates run in order
-      for (int j = 0; j < nupd[i]; ++j) {
-        const int u = u0 + j, k = ks[u];
-        if (k == 0) continue;
-        const int b = (int)blocks[u], t0 = bt.row[b], s0 = bt.col[b];
-        const int bu = B_T0U + 2 * j, bv = B_T0V + 2 * j;
-        hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[t0] * k)), dim3(256), 0, s, ct.size[t0],
-                           ct.offset[t0], k, (const int64_t *)nullptr, Xs[u], (long)ldxs[u], z.env.buf[bu],
-                           z.d_bcols.p, bu);
-        hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[s0] * k)), dim3(256), 0, s, ct.size[s0],
-                           ct.offset[s0], k, (const int64_t *)nullptr, Ys[u], (long)ldys[u], z.env.buf[bv],
-                           z.d_bcols.p, bv);
-        HIPCHK(hipGetLastError());
-        P.addlr(b, bu, bv);
-      }
-      upload_tasks_reuse(z.upd, tasks, P.aux);
-      sync_env(z);
-      items[i] = BatchItem{z.upd.d.p, z.d_env.p, z.upd.aux.p, z.upd.count, 0};
-      u0 += nupd[i];
-    }
+    const std::vector<BatchItem> items = plan_update_batch(ms, nupd, blocks, ks, Xs, ldxs, Ys, ldys, tr);
     struct ItemsGuard {
       Dev<BatchItem> *d; hipStream_t s;
       ~ItemsGuard() { (void)hipStreamSynchronize(s); items_release(d); }
@@ -1866,9 +1952,18 @@ static const TaskList &prec_list(h2_mat l) {
   return l->prec;
 }
 
-// the substitution tasks (and the leaf solves) use the run-time wave count;
-// four waves measured faster than eight for them
+// The substitution tasks (and the leaf solves) use the run-time wave count
+// (at least two waves: the push to the sons takes one wave per son); every
+// column, cluster and block group is computed by one wave in a fixed order,
+// so the result does not depend on the count.  Default four waves;
+// h2_autotune_precond picks per matrix and column count.
 constexpr int PREC_THREADS = 256;
+constexpr int PREC_SHAPES[3] = {128, 256, 512};
+
+static int prec_threads(const h2_mat_s &l, int nrhs) {
+  const int t = (nrhs >= 1 && nrhs <= BC) ? l.prec_nt[nrhs] : 0;
+  return t > 0 ? t : PREC_THREADS;
+}
 
 static void prec_gather(h2_mat l, const double *r, int nrhs) {
   const h2_ctree_s &ct = *l->bt->ct;
@@ -1890,7 +1985,7 @@ static void precond_device(h2_mat l, const double *r, double *z, int nrhs) {
   if (l->inverse) { precond_inverse_device(l, r, z, nrhs); return; }
   const TaskList &tl = prec_list(l);
   prec_gather(l, r, nrhs);
-  run_tasks(*l, tl, PREC_THREADS);
+  run_tasks(*l, tl, prec_threads(*l, nrhs));
   prec_scatter(l, z, nrhs);
 }
 
@@ -1948,9 +2043,118 @@ h2_status h2_trsv(h2_mat l, int32_t trans, const double *r, double *z, int32_t n
       upload_tasks(*l, tl, tasks, P.aux);
     }
     prec_gather(l, r, nrhs);
-    run_tasks(*l, tl, PREC_THREADS);
+    run_tasks(*l, tl, prec_threads(*l, nrhs));
     prec_scatter(l, z, nrhs);
     check_device_error(*l);
+  });
+}
+
+h2_status h2_precond_config(h2_mat l, int32_t nrhs, int32_t threads) {
+  return guarded([&] {
+    require_ok(l);
+    REQUIRE(l->lower && !l->inverse, "h2_precond_config needs a Cholesky factor");
+    REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
+    REQUIRE(threads == 0 || std::find(std::begin(PREC_SHAPES), std::end(PREC_SHAPES), threads) !=
+                                std::end(PREC_SHAPES),
+            "threads must be 0, 128, 256 or 512");
+    l->prec_nt[nrhs] = threads;
+  });
+}
+
+// Key of a tuning result: the device's architecture and the shape of the
+// substitution work (unknowns, clusters, blocks, stored values, columns).
+static std::string tune_key(h2_mat_s &l, int nrhs) {
+  hipDeviceProp_t pr;
+  HIPCHK(hipGetDeviceProperties(&pr, l.ctx->device));
+  const h2_ctree_s &ct = *l.bt->ct;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "precond/%s/n%ld/c%ld/a%d/b%d/v%lld/r%d", pr.gcnArchName, (long)ct.n,
+                (long)ct.nc, l.nadm, l.nnear, (long long)mat_stored_values(l, nullptr, nullptr), nrhs);
+  for (char *c = buf; *c; ++c)
+    if (*c == ' ' || *c == ':') *c = '_';
+  return buf;
+}
+
+h2_status h2_autotune_precond(h2_mat l, int32_t nrhs, int32_t reps, const char *cache_path, int32_t *threads,
+                              double *ms_per_apply, int32_t *from_cache, double *ms_by_shape) {
+  return guarded([&] {
+    require_ok(l);
+    REQUIRE(l->lower && !l->inverse, "h2_autotune_precond needs a Cholesky factor");
+    REQUIRE(nrhs >= 1 && nrhs <= H2_MAX_COLS, "nrhs out of range");
+    REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+    const std::string key = tune_key(*l, nrhs);
+    if (from_cache) *from_cache = 0;
+    if (ms_by_shape)
+      for (int i = 0; i < 3; ++i) ms_by_shape[i] = 0.0;
+    if (cache_path && *cache_path) {
+      if (FILE *f = std::fopen(cache_path, "r")) {
+        char k[256];
+        int t = 0;
+        double ms = 0.0;
+        int best = 0;
+        double best_ms = 0.0;
+        while (std::fscanf(f, "%255s %d %lf", k, &t, &ms) == 3)
+          if (key == k && std::find(std::begin(PREC_SHAPES), std::end(PREC_SHAPES), t) != std::end(PREC_SHAPES)) {
+            best = t;       // the last entry of a key wins
+            best_ms = ms;
+          }
+        std::fclose(f);
+        if (best > 0) {
+          l->prec_nt[nrhs] = best;
+          if (threads) *threads = best;
+          if (ms_per_apply) *ms_per_apply = best_ms;
+          if (from_cache) *from_cache = 1;
+          return;
+        }
+      }
+    }
+    const h2_ctree_s &ct = *l->bt->ct;
+    hipStream_t s = l->ctx->stream;
+    const size_t len = (size_t)ct.n * nrhs;
+    Dev<double> r, z;
+    r.alloc_on(len, s);
+    z.alloc_on(len, s);
+    hipLaunchKernelGGL(k_fill_double, dim3(grid_for((long)len)), dim3(256), 0, s, r.p, (int)len, 1.0);
+    HIPCHK(hipGetLastError());
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    struct Events {
+      hipEvent_t a, b;
+      ~Events() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } ev{e0, e1};
+    const int saved = l->prec_nt[nrhs];
+    int best = 0;
+    double best_ms = 0.0;
+    try {
+      for (int si = 0; si < 3; ++si) {
+        const int t = PREC_SHAPES[si];
+        l->prec_nt[nrhs] = t;
+        precond_device(l, r.p, z.p, nrhs);      // warm-up (and plans the list once)
+        HIPCHK(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) precond_device(l, r.p, z.p, nrhs);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const double per = (double)ms / reps;
+        if (ms_by_shape) ms_by_shape[si] = per;
+        if (best == 0 || per < best_ms) { best = t; best_ms = per; }
+      }
+    } catch (...) {
+      l->prec_nt[nrhs] = saved;
+      throw;
+    }
+    check_device_error(*l);
+    l->prec_nt[nrhs] = best;
+    if (threads) *threads = best;
+    if (ms_per_apply) *ms_per_apply = best_ms;
+    if (cache_path && *cache_path) {
+      FILE *f = std::fopen(cache_path, "a");
+      REQUIRE(f != nullptr, "cannot append to the tuning cache file");
+      std::fprintf(f, "%s %d %.6f\n", key.c_str(), best, best_ms);
+      std::fclose(f);
+    }
   });
 }
 
@@ -2006,169 +2210,302 @@ h2_status h2_spmv(h2_csr a, const double *x, double *y) {
   });
 }
 
-h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
-                         const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
-                         double *relres, h2_status *status) {
-  return guarded([&] {
-    REQUIRE(as && bs && xs, "null argument");
-    REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
-    std::vector<h2_mat_s *> ms = batch_members(ls, count, "h2_pcg_batched");
-    hipStream_t s = ms[0]->ctx->stream;
-    const int NP = 256;   // partial sums of the dot products
-    // one CG iteration state per column; a system's columns share its
-    // preconditioner launches
-    struct Col {
-      const double *b; double *x, *r, *z, *p, *q, *part, *sc;
-      double nb, rel; int it; bool active, conv;
-    };
-    struct Sys {
-      h2_csr_s *a; h2_mat_s *l; int n, g, k, c0; double *R, *Z;
-    };
-    std::vector<Sys> sys(count);
-    std::vector<Col> col;
+}  // extern "C"
+
+static void pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs, const int32_t *nrhs,
+                        int32_t count, double rtol, int32_t maxit, int32_t *iters, double *relres,
+                        h2_status *status, bool graph) {
+  REQUIRE(as && bs && xs, "null argument");
+  REQUIRE(maxit >= 1 && rtol >= 0.0, "bad maxit or rtol");
+  std::vector<h2_mat_s *> ms = batch_members(ls, count, graph ? "h2_pcg_batched_graph" : "h2_pcg_batched");
+  hipStream_t s = ms[0]->ctx->stream;
+  const int NP = 256;   // partial sums of the dot products
+  // one CG iteration state per column; a system's columns share its
+  // preconditioner launches
+  struct Col {
+    const double *b; double *x, *r, *z, *p, *q, *part, *sc;
+    double nb, rel; int it; bool active, conv;
+  };
+  struct Sys {
+    h2_csr_s *a; h2_mat_s *l; int n, g, k, c0; double *R, *Z;
+  };
+  std::vector<Sys> sys(count);
+  std::vector<Col> col;
+  for (int i = 0; i < count; ++i) {
+    Sys &y = sys[i];
+    y.a = as[i]; y.l = ms[i];
+    REQUIRE(y.a && bs[i] && xs[i], "null argument");
+    REQUIRE(y.a->n == y.l->bt->ct->n, "size mismatch");
+    y.n = (int)y.a->n;
+    y.k = nrhs ? nrhs[i] : 1;
+    REQUIRE(y.k >= 1 && y.k <= BC, "nrhs must be in [1, H2_MAX_COLS]");
+    y.g = grid_for(y.n);
+    const size_t need = (size_t)(4 * y.n + NP + 8) * y.k;
+    if (y.l->d_pcg.n < need) y.l->d_pcg.alloc_on(need, y.l->stream);
+    double *base = y.l->d_pcg.p;
+    y.R = base;
+    y.Z = y.R + (size_t)y.n * y.k;
+    double *P = y.Z + (size_t)y.n * y.k, *Q = P + (size_t)y.n * y.k, *PART = Q + (size_t)y.n * y.k;
+    double *SC = PART + (size_t)NP * y.k;
+    y.c0 = (int)col.size();
+    for (int c = 0; c < y.k; ++c) {
+      const size_t o = (size_t)c * y.n;
+      col.push_back(Col{bs[i] + o, xs[i] + o, y.R + o, y.Z + o, P + o, Q + o, PART + (size_t)c * NP,
+                        SC + 8 * c, 0.0, 0.0, 0, true, false});
+    }
+    prec_list(y.l);
+    sync_env(*y.l);
+  }
+  const int ncol = (int)col.size();
+  if (status)
+    for (int c = 0; c < ncol; ++c) status[c] = H2_OK;
+  auto sys_active = [&](const Sys &y) {
+    for (int c = 0; c < y.k; ++c)
+      if (col[y.c0 + c].active) return true;
+    return false;
+  };
+  auto dot = [&](const Sys &y, Col &c, const double *u, const double *v, double *dst) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, y.n, u, v, c.part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, c.part, dst);
+  };
+  std::vector<double> hs(ncol);
+  auto read_scalars = [&](int slot) {     // sc[slot] of every active column
+    for (int c = 0; c < ncol; ++c)
+      if (col[c].active) HIPCHK(hipMemcpyAsync(&hs[c], col[c].sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  };
+  std::vector<BatchItem> items(count);
+  struct ItemsGuard {
+    Dev<BatchItem> *d; hipStream_t s;
+    ~ItemsGuard() { (void)hipStreamSynchronize(s); items_release(d); }
+  } guard{items_acquire(count), s};
+  Dev<BatchItem> &d_items = *guard.d;
+  // Z = (L L^*)^{-1} R for every system with an active column: one launch,
+  // one workgroup per system, all its columns at once
+  auto precond_all = [&]() {
     for (int i = 0; i < count; ++i) {
       Sys &y = sys[i];
-      y.a = as[i]; y.l = ms[i];
-      REQUIRE(y.a && bs[i] && xs[i], "null argument");
-      REQUIRE(y.a->n == y.l->bt->ct->n, "size mismatch");
-      y.n = (int)y.a->n;
-      y.k = nrhs ? nrhs[i] : 1;
-      REQUIRE(y.k >= 1 && y.k <= BC, "nrhs must be in [1, H2_MAX_COLS]");
-      y.g = grid_for(y.n);
-      const size_t need = (size_t)(4 * y.n + NP + 8) * y.k;
-      if (y.l->d_pcg.n < need) y.l->d_pcg.alloc_on(need, y.l->stream);
-      double *base = y.l->d_pcg.p;
-      y.R = base;
-      y.Z = y.R + (size_t)y.n * y.k;
-      double *P = y.Z + (size_t)y.n * y.k, *Q = P + (size_t)y.n * y.k, *PART = Q + (size_t)y.n * y.k;
-      double *SC = PART + (size_t)NP * y.k;
-      y.c0 = (int)col.size();
-      for (int c = 0; c < y.k; ++c) {
-        const size_t o = (size_t)c * y.n;
-        col.push_back(Col{bs[i] + o, xs[i] + o, y.R + o, y.Z + o, P + o, Q + o, PART + (size_t)c * NP,
-                          SC + 8 * c, 0.0, 0.0, 0, true, false});
-      }
-      prec_list(y.l);
-      sync_env(*y.l);
+      const bool act = sys_active(y);
+      const TaskList &tl = y.l->prec;
+      items[i] = BatchItem{tl.d.p, y.l->d_env.p, tl.aux.p, act ? tl.count : 0, 0};
+      if (act) prec_gather(y.l, y.R, y.k);
     }
-    const int ncol = (int)col.size();
-    if (status)
-      for (int c = 0; c < ncol; ++c) status[c] = H2_OK;
-    auto sys_active = [&](const Sys &y) {
-      for (int c = 0; c < y.k; ++c)
-        if (col[y.c0 + c].active) return true;
-      return false;
-    };
-    auto dot = [&](const Sys &y, Col &c, const double *u, const double *v, double *dst) {
-      hipLaunchKernelGGL(k_dot_partial, dim3(NP), dim3(256), 0, s, y.n, u, v, c.part);
-      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, NP, c.part, dst);
-    };
-    std::vector<double> hs(ncol);
-    auto read_scalars = [&](int slot) {     // sc[slot] of every active column
-      for (int c = 0; c < ncol; ++c)
-        if (col[c].active) HIPCHK(hipMemcpyAsync(&hs[c], col[c].sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-    };
-    std::vector<BatchItem> items(count);
-    struct ItemsGuard {
-      Dev<BatchItem> *d; hipStream_t s;
-      ~ItemsGuard() { (void)hipStreamSynchronize(s); items_release(d); }
-    } guard{items_acquire(count), s};
-    Dev<BatchItem> &d_items = *guard.d;
-    // Z = (L L^*)^{-1} R for every system with an active column: one launch,
-    // one workgroup per system, all its columns at once
-    auto precond_all = [&]() {
-      for (int i = 0; i < count; ++i) {
-        Sys &y = sys[i];
-        const bool act = sys_active(y);
-        const TaskList &tl = y.l->prec;
-        items[i] = BatchItem{tl.d.p, y.l->d_env.p, tl.aux.p, act ? tl.count : 0, 0};
-        if (act) prec_gather(y.l, y.R, y.k);
+    int nt = 0;   // one launch shape for all: the largest tuned one
+    for (const Sys &y : sys) nt = std::max(nt, prec_threads(*y.l, y.k));
+    launch_batch(d_items, items, nt, s);
+    for (Sys &y : sys)
+      if (sys_active(y)) prec_scatter(y.l, y.Z, y.k);
+  };
+  for (Sys &y : sys)
+    for (int c = 0; c < y.k; ++c) {
+      Col &t = col[y.c0 + c];
+      HIPCHK(hipMemsetAsync(t.x, 0, y.n * sizeof(double), s));
+      HIPCHK(hipMemcpyAsync(t.r, t.b, y.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      dot(y, t, t.b, t.b, t.sc + 4);
+    }
+  read_scalars(4);
+  for (int c = 0; c < ncol; ++c) {
+    col[c].nb = std::sqrt(hs[c]);
+    if (col[c].nb == 0.0) { col[c].active = false; col[c].conv = true; }
+  }
+  precond_all();
+  for (Sys &y : sys)
+    for (int c = 0; c < y.k; ++c) {
+      Col &t = col[y.c0 + c];
+      if (!t.active) continue;
+      HIPCHK(hipMemcpyAsync(t.p, t.z, y.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      dot(y, t, t.r, t.z, t.sc + 0);
+    }
+  if (graph) {
+    // One CG iteration of every column as a HIP graph, replayed until no
+    // column is active: all columns per launch (k_bpcg_*), gated by flags
+    // that the convergence test sets on the device, the preconditioner
+    // launch gated per system.  Only kernels are captured.
+    REQUIRE(ncol <= 65535, "too many right-hand sides for the graph form");
+    std::vector<PcgCol> hc(ncol);
+    std::vector<int> hctl(4 * (size_t)ncol + count + 1, 0);
+    int *h_act = hctl.data(), *h_conv = h_act + 2 * ncol, *h_sys = h_act + 3 * ncol;
+    int gx = 1;
+    for (int i = 0; i < count; ++i) {
+      const Sys &y = sys[i];
+      gx = std::max(gx, y.g);
+      for (int c = 0; c < y.k; ++c) {
+        const Col &t = col[y.c0 + c];
+        hc[y.c0 + c] = PcgCol{y.a->rp.p, y.a->ci.p, y.a->v.p, t.x, t.r, t.z, t.p, t.q, t.part, t.sc, t.nb, y.n, i};
+        h_act[y.c0 + c] = t.active ? 1 : 0;
+        h_conv[y.c0 + c] = t.conv ? 1 : 0;
+        if (t.active) h_sys[i] = 1;
       }
-      launch_batch(d_items, items, PREC_THREADS, s);
-      for (Sys &y : sys)
-        if (sys_active(y)) prec_scatter(y.l, y.Z, y.k);
-    };
+    }
+    Dev<PcgCol> d_cols;
+    Dev<int> d_ctl;
+    Dev<double> d_rel;
+    d_cols.alloc_on(ncol, s);
+    d_ctl.alloc_on(hctl.size(), s);
+    d_rel.alloc_on(ncol, s);
+    HIPCHK(hipMemcpyAsync(d_cols.p, hc.data(), ncol * sizeof(PcgCol), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_ctl.p, hctl.data(), hctl.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill_double, dim3(grid_for(ncol)), dim3(256), 0, s, d_rel.p, ncol, 0.0);
+    const PcgCtl ctl{d_ctl.p, d_ctl.p + ncol, d_ctl.p + 2 * ncol, d_ctl.p + 3 * ncol, d_ctl.p + 3 * ncol + count,
+                     d_rel.p};
+    int nt = 0;
+    for (int i = 0; i < count; ++i) {
+      const Sys &y = sys[i];
+      const TaskList &tl = y.l->prec;
+      items[i] = BatchItem{tl.d.p, y.l->d_env.p, tl.aux.p, tl.count, 0, ctl.sys_act + i};
+      nt = std::max(nt, prec_threads(*y.l, y.k));
+    }
+    HIPCHK(hipMemcpyAsync(d_items.p, items.data(), count * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    struct GraphGuard {
+      hipStream_t cs = nullptr; hipGraph_t g = nullptr; hipGraphExec_t x = nullptr; bool capturing = false;
+      ~GraphGuard() {
+        if (capturing) { hipGraph_t t = nullptr; (void)hipStreamEndCapture(cs, &t); if (t) (void)hipGraphDestroy(t); }
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        if (cs) (void)hipStreamDestroy(cs);
+      }
+    } gg;
+    // captured on a private stream (a legacy default stream cannot capture)
+    HIPCHK(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
+    gg.capturing = true;
+    const hipStream_t c = gg.cs;
+    const dim3 gv((unsigned)gx, (unsigned)ncol), gd((unsigned)NP, (unsigned)ncol);
+    hipLaunchKernelGGL(k_bpcg_spmv, gv, dim3(256), 0, c, (const PcgCol *)d_cols.p, (const int *)ctl.act);
+    hipLaunchKernelGGL(k_bpcg_dot_partial, gd, dim3(256), 0, c, (const PcgCol *)d_cols.p, (const int *)ctl.act,
+                       (int)PCG_DOT_PQ);
+    hipLaunchKernelGGL(k_bpcg_dot_final, dim3(ncol), dim3(256), 0, c, (const PcgCol *)d_cols.p,
+                       (const int *)ctl.act, NP, 1);
+    hipLaunchKernelGGL(k_bpcg_update_xr, gv, dim3(256), 0, c, (const PcgCol *)d_cols.p, (const int *)ctl.act);
+    hipLaunchKernelGGL(k_bpcg_dot_partial, gd, dim3(256), 0, c, (const PcgCol *)d_cols.p, (const int *)ctl.act,
+                       (int)PCG_DOT_RR);
+    hipLaunchKernelGGL(k_bpcg_dot_final, dim3(ncol), dim3(256), 0, c, (const PcgCol *)d_cols.p,
+                       (const int *)ctl.act, NP, 3);
+    hipLaunchKernelGGL(k_bpcg_check, dim3(1), dim3(256), 0, c, (const PcgCol *)d_cols.p, ctl, ncol, count, rtol,
+                       (int)maxit);
+    for (const Sys &y : sys) {
+      const h2_ctree_s &ct = *y.l->bt->ct;
+      const long work = (long)ct.n * y.k;
+      hipLaunchKernelGGL(k_gather, dim3(grid_for(work)), dim3(256), 0, c, (int)ct.n, 0, y.k, ct.d_perm.p,
+                         (const double *)y.R, (long)ct.n, y.l->env.buf[B_X], y.l->d_bcols.p, (int)B_X);
+    }
+    hipLaunchKernelGGL(k_interp_batch, dim3((unsigned)count), dim3((unsigned)nt),
+                       LDS_TOTAL_DOUBLES * sizeof(double), c, (const BatchItem *)d_items.p);
+    for (const Sys &y : sys) {
+      const h2_ctree_s &ct = *y.l->bt->ct;
+      const long work = (long)ct.n * y.k;
+      hipLaunchKernelGGL(k_scatter, dim3(grid_for(work)), dim3(256), 0, c, (int)ct.n, y.k, ct.d_perm.p,
+                         (const double *)y.l->env.buf[B_X], y.Z, (long)ct.n, 1.0, 0.0);
+    }
+    hipLaunchKernelGGL(k_bpcg_dot_partial, gd, dim3(256), 0, c, (const PcgCol *)d_cols.p, (const int *)ctl.act,
+                       (int)PCG_DOT_RZ);
+    hipLaunchKernelGGL(k_bpcg_dot_final, dim3(ncol), dim3(256), 0, c, (const PcgCol *)d_cols.p,
+                       (const int *)ctl.act, NP, 2);
+    hipLaunchKernelGGL(k_bpcg_update_p, gv, dim3(256), 0, c, (const PcgCol *)d_cols.p, (const int *)ctl.act);
+    hipLaunchKernelGGL(k_bpcg_next, dim3(grid_for(ncol)), dim3(256), 0, c, (const PcgCol *)d_cols.p,
+                       (const int *)ctl.act, ncol);
+    gg.capturing = false;
+    HIPCHK(hipStreamEndCapture(c, &gg.g));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipGraphInstantiate(&gg.x, gg.g, nullptr, nullptr, 0));
+    // every replay counts an iteration for each active column, so at most
+    // maxit replays leave none active
+    int nact = 1;
+    for (int rep = 0; rep < maxit && nact > 0; ++rep) {
+      HIPCHK(hipGraphLaunch(gg.x, s));
+      HIPCHK(hipMemcpyAsync(&nact, ctl.nact, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    std::vector<int> h_it(ncol), h_cv(ncol);
+    std::vector<double> h_rel(ncol);
+    HIPCHK(hipMemcpyAsync(h_it.data(), ctl.it, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_cv.data(), ctl.conv, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_rel.data(), ctl.rel, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < ncol; ++k) {
+      col[k].it = h_it[k];
+      col[k].conv = h_cv[k] != 0;
+      col[k].rel = h_rel[k];
+      col[k].active = false;
+    }
+  } else for (;;) {
+    bool any = false;
     for (Sys &y : sys)
       for (int c = 0; c < y.k; ++c) {
         Col &t = col[y.c0 + c];
-        HIPCHK(hipMemsetAsync(t.x, 0, y.n * sizeof(double), s));
-        HIPCHK(hipMemcpyAsync(t.r, t.b, y.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        dot(y, t, t.b, t.b, t.sc + 4);
+        if (!t.active) continue;
+        any = true;
+        hipLaunchKernelGGL(k_spmv, dim3(y.g), dim3(256), 0, s, y.n, y.a->rp.p, y.a->ci.p, y.a->v.p, t.p, t.q);
+        ++t.it;
+        dot(y, t, t.p, t.q, t.sc + 1);
+        hipLaunchKernelGGL(k_pcg_update_xr, dim3(y.g), dim3(256), 0, s, y.n, t.sc, t.p, t.q, t.x, t.r);
+        dot(y, t, t.r, t.r, t.sc + 3);
       }
-    read_scalars(4);
-    for (int c = 0; c < ncol; ++c) {
-      col[c].nb = std::sqrt(hs[c]);
-      if (col[c].nb == 0.0) { col[c].active = false; col[c].conv = true; }
+    if (!any) break;
+    read_scalars(3);
+    any = false;
+    for (Col &t : col) {
+      if (!t.active) continue;
+      t.rel = std::sqrt(hs[&t - col.data()]) / t.nb;
+      if (t.rel <= rtol) { t.conv = true; t.active = false; }
+      else if (t.it >= maxit) t.active = false;
+      any = any || t.active;
     }
+    if (!any) break;
     precond_all();
     for (Sys &y : sys)
       for (int c = 0; c < y.k; ++c) {
         Col &t = col[y.c0 + c];
         if (!t.active) continue;
-        HIPCHK(hipMemcpyAsync(t.p, t.z, y.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        dot(y, t, t.r, t.z, t.sc + 0);
+        dot(y, t, t.r, t.z, t.sc + 2);
+        hipLaunchKernelGGL(k_pcg_update_p, dim3(y.g), dim3(256), 0, s, y.n, t.sc, t.z, t.p);
+        hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, t.sc + 0, t.sc + 2);
       }
-    for (;;) {
-      bool any = false;
-      for (Sys &y : sys)
-        for (int c = 0; c < y.k; ++c) {
-          Col &t = col[y.c0 + c];
-          if (!t.active) continue;
-          any = true;
-          hipLaunchKernelGGL(k_spmv, dim3(y.g), dim3(256), 0, s, y.n, y.a->rp.p, y.a->ci.p, y.a->v.p, t.p, t.q);
-          ++t.it;
-          dot(y, t, t.p, t.q, t.sc + 1);
-          hipLaunchKernelGGL(k_pcg_update_xr, dim3(y.g), dim3(256), 0, s, y.n, t.sc, t.p, t.q, t.x, t.r);
-          dot(y, t, t.r, t.r, t.sc + 3);
-        }
-      if (!any) break;
-      read_scalars(3);
-      any = false;
-      for (Col &t : col) {
-        if (!t.active) continue;
-        t.rel = std::sqrt(hs[&t - col.data()]) / t.nb;
-        if (t.rel <= rtol) { t.conv = true; t.active = false; }
-        else if (t.it >= maxit) t.active = false;
-        any = any || t.active;
-      }
-      if (!any) break;
-      precond_all();
-      for (Sys &y : sys)
-        for (int c = 0; c < y.k; ++c) {
-          Col &t = col[y.c0 + c];
-          if (!t.active) continue;
-          dot(y, t, t.r, t.z, t.sc + 2);
-          hipLaunchKernelGGL(k_pcg_update_p, dim3(y.g), dim3(256), 0, s, y.n, t.sc, t.z, t.p);
-          hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, t.sc + 0, t.sc + 2);
-        }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  for (int c = 0; c < ncol; ++c) {
+    if (iters) iters[c] = col[c].it;
+    if (relres) relres[c] = col[c].rel;
+  }
+  std::vector<h2_status> sst(count, H2_OK);
+  try {
+    batch_errors(ms, sst.data());
+  } catch (const H2Error &) {
+    if (status)
+      for (int i = 0; i < count; ++i)
+        for (int c = 0; c < sys[i].k; ++c) status[sys[i].c0 + c] = sst[i];
+    throw;
+  }
+  int bad = -1;
+  for (int c = 0; c < ncol; ++c)
+    if (!col[c].conv) {
+      if (status) status[c] = H2_ERR_NOT_CONVERGED;
+      if (bad < 0) bad = c;
     }
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    for (int c = 0; c < ncol; ++c) {
-      if (iters) iters[c] = col[c].it;
-      if (relres) relres[c] = col[c].rel;
-    }
-    std::vector<h2_status> sst(count, H2_OK);
-    try {
-      batch_errors(ms, sst.data());
-    } catch (const H2Error &) {
-      if (status)
-        for (int i = 0; i < count; ++i)
-          for (int c = 0; c < sys[i].k; ++c) status[sys[i].c0 + c] = sst[i];
-      throw;
-    }
-    int bad = -1;
-    for (int c = 0; c < ncol; ++c)
-      if (!col[c].conv) {
-        if (status) status[c] = H2_ERR_NOT_CONVERGED;
-        if (bad < 0) bad = c;
-      }
-    if (bad >= 0)
-      throw H2Error(H2_ERR_NOT_CONVERGED,
-                    "PCG did not reach the tolerance (first: right-hand side " + std::to_string(bad) + ")");
-  });
+  if (bad >= 0)
+    throw H2Error(H2_ERR_NOT_CONVERGED,
+                  "PCG did not reach the tolerance (first: right-hand side " + std::to_string(bad) + ")");
 }
+
+extern "C" {
+
+h2_status h2_pcg_batched(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
+                         const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
+                         double *relres, h2_status *status) {
+  return guarded([&] { pcg_batched(as, ls, bs, xs, nrhs, count, rtol, maxit, iters, relres, status, false); });
+}
+
+h2_status h2_pcg_batched_graph(h2_csr *as, h2_mat *ls, const double *const *bs, double *const *xs,
+                               const int32_t *nrhs, int32_t count, double rtol, int32_t maxit, int32_t *iters,
+                               double *relres, h2_status *status) {
+  return guarded([&] { pcg_batched(as, ls, bs, xs, nrhs, count, rtol, maxit, iters, relres, status, true); });
+}
+
+}  // extern "C"
+
+extern "C" {
 
 // PCG body shared by h2_pcg and h2_pcg_noalloc.  work: 4n + PCG_PART + 8
 // doubles (r, z, p, q, dot partial sums, scalars).  fill_kernel: clear x

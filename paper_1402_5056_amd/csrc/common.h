@@ -110,6 +110,28 @@ struct BatchItem {
   const int *aux;
   int ntask;
   int pad;
+  const int *gate;   // optional: the workgroup skips its list while *gate == 0
+};
+
+// One right-hand side of the batched PCG in its graph form: the system's
+// CSR matrix, the column's vectors (length n), its dot-product partial sums
+// and scalars (sc[0] = r.z, sc[1] = p.q, sc[2] = new r.z, sc[3] = r.r),
+// ||b|| and the index of its system.
+struct PcgCol {
+  const int64_t *rp;
+  const int *ci;
+  const double *v;
+  double *x, *r, *z, *p, *q, *part, *sc;
+  double nb;
+  int n, sys;
+};
+
+// Device state of the batched PCG graph form, per column: active flag,
+// iterations, converged flag, relative residual; per system: any column
+// active; and the number of active columns.
+struct PcgCtl {
+  int *act, *it, *conv, *sys_act, *nact;
+  double *rel;
 };
 
 // Layout of the optional profile counters (ticks of the 100 MHz wall clock).

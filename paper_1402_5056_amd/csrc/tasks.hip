@@ -1780,6 +1780,7 @@ __global__ __launch_bounds__(NT) void k_interp(const Task *__restrict__ tasks, i
 // task list, matrix and work areas; nothing is shared between workgroups).
 __global__ __launch_bounds__(NT) void k_interp_batch(const BatchItem *__restrict__ items) {
   const BatchItem it = items[blockIdx.x];
+  if (it.gate != nullptr && *it.gate == 0) return;
   interp_run(it.tasks, it.ntask, it.env, it.aux);
 }
 
@@ -1876,5 +1877,118 @@ __global__ void k_pcg_update_p(int n, double *__restrict__ sc, const double *__r
 }
 
 __global__ void k_copy_scalar(double *dst, const double *src) { *dst = *src; }
+
+// ------------------------------------------- batched PCG, all columns per launch
+// The graph form of the batched PCG: one launch per operation for all
+// right-hand sides (blockIdx.y = column), each gated by the column's active
+// flag.  Per column the arithmetic is that of the single-column kernels
+// above (same row loops, same partial-sum blocking of the dot products), so
+// both forms give the same numbers.
+enum : int { PCG_DOT_PQ = 0, PCG_DOT_RR = 1, PCG_DOT_RZ = 2 };
+
+__global__ void k_bpcg_spmv(const PcgCol *__restrict__ cols, const int *__restrict__ act) {
+  const int c = blockIdx.y;
+  if (act[c] == 0) return;
+  const PcgCol k = cols[c];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n; i += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t p = k.rp[i]; p < k.rp[i + 1]; ++p) s = fma(k.v[p], k.p[k.ci[p]], s);
+    k.q[i] = s;
+  }
+}
+
+__global__ void k_bpcg_dot_partial(const PcgCol *__restrict__ cols, const int *__restrict__ act, int which) {
+  const int c = blockIdx.y;
+  if (act[c] == 0) return;
+  const PcgCol k = cols[c];
+  const double *a = which == PCG_DOT_PQ ? k.p : k.r;
+  const double *b = which == PCG_DOT_PQ ? k.q : (which == PCG_DOT_RR ? k.r : k.z);
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n; i += gridDim.x * blockDim.x) s = fma(a[i], b[i], s);
+  s = wave_sum(s);
+  if (lane_id() == 0) red[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < num_waves(); ++w) t += red[w];
+    k.part[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_bpcg_dot_final(const PcgCol *__restrict__ cols, const int *__restrict__ act, int np, int slot) {
+  const int c = blockIdx.x;
+  if (act[c] == 0) return;
+  const PcgCol k = cols[c];
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += k.part[i];
+  s = wave_sum(s);
+  if (lane_id() == 0) red[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < num_waves(); ++w) t += red[w];
+    k.sc[slot] = t;
+  }
+}
+
+__global__ void k_bpcg_update_xr(const PcgCol *__restrict__ cols, const int *__restrict__ act) {
+  const int c = blockIdx.y;
+  if (act[c] == 0) return;
+  const PcgCol k = cols[c];
+  const double alpha = k.sc[0] / k.sc[1];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n; i += gridDim.x * blockDim.x) {
+    k.x[i] = fma(alpha, k.p[i], k.x[i]);
+    k.r[i] = fma(-alpha, k.q[i], k.r[i]);
+  }
+}
+
+__global__ void k_bpcg_update_p(const PcgCol *__restrict__ cols, const int *__restrict__ act) {
+  const int c = blockIdx.y;
+  if (act[c] == 0) return;
+  const PcgCol k = cols[c];
+  const double beta = k.sc[2] / k.sc[0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n; i += gridDim.x * blockDim.x)
+    k.p[i] = fma(beta, k.p[i], k.z[i]);
+}
+
+__global__ void k_bpcg_next(const PcgCol *__restrict__ cols, const int *__restrict__ act, int ncol) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += gridDim.x * blockDim.x)
+    if (act[c] != 0) cols[c].sc[0] = cols[c].sc[2];
+}
+
+// Convergence test after x and r are updated (one workgroup): a column that
+// ran this iteration counts it, stores ||r|| / ||b|| and stops when that is
+// at most rtol (converged) or the iteration limit is reached; a system stays
+// active while one of its columns is.
+__global__ void k_bpcg_check(const PcgCol *__restrict__ cols, PcgCtl ctl, int ncol, int nsys, double rtol,
+                             int maxit) {
+  for (int y = threadIdx.x; y < nsys; y += blockDim.x) ctl.sys_act[y] = 0;
+  __syncthreads();
+  int cnt = 0;
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    if (ctl.act[c] == 0) continue;
+    const int it = ctl.it[c] + 1;
+    ctl.it[c] = it;
+    const double rel = sqrt(cols[c].sc[3]) / cols[c].nb;
+    ctl.rel[c] = rel;
+    int a = 1;
+    if (rel <= rtol) { ctl.conv[c] = 1; a = 0; }
+    else if (it >= maxit) a = 0;
+    ctl.act[c] = a;
+    if (a) { ctl.sys_act[cols[c].sys] = 1; ++cnt; }
+  }
+  __shared__ int red[16];
+  int s = cnt;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane_id() == 0) red[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < num_waves(); ++w) t += red[w];
+    *ctl.nact = t;
+  }
+}
 
 }  // namespace h2

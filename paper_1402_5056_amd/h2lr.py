@@ -100,10 +100,16 @@ _SIG = {
     "h2_lowrank_update_batched": [_P(_vp), _i32, _P(_i32), _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp),
                                   _P(_i64), _P(h2_trunc), _P(C.c_int)],
     "h2_cholesky_launch": [_P(_vp), _i32, _P(h2_trunc), _P(_vp)],
+    "h2_precond_config": [_vp, _i32, _i32],
+    "h2_autotune_precond": [_vp, _i32, _i32, C.c_char_p, _P(_i32), _P(_d), _P(_i32), _P(_d)],
+    "h2_update_cholesky_launch": [_P(_vp), _i32, _P(_i32), _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp),
+                                  _P(_i64), _P(_vp), _i32, _P(h2_trunc), _P(_vp)],
     "h2_job_query": [_vp, _P(_i32)],
     "h2_job_finish": [_vp, _P(C.c_int)],
     "h2_pcg_batched": [_P(_vp), _P(_vp), _P(_vp), _P(_vp), _P(_i32), _i32, _d, _i32, _P(_i32), _P(_d),
                        _P(C.c_int)],
+    "h2_pcg_batched_graph": [_P(_vp), _P(_vp), _P(_vp), _P(_vp), _P(_i32), _i32, _d, _i32, _P(_i32), _P(_d),
+                             _P(C.c_int)],
     "h2_precond": [_vp, _vp, _vp, _i32],
     "h2_trsv": [_vp, _i32, _vp, _vp, _i32],
     "h2_tri_invert": [_vp, _vp],
@@ -407,24 +413,26 @@ def h2_mat_bytes(m: Mat) -> int:
     return v.value
 
 
+def _update_arrays(mats, updates):
+    """Flat host arrays of a batch of local updates (h2_lowrank_update_batched)."""
+    k = len(mats)
+    flat = [u for ups in updates for u in ups]
+    nu = max(len(flat), 1)
+
+    def ld(T):
+        return T.stride(1) if T.shape[1] > 1 else T.shape[0]
+    return ((_vp * max(k, 1))(*[m.h for m in mats]), (_i32 * max(k, 1))(*[len(u) for u in updates]),
+            (_i64 * nu)(*[int(b) for b, _, _ in flat]), (_i32 * nu)(*[int(X.shape[1]) for _, X, _ in flat]),
+            (_vp * nu)(*[_ptr(X) for _, X, _ in flat]), (_i64 * nu)(*[ld(X) for _, X, _ in flat]),
+            (_vp * nu)(*[_ptr(Y) for _, _, Y in flat]), (_i64 * nu)(*[ld(Y) for _, _, Y in flat]))
+
+
 def h2_lowrank_update_batched(mats, updates, tr: h2_trunc, check: bool = True):
     """updates[i]: list of (block, X, Y) for mats[i] (at most 4), X, Y
     column-major device tensors as for h2_lowrank_update.  Returns the
     per-matrix status list."""
     k = len(mats)
-    flat = [u for ups in updates for u in ups]
-    nu = len(flat)
-
-    def ld(T):
-        return T.stride(1) if T.shape[1] > 1 else T.shape[0]
-    arr = (_vp * k)(*[m.h for m in mats])
-    nupd = (_i32 * k)(*[len(u) for u in updates])
-    blocks = (_i64 * max(nu, 1))(*[int(b) for b, _, _ in flat])
-    ks = (_i32 * max(nu, 1))(*[int(X.shape[1]) for _, X, _ in flat])
-    Xs = (_vp * max(nu, 1))(*[_ptr(X) for _, X, _ in flat])
-    Ys = (_vp * max(nu, 1))(*[_ptr(Y) for _, _, Y in flat])
-    ldx = (_i64 * max(nu, 1))(*[ld(X) for _, X, _ in flat])
-    ldy = (_i64 * max(nu, 1))(*[ld(Y) for _, _, Y in flat])
+    arr, nupd, blocks, ks, Xs, ldx, Ys, ldy = _update_arrays(mats, updates)
     st = (C.c_int * k)()
     status = _lib.h2_lowrank_update_batched(arr, k, nupd, blocks, ks, Xs, ldx, Ys, ldy, C.byref(tr), st)
     codes = list(st)
@@ -445,12 +453,13 @@ def h2_cholesky_batched(mats, tr: h2_trunc):
 
 
 class Job:
-    """A launched batch of factorisations (h2_cholesky_launch); holds its
-    matrices until finish()."""
+    """A launched batch (h2_cholesky_launch, h2_update_cholesky_launch);
+    holds its matrices (and the update factors it reads) until finish()."""
 
-    def __init__(self, h, mats):
+    def __init__(self, h, mats, keep=()):
         self.h = h
         self.mats = list(mats)
+        self.keep = list(keep)
 
     def done(self) -> bool:
         v = _i32()
@@ -473,6 +482,7 @@ class Job:
         status = _lib.h2_job_finish(h, st)
         codes = list(st)
         self.mats = []
+        self.keep = []
         if check:
             _check(status)
         return codes
@@ -485,11 +495,26 @@ def h2_cholesky_launch(mats, tr: h2_trunc) -> Job:
     return Job(h.value, mats)
 
 
-def h2_pcg_batched(csrs, mats, bs, xs, rtol: float = 1e-8, maxit: int = 500, check: bool = True):
+def h2_update_cholesky_launch(umats, updates, cmats, tr: h2_trunc) -> Job:
+    """Local updates of umats (updates as for h2_lowrank_update_batched) and
+    Cholesky factorisations of cmats in one launch; the job's status list
+    has the updated matrices first."""
+    arr, nupd, blocks, ks, Xs, ldx, Ys, ldy = _update_arrays(umats, updates)
+    carr = (_vp * max(len(cmats), 1))(*[m.h for m in cmats])
+    h = _vp()
+    _check(_lib.h2_update_cholesky_launch(arr, len(umats), nupd, blocks, ks, Xs, ldx, Ys, ldy, carr, len(cmats),
+                                          C.byref(tr), C.byref(h)))
+    keep = [T for ups in updates for _, X, Y in ups for T in (X, Y)]
+    return Job(h.value, list(umats) + list(cmats), keep)
+
+
+def h2_pcg_batched(csrs, mats, bs, xs, rtol: float = 1e-8, maxit: int = 500, check: bool = True,
+                   graph: bool = False):
     """bs[i], xs[i]: device float64 tensors of shape (n_i,) or (k_i, n_i)
     (k_i right-hand sides, contiguous).  Returns (iters, relres, status),
     flat lists with one entry per right-hand side; raises H2Error for the
-    first failure when check is true."""
+    first failure when check is true.  graph: replay the iterations from a
+    captured HIP graph (h2_pcg_batched_graph)."""
     k = len(mats)
     A = (_vp * k)(*[a.h for a in csrs])
     Ls = (_vp * k)(*[m.h for m in mats])
@@ -504,7 +529,8 @@ def h2_pcg_batched(csrs, mats, bs, xs, rtol: float = 1e-8, maxit: int = 500, che
     it = (_i32 * tot)()
     rel = (_d * tot)()
     st = (C.c_int * tot)()
-    status = _lib.h2_pcg_batched(A, Ls, B, X, nr, k, float(rtol), int(maxit), it, rel, st)
+    fn = _lib.h2_pcg_batched_graph if graph else _lib.h2_pcg_batched
+    status = fn(A, Ls, B, X, nr, k, float(rtol), int(maxit), it, rel, st)
     if check:
         _check(status)
     return list(it), list(rel), list(st)
@@ -529,6 +555,19 @@ def h2_trsv(m: Mat, r, z, trans: bool = False):
 def h2_precond(m: Mat, r, z):
     nrhs = 1 if r.dim() == 1 else r.shape[0]
     _check(_lib.h2_precond(m.h, _ptr(r), _ptr(z), nrhs))
+
+
+def h2_precond_config(m: Mat, nrhs: int, threads: int):
+    _check(_lib.h2_precond_config(m.h, int(nrhs), int(threads)))
+
+
+def h2_autotune_precond(m: Mat, nrhs: int = 1, reps: int = 5, cache_path: str | None = None):
+    """Returns (threads, ms per application, from_cache, {threads: ms} of
+    every shape timed)."""
+    t, ms, fc, by = _i32(), _d(), _i32(), (_d * 3)()
+    path = cache_path.encode() if cache_path else None
+    _check(_lib.h2_autotune_precond(m.h, int(nrhs), int(reps), path, C.byref(t), C.byref(ms), C.byref(fc), by))
+    return t.value, ms.value, bool(fc.value), ({} if fc.value else dict(zip((128, 256, 512), list(by))))
 
 
 def h2_csr_create(ctx: Ctx, A) -> Csr:

@@ -3,7 +3,8 @@
  * accounting): "device" memory is host memory, copies are memmove, kernel
  * launches and events do nothing.  No numerical result is meaningful under
  * it.  Exports the runtime symbols the library imports, versioned hip_4.2
- * (the stream-ordered allocator hip_5.1). */
+ * (graphs and stream capture hip_4.3, the stream-ordered allocator hip_5.1,
+ * the device properties hip_6.0). */
 #include <stdlib.h>
 #include <string.h>
 #include <stddef.h>
@@ -41,3 +42,15 @@ hipError_t hipEventRecord(void *e, void *s) { return 0; }
 hipError_t hipEventQuery(void *e) { return 0; }
 hipError_t hipEventSynchronize(void *e) { return 0; }
 hipError_t hipEventDestroy(void *e) { return 0; }
+hipError_t hipEventCreate(void **e) { *e = (void *)dummy; return 0; }
+hipError_t hipStreamCreateWithFlags(void **s, unsigned f) { *s = (void *)dummy; return 0; }
+hipError_t hipStreamDestroy(void *s) { return 0; }
+hipError_t hipStreamBeginCapture(void *s, int mode) { return 0; }
+hipError_t hipStreamEndCapture(void *s, void **g) { *g = (void *)dummy; return 0; }
+hipError_t hipGraphInstantiate(void **x, void *g, void *node, char *log, size_t n) { *x = (void *)dummy; return 0; }
+hipError_t hipGraphLaunch(void *x, void *s) { return 0; }
+hipError_t hipGraphExecDestroy(void *x) { return 0; }
+hipError_t hipGraphDestroy(void *g) { return 0; }
+hipError_t hipEventElapsedTime(float *ms, void *a, void *b) { *ms = 1.0f; return 0; }
+/* the properties structure (1472 bytes in this runtime) is only written */
+hipError_t hipGetDevicePropertiesR0600(void *prop, int dev) { memset(prop, 0, 1472); return 0; }

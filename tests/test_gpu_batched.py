@@ -304,3 +304,53 @@ def test_update_batched_argument_errors(lib):
     with pytest.raises(lib.H2Error) as ei:
         lib.h2_lowrank_update_batched([L], [[(above, X, X)]], tr)
     assert ei.value.name == "H2_ERR_ARG"
+
+
+def test_update_and_cholesky_one_launch(lib):
+    """Local updates of full-storage matrices and Cholesky factorisations of
+    other matrices in one launch (h2_update_cholesky_launch): every result
+    equals the separate batched calls bit for bit (same task lists, same
+    arithmetic), and the factors equal the oracle's within 1e-12."""
+    from tests.helpers import to_dev_cols
+    print("case: updates + Cholesky in one launch (sides 24, 32, 40)", flush=True)
+    ctx = lib.h2_ctx_create(0)
+    eps = 1e-6
+    tr = lib.trunc(eps, "block_rel", 32)
+    U, Us, L, Ls, updates, refs = [], [], [], [], [], []
+    for (side, sg, leaf), nup in zip(((24, 3, 16), (32, 4, 32), (40, 7, 24)), (4, 3, 2)):
+        p, A, bt = _problem(lib, ctx, side, sg, leaf, 2.0, False)
+        U.append(lib.h2_mat_from_csr(ctx, bt, A))
+        Us.append(lib.h2_mat_from_csr(ctx, bt, A))
+        L.append(lib.h2_mat_from_csr(ctx, bt, A, lower=True))
+        Ls.append(lib.h2_mat_from_csr(ctx, bt, A, lower=True))
+        ex = lib.h2_btree_export(bt)
+        tree = lib.h2_ctree_export(lib.h2_ctree_build(ctx, p["coords"], leaf))
+        sons = [b for b in range(len(ex["parent"])) if ex["parent"][b] == 0]
+        ups = []
+        for j in range(nup):
+            b = sons[j % len(sons)]
+            X = w.gaussian(int(tree["size"][ex["row"][b]]), 4, 500 + side + j)
+            Y = w.gaussian(int(tree["size"][ex["col"][b]]), 4, 600 + side + j)
+            ups.append((b, to_dev_cols(X), to_dev_cols(Y)))
+        updates.append(ups)
+        oc = build_cluster_tree(p["coords"], leaf)
+        refs.append((A.shape[0], oc, o_from_csr(A, oc, build_block_tree(oc, 2.0), lower=True)))
+    job = lib.h2_update_cholesky_launch(U, updates, L, tr)
+    assert job.finish() == [0] * 6
+    assert lib.h2_lowrank_update_batched(Us, updates, tr) == [0, 0, 0]
+    assert lib.h2_cholesky_batched(Ls, tr) == [0, 0, 0]
+    tp = TruncParams(eps, "block_rel", 32)
+    for M, Ms, F, Fs, (n, oc, H) in zip(U, Us, L, Ls, refs):
+        assert np.array_equal(dense_via_matvec(lib, M, n), dense_via_matvec(lib, Ms, n))
+        D = dense_via_matvec(lib, F, n)
+        assert np.array_equal(D, dense_via_matvec(lib, Fs, n))
+        err = rel2(D, to_original(o_to_dense(o_cholesky(H, tp)), oc.perm))
+        print(f"  n={n}: updates equal, factor equal, ||L - L_oracle||_2 / ||L_oracle||_2 = {err:.3e}", flush=True)
+        assert err < TOL
+    # argument errors: a matrix in both lists, nothing to do
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_update_cholesky_launch([L[0]], [[]], [L[0]], tr)
+    assert ei.value.name == "H2_ERR_ARG"
+    with pytest.raises(lib.H2Error) as ei:
+        lib.h2_update_cholesky_launch([], [], [], tr)
+    assert ei.value.name == "H2_ERR_ARG"

@@ -112,10 +112,14 @@ def stub_dir(tmp_path_factory):
         pytest.skip("library not built")
     d = tmp_path_factory.mktemp("hipstub")
     ver = d / "ver.map"
-    # the stream-ordered allocator came with the runtime's symbol version hip_5.1
+    # symbol versions of the runtime: graphs hip_4.3, the stream-ordered
+    # allocator hip_5.1, the device properties hip_6.0
     ver.write_text("hip_4.2 { global: *; };\n"
+                   "hip_4.3 { global: hipStreamBeginCapture; hipStreamEndCapture; hipGraphInstantiate; "
+                   "hipGraphLaunch; hipGraphExecDestroy; hipGraphDestroy; } hip_4.2;\n"
                    "hip_5.1 { global: hipMallocAsync; hipFreeAsync; hipDeviceGetDefaultMemPool; "
-                   "hipMemPoolSetAttribute; } hip_4.2;\n")
+                   "hipMemPoolSetAttribute; } hip_4.3;\n"
+                   "hip_6.0 { global: hipGetDevicePropertiesR0600; } hip_5.1;\n")
     src = os.path.join(ROOT, "tests", "host_stub", "hip_host_stub.c")
     subprocess.run(["gcc", "-O1", "-shared", "-fPIC", "-o", str(d / "libamdhip64.so.7"), src,
                     f"-Wl,--version-script={ver}", "-Wl,-soname,libamdhip64.so.7"], check=True)
