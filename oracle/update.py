@@ -251,3 +251,53 @@ def addlr(Z: H2Matrix, b0: int, X: np.ndarray, Y: np.ndarray, tp: TruncParams,
     for b, S in newS.items():
         Z.S[b] = S
     return True
+
+
+def common_block(bt, blocks) -> int:
+    """The smallest block of the block tree that contains every block in
+    ``blocks``: the deepest common ancestor (a block contains its sons'
+    index sets, so the ancestors of a block are exactly the blocks that
+    contain it)."""
+    def ancestors(b):
+        out = []
+        while b >= 0:
+            out.append(int(b))
+            b = int(bt.parent[b])
+        return out
+    common = set(ancestors(blocks[0]))
+    for b in blocks[1:]:
+        common &= set(ancestors(b))
+    # the deepest one: the first ancestor of blocks[0] that is common
+    return next(a for a in ancestors(blocks[0]) if a in common)
+
+
+def addlr_accumulated(Z: H2Matrix, updates, tp: TruncParams, margins: list | None = None):
+    """Accumulated local update (the accumulation variant of the truncation
+    strategies, last paragraph of Section 4): the updates (b_i, X_i, Y_i) are
+    merged into ONE local update of the smallest block b* = (t*, s*)
+    containing every target, with the factors placed side by side,
+        X* = [P_1 X_1, ..., P_m X_m],   Y* = [Q_1 Y_1, ..., Q_m Y_m],
+    P_i (Q_i) putting the rows of t_i (s_i) at their place in t* (s*) and
+    zeros elsewhere, so that X* Y*^* = sum_i P_i X_i Y_i^* Q_i^* exactly;
+    then one recompression instead of m.  Returns b*.
+
+    Reading: the paper names the truncation strategies without fixing how
+    contributions are grouped; merging into the smallest containing block
+    with block-placed factors is the reading taken here."""
+    ct, bt = Z.ct, Z.bt
+    blocks = [int(b) for b, _, _ in updates]
+    bs = common_block(bt, blocks)
+    ts, ss = int(bt.row[bs]), int(bt.col[bs])
+    ks = [np.asarray(X).shape[1] for _, X, _ in updates]
+    Xs = np.zeros((int(ct.size[ts]), sum(ks)))
+    Ys = np.zeros((int(ct.size[ss]), sum(ks)))
+    c = 0
+    for (b, X, Y), k in zip(updates, ks):
+        t, s = int(bt.row[b]), int(bt.col[b])
+        rt = int(ct.offset[t] - ct.offset[ts])
+        rs = int(ct.offset[s] - ct.offset[ss])
+        Xs[rt:rt + int(ct.size[t]), c:c + k] = X
+        Ys[rs:rs + int(ct.size[s]), c:c + k] = Y
+        c += k
+    addlr(Z, bs, Xs, Ys, tp, margins)
+    return bs
