@@ -213,6 +213,19 @@ h2_status h2_profile(h2_mat m, int32_t enable, int64_t *counters, int32_t n);
 h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X, int64_t ldx,
                             const double *Y, int64_t ldy, const h2_trunc *tr);
 
+/* Accumulated local update: the count updates (blocks[i], X_i, Y_i), with
+ * arguments as for h2_lowrank_update, are merged into ONE local update of
+ * the smallest block b* = (t*, s*) of the block tree that contains every
+ * target, with factors X* = [P_1 X_1 ... P_m X_m], Y* = [Q_1 Y_1 ... Q_m Y_m]
+ * (P_i, Q_i place the rows of t_i, s_i inside t*, s*; zeros elsewhere), so
+ * X* Y*^* = sum_i P_i X_i Y_i^* Q_i^* and one recompression replaces m
+ * (the accumulation variant of the truncation strategies at the end of
+ * Section 4).  sum_i k_i <= H2_MAX_UPDATE_RANK.  merged_block (may be NULL)
+ * receives b*.  H2_ERR_ARG for bad arguments; H2_ERR_RANK_CAP poisons. */
+h2_status h2_lowrank_update_accumulated(h2_mat z, int32_t count, const int64_t *blocks, const int32_t *ks,
+                                        const double *const *Xs, const int64_t *ldxs, const double *const *Ys,
+                                        const int64_t *ldys, const h2_trunc *tr, int64_t *merged_block);
+
 /* Local low-rank updates of count distinct matrices in one launch (one
  * workgroup per matrix; each matrix's updates run in order with the
  * arithmetic of h2_lowrank_update, so the results equal the single calls).

@@ -1494,6 +1494,89 @@ h2_status h2_lowrank_update(h2_mat z, int64_t block, int32_t k, const double *X,
   });
 }
 
+// Smallest block of the block tree containing every block in the list: the
+// deepest common ancestor (the ancestors of a block are the blocks that
+// contain it).
+static int common_block(const h2_btree_s &bt, const int64_t *blocks, int count) {
+  std::vector<int> path;   // ancestors of the first block, deepest first
+  for (int b = (int)blocks[0]; b >= 0; b = bt.parent[b]) path.push_back(b);
+  std::vector<char> keep(path.size(), 1);
+  for (int i = 1; i < count; ++i) {
+    std::vector<char> seen(path.size(), 0);
+    for (int b = (int)blocks[i]; b >= 0; b = bt.parent[b])
+      for (size_t j = 0; j < path.size(); ++j)
+        if (path[j] == b) seen[j] = 1;
+    for (size_t j = 0; j < path.size(); ++j) keep[j] = keep[j] && seen[j];
+  }
+  for (size_t j = 0; j < path.size(); ++j)
+    if (keep[j]) return path[j];
+  return 0;   // the root contains every block
+}
+
+h2_status h2_lowrank_update_accumulated(h2_mat z, int32_t count, const int64_t *blocks, const int32_t *ks,
+                                        const double *const *Xs, const int64_t *ldxs, const double *const *Ys,
+                                        const int64_t *ldys, const h2_trunc *tr, int64_t *merged_block) {
+  return guarded([&] {
+    require_ok(z);
+    require_validated_tree(*z);
+    REQUIRE(count >= 1 && blocks && ks && Xs && ldxs && Ys && ldys, "null argument or empty list");
+    const h2_btree_s &bt = *z->bt;
+    const h2_ctree_s &ct = *bt.ct;
+    int ktot = 0;
+    for (int i = 0; i < count; ++i) {
+      REQUIRE(blocks[i] >= 0 && blocks[i] < bt.nb, "block out of range");
+      REQUIRE(ks[i] >= 0 && ks[i] <= H2_MAX_UPDATE_RANK, "update rank out of range");
+      const int t = bt.row[blocks[i]], c = bt.col[blocks[i]];
+      if (z->lower) REQUIRE(t == c || ct.offset[t] > ct.offset[c], "block above the diagonal of a lower matrix");
+      if (ks[i] == 0) continue;
+      REQUIRE(Xs[i] && Ys[i], "null factor");
+      REQUIRE(ldxs[i] >= ct.size[t] && ldys[i] >= ct.size[c], "leading dimension too small");
+      ktot += ks[i];
+    }
+    REQUIRE(ktot <= H2_MAX_UPDATE_RANK, "accumulated rank above H2_MAX_UPDATE_RANK");
+    const int bs = common_block(bt, blocks, count);
+    const int ts = bt.row[bs], ss = bt.col[bs];
+    if (z->lower) REQUIRE(ts == ss || ct.offset[ts] > ct.offset[ss], "internal: merged block above the diagonal");
+    if (merged_block) *merged_block = bs;
+    if (ktot == 0) return;
+    set_trunc(*z, tr);
+    hipStream_t s = z->ctx->stream;
+    // merged factors: the rows of t* (s*) in the update buffers, cleared,
+    // then every factor at its rows and its own columns
+    const int side_rows[2] = {ts, ss};
+    const int bufs[2] = {B_X, B_Y};
+    for (int side = 0; side < 2; ++side) {
+      const int c = side_rows[side];
+      const long len = (long)ct.size[c] * BC;
+      hipLaunchKernelGGL(k_fill_double, dim3(grid_for(len)), dim3(256), 0, s,
+                         z->env.buf[bufs[side]] + (long)ct.offset[c] * BC, (int)len, 0.0);
+    }
+    int col0 = 0;
+    for (int i = 0; i < count; ++i) {
+      const int k = ks[i];
+      if (k == 0) continue;
+      const int t = bt.row[blocks[i]], c = bt.col[blocks[i]];
+      hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[t] * k)), dim3(256), 0, s, ct.size[t],
+                         ct.offset[t], k, (const int64_t *)nullptr, Xs[i], (long)ldxs[i],
+                         z->env.buf[B_X] + col0, z->d_bcols.p, (int)B_X);
+      hipLaunchKernelGGL(k_gather, dim3(grid_for((long)ct.size[c] * k)), dim3(256), 0, s, ct.size[c],
+                         ct.offset[c], k, (const int64_t *)nullptr, Ys[i], (long)ldys[i],
+                         z->env.buf[B_Y] + col0, z->d_bcols.p, (int)B_Y);
+      col0 += k;
+    }
+    for (int side = 0; side < 2; ++side)
+      hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, z->d_bcols.p + bufs[side], 1, ktot);
+    HIPCHK(hipGetLastError());
+    std::vector<Task> tasks;
+    Planner P(*z, tasks);
+    P.addlr(bs, B_X, B_Y);
+    TaskList tl;
+    upload_tasks(*z, tl, tasks, P.aux);
+    run_tasks(*z, tl);
+    check_device_error(*z);
+  });
+}
+
 h2_status h2_matvec(h2_mat z, int32_t trans, double alpha, const double *x, double beta, double *y,
                     int32_t nrhs) {
   return guarded([&] {

@@ -100,6 +100,8 @@ _SIG = {
     "h2_lowrank_update_batched": [_P(_vp), _i32, _P(_i32), _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp),
                                   _P(_i64), _P(h2_trunc), _P(C.c_int)],
     "h2_cholesky_launch": [_P(_vp), _i32, _P(h2_trunc), _P(_vp)],
+    "h2_lowrank_update_accumulated": [_vp, _i32, _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp), _P(_i64),
+                                      _P(h2_trunc), _P(_i64)],
     "h2_precond_config": [_vp, _i32, _i32],
     "h2_autotune_precond": [_vp, _i32, _i32, C.c_char_p, _P(_i32), _P(_d), _P(_i32), _P(_d)],
     "h2_update_cholesky_launch": [_P(_vp), _i32, _P(_i32), _P(_i64), _P(_i32), _P(_vp), _P(_i64), _P(_vp),
@@ -425,6 +427,16 @@ def _update_arrays(mats, updates):
             (_i64 * nu)(*[int(b) for b, _, _ in flat]), (_i32 * nu)(*[int(X.shape[1]) for _, X, _ in flat]),
             (_vp * nu)(*[_ptr(X) for _, X, _ in flat]), (_i64 * nu)(*[ld(X) for _, X, _ in flat]),
             (_vp * nu)(*[_ptr(Y) for _, _, Y in flat]), (_i64 * nu)(*[ld(Y) for _, _, Y in flat]))
+
+
+def h2_lowrank_update_accumulated(m: Mat, updates, tr: h2_trunc) -> int:
+    """updates: list of (block, X, Y) as for h2_lowrank_update, merged into
+    one local update; returns the merged block."""
+    _, _, blocks, ks, Xs, ldx, Ys, ldy = _update_arrays([m], [updates])
+    mb = _i64()
+    _check(_lib.h2_lowrank_update_accumulated(m.h, len(updates), blocks, ks, Xs, ldx, Ys, ldy, C.byref(tr),
+                                              C.byref(mb)))
+    return mb.value
 
 
 def h2_lowrank_update_batched(mats, updates, tr: h2_trunc, check: bool = True):
