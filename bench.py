@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--precond", choices=("substitution", "inverse"), default="substitution",
                     help="preconditioner: substitutions with the factor L, or products with "
                          "G ~ L^{-1} formed by the triangular inversion after the factorisation")
+    ap.add_argument("--accumulate", action="store_true",
+                    help="accumulated updates: the temporaries of a product target in as few local updates "
+                         "as the update rank allows")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape of the substitutions (no autotuning)")
     ap.add_argument("--tune-cache", type=str, default=None,
@@ -108,7 +111,7 @@ def measured_traffic(args):
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), for the
     default workload only; None otherwise or when the summary is absent."""
     default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
-               and args.sigma_seed == "10" and args.precision == "fp64")
+               and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate)
     if not default:
         return None
     try:
@@ -145,7 +148,7 @@ def measured_step_roofline(args):
     committed device-counter summary: algorithmic flops and bytes of each
     step over the wall time of its stage; None for other workloads."""
     default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
-               and args.sigma_seed == "10" and args.precision == "fp64")
+               and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate)
     if not default:
         return None
     steps = []
@@ -487,7 +490,8 @@ def bench_bem(args):
                                f"Galerkin BEM, n={n} panels, bisection cluster tree leaf 32, eta {args.eta:g}, "
                                f"H2(A) by local updates of the far-field blocks, block-relative eps {eps:.3g}, "
                                f"H2-Cholesky + PCG (dense A) 1 Gaussian RHS to {args.rtol}",
-                   "n": n, "precision": args.precision, "parallelism": "1 GPU"},
+                   "n": n, "precision": args.precision, "accumulate": bool(args.accumulate),
+                   "parallelism": "1 GPU"},
         "setup_s": setup, "solve_s": solve, "solves_per_s": 1.0 / solve, "pcg_iters": iters,
         "true_relres": float(np.linalg.norm(p["b"] - A @ xr) / np.linalg.norm(p["b"])),
         "mem_per_dof_kb": stored * 8.0 / n / 1024.0, "max_rank": [kr, kc],
@@ -621,7 +625,7 @@ def main():
     csr = h2lr.h2_csr_create(ctx, p["A"])
     b = torch.tensor(p["b"], device="cuda")
     x = torch.zeros_like(b)
-    tr = h2lr.trunc(args.eps, "block_rel", 32, precision=args.precision)
+    tr = h2lr.trunc(args.eps, "block_rel", 32, precision=args.precision, accumulate=args.accumulate)
 
     inverse = args.precond == "inverse"
     inv_info = {}
@@ -707,9 +711,11 @@ def main():
                                   ", geometric-bisection")
                                + f" cluster tree leaf 32, eta {args.eta:g}, "
                                f"block-relative eps {args.eps}, H2-Cholesky"
+                               + (" (accumulated updates)" if args.accumulate else "")
                                + (" + triangular inverse" if inverse else "")
                                + f" + PCG 1 Gaussian RHS to {args.rtol}",
-                   "n": n, "precision": args.precision, "parallelism": "1 GPU"},
+                   "n": n, "precision": args.precision, "accumulate": bool(args.accumulate),
+                   "parallelism": "1 GPU"},
         "setup_s": setup_s,
         "cholesky_s": chol_s,
         "inverse_s": (setup_s - chol_s) if inverse else None,

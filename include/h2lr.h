@@ -71,12 +71,20 @@ typedef struct h2_job_s *h2_job;
  * float operands and accumulate in float on the matrix cores; QR, SVD,
  * weights, nearfield and all vector solves stay FP64 (results stored FP64).
  * H2_PREC_MIXED_BF16 (a trial): as H2_PREC_MIXED, and every new leaf basis
- * is stored rounded to bfloat16 precision. */
+ * is stored rounded to bfloat16 precision.  accumulate (products, hence
+ * Cholesky, LR and the triangular inverse): 0 = every temporary low-rank
+ * matrix of an admissible product target (one per pair of sons, Section 6)
+ * is added by its own local update; 1 = accumulated updates: the
+ * temporaries of one target are concatenated, in order, into as few local
+ * updates as the update rank H2_MAX_UPDATE_RANK allows (greedy), so fewer
+ * recompressions run (a truncation strategy of the kind named at the end of
+ * Section 4; it changes the truncation sequence). */
 typedef struct {
   double eps;
   int32_t mode;
   int32_t rank_cap;
   int32_t precision;
+  int32_t accumulate;
 } h2_trunc;
 #define H2_PREC_FP64 0
 #define H2_PREC_MIXED 1

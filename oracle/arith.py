@@ -111,6 +111,39 @@ class RkTemp:
         self.U, self.V = _rk_truncate(np.hstack([self.U, Ue]), np.hstack([self.V, Ve]), tp)
 
 
+MAX_UPDATE_RANK = 32     # columns of one local update factor
+
+
+def flush_temps(ct, bZ: int, t: int, r: int, temps, tp: TruncParams, add):
+    """Add the temporaries of an admissible product target Z|_(t, r) (one per
+    pair of sons, each placed at its rows of t and r) by local updates: one
+    update each, in pair order; or, with tp.accumulate, consecutive
+    temporaries concatenated while their total rank stays within
+    MAX_UPDATE_RANK, one local update per group."""
+    placed = []
+    for tm in temps:
+        U = np.zeros((int(ct.size[t]), tm.U.shape[1]))
+        V = np.zeros((int(ct.size[r]), tm.V.shape[1]))
+        a = int(ct.offset[tm.t] - ct.offset[t])
+        c = int(ct.offset[tm.r] - ct.offset[r])
+        U[a:a + tm.U.shape[0]] = tm.U
+        V[c:c + tm.V.shape[0]] = tm.V
+        placed.append((U, V))
+    if not getattr(tp, "accumulate", False):
+        for U, V in placed:
+            add(bZ, U, V)
+        return
+    i = 0
+    while i < len(placed):
+        j, kt = i, 0
+        while j < len(placed) and kt + placed[j][0].shape[1] <= MAX_UPDATE_RANK:
+            kt += placed[j][0].shape[1]
+            j += 1
+        j = max(j, i + 1)
+        add(bZ, np.hstack([u for u, _ in placed[i:j]]), np.hstack([v for _, v in placed[i:j]]))
+        i = j
+
+
 class _Chol:
     def __init__(self, L: H2Matrix, tp: TruncParams, stats: dict | None):
         assert L.lower
@@ -165,15 +198,7 @@ class _Chol:
                 temps = {p: RkTemp(ct, p[0], p[1]) for p in pairs}
                 for (t2, s2, r2) in triples:
                     self.mm(t2, s2, r2, alpha, temps[(t2, r2)])
-                for p in pairs:
-                    tm = temps[p]
-                    U = np.zeros((int(ct.size[t]), tm.U.shape[1]))
-                    V = np.zeros((int(ct.size[r]), tm.V.shape[1]))
-                    a = int(ct.offset[p[0]] - ct.offset[t])
-                    c = int(ct.offset[p[1]] - ct.offset[r])
-                    U[a:a + tm.U.shape[0]] = tm.U
-                    V[c:c + tm.V.shape[0]] = tm.V
-                    self._addlr(bZ, U, V)
+                flush_temps(ct, bZ, t, r, [temps[p] for p in pairs], self.tp, self._addlr)
             return
         # Case 2: at least one factor is a leaf -> low-rank emission
         cache = {}
@@ -303,15 +328,7 @@ class _Chol:
                 temps = {p: RkTemp(ct, p[0], p[1]) for p in pairs}
                 for (t2, s2, r2) in triples:
                     self.mm_n(t2, s2, r2, alpha, temps[(t2, r2)])
-                for p in pairs:
-                    tm = temps[p]
-                    U = np.zeros((int(ct.size[t]), tm.U.shape[1]))
-                    V = np.zeros((int(ct.size[r]), tm.V.shape[1]))
-                    a = int(ct.offset[p[0]] - ct.offset[t])
-                    c = int(ct.offset[p[1]] - ct.offset[r])
-                    U[a:a + tm.U.shape[0]] = tm.U
-                    V[c:c + tm.V.shape[0]] = tm.V
-                    self._addlr(bZ, U, V)
+                flush_temps(ct, bZ, t, r, [temps[p] for p in pairs], self.tp, self._addlr)
             return
         cache = {}
         if bt.kind[bY] == ADM:          # Y = V_s S W_r^*

@@ -49,10 +49,17 @@ class TruncParams:
     matrix (the usual numerical rank): they are indistinguishable from zero
     and their singular vectors are not determined by the data.
     rank_cap: an update that would create a rank above this raises.
+    accumulate: in products (hence Cholesky, LR, triangular inverse), add the
+        temporaries of one admissible target by accumulated updates: the
+        temporaries, in pair order, are concatenated into as few local
+        updates as the update rank MAX_UPDATE_RANK allows (greedy) instead
+        of one update each (a truncation strategy of the kind named at the
+        end of Section 4; a reading).
     """
     eps: float = 1e-6
     mode: str = "block_rel"
     rank_cap: int = 64
+    accumulate: bool = False
 
     def tau(self, sig: np.ndarray) -> float:
         if self.mode == "block_rel":

@@ -47,7 +47,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .arith import RkTemp
+from .arith import RkTemp, flush_temps
 from .h2 import H2Matrix, TruncParams, block_apply, block_dense, to_dense
 from .trees import ADM, INNER, NEAR
 from .update import addlr
@@ -101,15 +101,7 @@ class _Prod:
                 temps = {p: RkTemp(ct, p[0], p[1]) for p in pairs}
                 for (t2, s2, r2) in triples:
                     self.mm(t2, s2, r2, alpha, temps[(t2, r2)])
-                for p in pairs:
-                    tm = temps[p]
-                    U = np.zeros((int(ct.size[t]), tm.U.shape[1]))
-                    V = np.zeros((int(ct.size[r]), tm.V.shape[1]))
-                    a = int(ct.offset[p[0]] - ct.offset[t])
-                    c = int(ct.offset[p[1]] - ct.offset[r])
-                    U[a:a + tm.U.shape[0]] = tm.U
-                    V[c:c + tm.V.shape[0]] = tm.V
-                    self._addlr(bZ, U, V)
+                flush_temps(ct, bZ, t, r, [temps[p] for p in pairs], self.tp, self._addlr)
             return
         cx, cy = {}, {}
         if bt.kind[bY] == ADM:

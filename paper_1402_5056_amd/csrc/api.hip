@@ -647,7 +647,7 @@ struct Planner {
               while (pairs[p].first != t2 || pairs[p].second != r2) ++p;
               mm(t2, s2, r2, alpha, p, t2, r2);
             }
-        for (size_t p = 0; p < pairs.size(); ++p) addlr(bZ, TU((int)p), TV((int)p));
+        emit(OP_ADDLR_ACC, bZ, (int)pairs.size());
       }
       return;
     }
@@ -742,7 +742,7 @@ struct Planner {
               while (pairs[p].first != t2 || pairs[p].second != r2) ++p;
               mm_n(t2, s2, r2, alpha, p, t2, r2);
             }
-        for (size_t p = 0; p < pairs.size(); ++p) addlr(bZ, TU((int)p), TV((int)p));
+        emit(OP_ADDLR_ACC, bZ, (int)pairs.size());
       }
       return;
     }
@@ -999,13 +999,15 @@ static void upload_tasks_reuse(TaskList &tl, const std::vector<Task> &tasks, con
 }
 
 static void set_trunc(h2_mat_s &m, const h2_trunc *tr) {
-  if (!tr) { m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; m.env.prec = 0; return; }
+  if (!tr) { m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; m.env.prec = 0; m.env.acc = 0; return; }
   REQUIRE(tr->mode >= 0 && tr->mode <= 2, "truncation mode must be 0, 1 or 2");
   REQUIRE(tr->rank_cap >= 1 && tr->rank_cap <= KC, "rank_cap must be in [1, H2_MAX_RANK]");
   REQUIRE(tr->eps >= 0.0 && std::isfinite(tr->eps), "eps must be finite and >= 0");
   REQUIRE(tr->precision == H2_PREC_FP64 || tr->precision == H2_PREC_MIXED || tr->precision == H2_PREC_MIXED_BF16,
           "precision must be 0, 1 or 2");
+  REQUIRE(tr->accumulate == 0 || tr->accumulate == 1, "accumulate must be 0 or 1");
   m.env.eps = tr->eps; m.env.mode = tr->mode; m.env.rank_cap = tr->rank_cap; m.env.prec = tr->precision;
+  m.env.acc = tr->accumulate;
 }
 
 static bool g_lds_attr_set = false;

@@ -47,6 +47,7 @@ enum Op : int {
   OP_NEG,            // i0 aux offset, i1 count        negate the stored leaf blocks listed in aux
   OP_NEAR_TRMUL,     // i0 near block, i1 diagonal leaf block, i2 side   N <- tril(N_cc) N (0) or N tril(N_cc) (1)
   OP_GETRF,          // i0 diagonal leaf block, i1 cluster   LR of the leaf without pivoting
+  OP_ADDLR_ACC,      // i0 block, i1 temporaries (pairs T0..T3)  add them: one update each, or accumulated
 };
 
 // Which triangle of a diagonal leaf a solve uses.  TRI_CHOL: the Cholesky
@@ -69,7 +70,7 @@ struct DevEnv {
   int rank_cap, mode;              // truncation
   double eps;
   int prec;                        // 0: FP64 products; 1: coupling/transfer products in FP32
-  int pad_prec;
+  int acc;                         // 1: accumulate the temporaries of a product target
   // cluster tree
   const int *offset, *size, *son0, *son1, *parent, *level;
   const int *desc_lo, *desc_hi;    // nc x nlev: descendants of t at level l = [lo, hi)

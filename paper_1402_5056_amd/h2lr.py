@@ -57,7 +57,8 @@ class H2Error(RuntimeError):
 
 
 class h2_trunc(C.Structure):
-    _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32)]
+    _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32),
+                ("accumulate", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -150,9 +151,9 @@ PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 
 
 def trunc(eps: float = 1e-4, mode: str = "block_rel", rank_cap: int = MAX_RANK,
-          precision: str = "fp64") -> h2_trunc:
+          precision: str = "fp64", accumulate: bool = False) -> h2_trunc:
     return h2_trunc(float(eps), MODES[mode] if isinstance(mode, str) else int(mode), int(rank_cap),
-                    PRECISIONS[precision] if isinstance(precision, str) else int(precision))
+                    PRECISIONS[precision] if isinstance(precision, str) else int(precision), int(bool(accumulate)))
 
 
 _LIVE = weakref.WeakSet()
@@ -330,7 +331,7 @@ def h2_mat_flops(m: Mat, reset: bool = False) -> float:
 
 OPS = ["", "addlr", "expand", "bapply", "rmul_s", "copy_near", "ident", "near_add", "temp_init",
        "temp_add", "potrf", "trsm", "trsv", "sub", "copy", "sv_zero", "sv_push", "sv_leaf", "sv_cross",
-       "sv_up"]
+       "sv_up", "trtri", "trmv", "neg", "near_trmul", "getrf", "addlr_temps"]
 STAGES = ["zero-check", "rfactors", "path-weights", "subtree-weights", "recompress", "couplings",
           "nearfield", "commit"]
 

@@ -23,7 +23,8 @@ CHILD = textwrap.dedent(r'''
     lib.h2_last_error.restype = C.c_char_p
 
     class trunc(C.Structure):
-        _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32)]
+        _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32),
+                    ("accumulate", C.c_int32)]
 
     def ok(st):
         assert st == 0, lib.h2_last_error()

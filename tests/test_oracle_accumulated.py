@@ -11,7 +11,11 @@ strategies, last paragraph of Section 4; the grouping is a reading).
 * With truncation every admissible block stays within the blockwise
   relative bound of the exact sum, and the error falls with eps.
 * A planted misplacement of the merged factor's rows (rolled by one row)
-  breaks the exactness pin."""
+  breaks the exactness pin.
+* In products (Cholesky): accumulated temporaries (TruncParams.accumulate)
+  keep the exact factor without truncation with fewer updates, keep the
+  O(eps) accuracy and the PCG count with truncation, and group by rank as
+  stated."""
 import numpy as np
 import pytest
 
@@ -135,3 +139,73 @@ def test_planted_misplacement_fails(sq32, monkeypatch):
     ups = _updates(ct, bt, group, 40)
     addlr_accumulated(Z, ups, TruncParams(0.0, "none", 1000))
     assert _rel2(to_dense(Z), _dense_sum(ct, bt, D0, ups)) > 1e-3
+
+
+# ------------------------------------------------ accumulated updates in products
+
+def _chol_setup(N, sigma_seed, leaf=32):
+    p = w.problem(N, sigma_seed=sigma_seed, rhs_seed=5)
+    ct = build_cluster_tree(p["coords"], leaf)
+    return p, ct, build_block_tree(ct, 2.0)
+
+
+def test_accumulated_cholesky_exact():
+    """Without truncation the Cholesky factor with accumulated updates is
+    LAPACK's, as with one update per temporary, and fewer updates run."""
+    from oracle.arith import cholesky
+    p, ct, bt = _chol_setup(24, 3, leaf=8)
+    Ap = p["A"].toarray()[ct.perm][:, ct.perm]
+    Lref = np.linalg.cholesky(Ap)
+    calls = {}
+    for acc in (False, True):
+        st = {}
+        L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(0.0, "none", 1000, accumulate=acc), st)
+        assert _rel2(np.tril(to_dense(L)), Lref) < 1e-12
+        calls[acc] = st["addlr_done"]
+    assert calls[True] < calls[False]
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_accumulated_cholesky_truncated(eps):
+    """With truncation: ||A - L L^*|| / ||A|| = O(eps) as for one update per
+    temporary, and PCG keeps its iteration count within one."""
+    from oracle.arith import cholesky, precond_apply
+    from oracle.solve import pcg
+    p, ct, bt = _chol_setup(32, 3)
+    Ap = p["A"].toarray()[ct.perm][:, ct.perm]
+    its = {}
+    for acc in (False, True):
+        L = cholesky(from_csr(p["A"], ct, bt, lower=True), TruncParams(eps, "block_rel", 32, accumulate=acc))
+        D = np.tril(to_dense(L))
+        assert np.linalg.norm(Ap - D @ D.T, 2) / np.linalg.norm(Ap, 2) < 50 * eps
+        _, its[acc], rel = pcg(p["A"], p["b"], lambda v: precond_apply(L, v))
+        assert rel <= 1e-8
+    assert abs(its[True] - its[False]) <= 1
+
+
+def test_flush_groups_by_rank():
+    """The grouping rule: consecutive temporaries while the total rank stays
+    within MAX_UPDATE_RANK, greedy in pair order (ranks 20, 10, 5, 30 give
+    the groups {20, 10}, {5}, {30}), each group one update with the
+    concatenated factors, whose sum equals that of one update each."""
+    from oracle.arith import MAX_UPDATE_RANK, RkTemp, flush_temps
+    assert MAX_UPDATE_RANK == 32
+    p, ct, bt = _chol_setup(32, None)
+    t = int(ct.son0[0]); r = t
+    sons = ct.sons(t)
+    temps = []
+    for i, (k, (a, b)) in enumerate(zip((20, 10, 5, 30), [(sons[0], sons[0]), (sons[0], sons[1]),
+                                                           (sons[1], sons[0]), (sons[1], sons[1])])):
+        tm = RkTemp(ct, a, b)
+        tm.U = w.gaussian(int(ct.size[a]), k, 60 + i)
+        tm.V = w.gaussian(int(ct.size[b]), k, 70 + i)
+        temps.append(tm)
+    got = []
+    flush_temps(ct, 7, t, r, temps, TruncParams(1e-6, "block_rel", 32, accumulate=True),
+                lambda b, U, V: got.append((b, U.shape[1], U @ V.T)))
+    assert [g[1] for g in got] == [30, 5, 30]
+    total = sum(g[2] for g in got)
+    one = []
+    flush_temps(ct, 7, t, r, temps, TruncParams(1e-6, "block_rel", 32),
+                lambda b, U, V: one.append(U @ V.T))
+    assert len(one) == 4 and np.allclose(total, sum(one), atol=1e-12)
