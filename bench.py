@@ -127,6 +127,7 @@ def measured_traffic(args):
 STAGES_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_stages.md")
 MIXED_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_mixed.md")
 TARGET_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_512_sigma.md")
+ACCUMULATED_PROFILE = os.path.join(ROOT, "profiles", "k_interp_p1_square_256_sigma_accumulated.md")
 
 
 def recorded(path, keys):
@@ -750,9 +751,10 @@ def main():
         out["inverse_mem_per_dof_kb"] = g_stored * 8.0 / n / 1024.0
         out["inverse_max_rank"] = [g_kr, g_kc]
     if measured_step_roofline(args) is not None:
-        # the other halves of the metric, recorded by committed runs of this
-        # build (not timed here): the mixed-precision form of this workload,
-        # and the 511^2 workload whose steps do not fit the run's time limit
+        # the other halves of the metric, read from committed measurement
+        # summaries (not timed here): the mixed-precision and the accumulated
+        # forms of this workload, and the 511^2 workload (about two minutes
+        # per step)
         mixed = recorded(MIXED_PROFILE, ("mixed_setup_s", "mixed_solve_s", "mixed_pcg_iters", "fp64_setup_s",
                                          "mixed_vs_fp64_factor_rel2"))
         if mixed:
@@ -760,6 +762,10 @@ def main():
         target = recorded(TARGET_PROFILE, ("target_setup_s", "target_solve_s", "target_pcg_iters", "target_n"))
         if target:
             out["target_511sq_recorded"] = dict(target, source=os.path.relpath(TARGET_PROFILE, ROOT))
+        acc = recorded(ACCUMULATED_PROFILE, ("accumulated_setup_s", "accumulated_solve_s", "accumulated_pcg_iters",
+                                             "plain_setup_s", "plain_solve_s"))
+        if acc:
+            out["accumulated_recorded"] = dict(acc, source=os.path.relpath(ACCUMULATED_PROFILE, ROOT))
     if args.precision != "fp64":
         # error of the mixed-precision factor against the FP64 factor of the
         # same matrix (not part of the timed steps): 20 power iterations on

@@ -19,7 +19,7 @@ def hipcc_command(out=LIB, arch="gfx950"):
 
 
 def build(verbose=True, out=LIB):
-    """Always recompiles (the build check must exercise the compiler)."""
+    """Always recompiles, also when a built library is present."""
     cmd = hipcc_command(out + ".tmp")
     if verbose:
         print(" ".join(cmd), flush=True)
