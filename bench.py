@@ -316,12 +316,17 @@ def bench_batch(args):
             h2lr.h2_mat_assign(q["U"], q["U0"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
         if args.batch_updates > 0:     # updates and factorisations, one launch
             job = h2lr.h2_update_cholesky_launch(umats, [q["ups"] for q in probs], mats, tr)
         else:
             job = h2lr.h2_cholesky_launch(mats, tr)
+        ev[1].record(stream)
         job.finish()
         t1 = time.perf_counter()
+        launch["ms"].append(ev[0].elapsed_time(ev[1]))
+        launch["flops"].append(sum(h2lr.h2_mat_flops(m, reset=True) for m in mats + umats))
         # all systems in lockstep, preconditioner applications in one launch
         # (the solver clears x itself)
         its, _, _ = h2lr.h2_pcg_batched([q["csr"] for q in probs], mats, [q["b"] for q in probs],
@@ -330,9 +335,11 @@ def bench_batch(args):
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1, its
 
+    launch = {"ms": [], "flops": []}
     for i in range(args.warmup):
         step()
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
+    launch = {"ms": [], "flops": []}
     setup, solve, iters = [], [], None
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -396,6 +403,16 @@ def bench_batch(args):
         "pcg_iters": iters,
         "worst_true_relres": worst,
     }
+    if launch["ms"]:
+        # the batched launch: algorithmic flops of every matrix's task list
+        # (device-counted) over the event-timed launch on the batch's stream
+        lms = float(np.median(launch["ms"]))
+        lfl = float(np.median(launch["flops"]))
+        out["roofline"] = {"bound": "alu", "kernel": "k_interp_batch (one workgroup per problem, one launch)",
+                           "achieved": lfl / (lms * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": lfl / (lms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                           "traffic": None, "flops_per_launch": lfl, "launch_ms": lms,
+                           "workgroups": len(mats) + (len(umats) if args.batch_updates > 0 else 0)}
     print(json.dumps(out), flush=True)
 
 
@@ -619,11 +636,25 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = h2lr.h2_ctx_create(0, stream.cuda_stream)
     build_tree = h2lr.h2_ctree_build_dd if args.cluster == "dd" else h2lr.h2_ctree_build
+    # preparation, timed apart from the steps: trees, H^2(A) (nearfield
+    # leaves from the CSR matrix), the sparse matrix for PCG
+    prep = {}
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
     ct = build_tree(ctx, p["coords"], 32)
+    prep["cluster_tree_s"] = time.perf_counter() - tp0
+    tp0 = time.perf_counter()
     bt = h2lr.h2_btree_build(ctx, ct, args.eta)
+    prep["block_tree_s"] = time.perf_counter() - tp0
+    tp0 = time.perf_counter()
     A0 = h2lr.h2_mat_from_csr(ctx, bt, p["A"], lower=True)
+    torch.cuda.synchronize()
+    prep["h2_from_csr_s"] = time.perf_counter() - tp0
     L = h2lr.h2_mat_copy(A0)
+    tp0 = time.perf_counter()
     csr = h2lr.h2_csr_create(ctx, p["A"])
+    torch.cuda.synchronize()
+    prep["csr_upload_s"] = time.perf_counter() - tp0
     b = torch.tensor(p["b"], device="cuda")
     x = torch.zeros_like(b)
     tr = h2lr.trunc(args.eps, "block_rel", 32, precision=args.precision, accumulate=args.accumulate)
@@ -718,13 +749,16 @@ def main():
                    "n": n, "precision": args.precision, "accumulate": bool(args.accumulate),
                    "parallelism": "1 GPU"},
         "setup_s": setup_s,
+        "setup_min_s": float(np.min(setup_ms)) / 1e3,
         "cholesky_s": chol_s,
         "inverse_s": (setup_s - chol_s) if inverse else None,
         "precond": args.precond,
         "precond_threads": tune[0] if tune else None,
         "precond_ms_by_threads": ({str(k): v for k, v in tune[3].items()} or None) if tune else None,
         "solve_s": float(np.median(solve_ms)) / 1e3,
+        "solve_min_s": float(np.min(solve_ms)) / 1e3,
         "solves_per_s": 1e3 / float(np.median(solve_ms)),
+        "prep_s": prep,
         "pcg_iters": iters,
         "true_relres": true_rel,
         "step_p50_ms": float(np.percentile(step_ms, 50)),

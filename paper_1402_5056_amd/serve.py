@@ -18,7 +18,8 @@ Scheduling (host side only; every numerical step runs in the h2lr library):
 * completion: a finished launch is checked, and all right-hand sides of its
   requests are solved by one batched PCG (``h2_pcg_batched``: one CG
   iteration per column; per iteration the preconditioner applications of
-  all requests, all columns of a request at once, in one launch);
+  all requests, all columns of a request at once, in one launch; by default
+  the iteration is captured once as a HIP graph and replayed);
 * release: a request's device memory returns to the budget as soon as its
   own results are back ("eager", the default): the library frees matrix
   memory in stream order (hipFreeAsync on the matrix's stream), so a release
@@ -70,7 +71,7 @@ class Request:
 class Server:
     def __init__(self, budget_bytes: int, eps: float = 1e-4, eta: float = 2.0, leaf: int = 32,
                  rtol: float = 1e-8, maxit: int = 500, slots: int = 2, max_batch: int = 32,
-                 device: int = 0, release: str = "eager"):
+                 device: int = 0, release: str = "eager", pcg_graph: bool = True):
         self.budget = int(budget_bytes)
         self.tr = h2lr.trunc(eps, "block_rel", 32)
         self.eta, self.leaf, self.rtol, self.maxit = eta, leaf, rtol, maxit
@@ -86,6 +87,7 @@ class Server:
         if release not in ("idle", "eager"):
             raise ValueError("release must be 'idle' or 'eager'")
         self.release = release
+        self.pcg_graph = pcg_graph     # batched PCG iterations replayed from a captured HIP graph
         self.release_s = 0.0           # host time spent freeing device memory
 
     # ------------------------------------------------------------ helpers
@@ -123,7 +125,7 @@ class Server:
             xs = [torch.zeros_like(b) for b in bs]
             stream.synchronize()
             its, _, codes = h2lr.h2_pcg_batched([r._csr for r in reqs], [r._L for r in reqs], bs, xs,
-                                                self.rtol, self.maxit, check=False)
+                                                self.rtol, self.maxit, check=False, graph=self.pcg_graph)
             pos = 0
             for r, x in zip(reqs, xs):
                 k = r.B.shape[1]
