@@ -97,7 +97,7 @@ class _FakeLib:
                 return [0] * len(mats)
         return Job()
 
-    def h2_pcg_batched(self, csrs, mats, bs, xs, rtol, maxit, check=True):
+    def h2_pcg_batched(self, csrs, mats, bs, xs, rtol, maxit, check=True, graph=False):
         its = []
         for c, b, x in zip(csrs, bs, xs):
             B = b.a.reshape(-1, c.A.shape[0])
