@@ -911,48 +911,51 @@ __device__ void task_addlr(const DevEnv &e, const Lds &L, double *lds, int b0, i
   }
 }
 
-// The temporaries T0..T(np-1) of an admissible product target b0 (each the
-// truncated sum of the son-pair products, on the rows of t and r) enter the
-// matrix by local updates: one each, in order (e.acc == 0), or accumulated:
-// consecutive temporaries are concatenated into the update buffers while the
-// total rank stays within KPMAX, one local update per group.
-__device__ void task_addlr_acc(const DevEnv &e, const Lds &L, double *lds, int b0, int np) {
-  if (!e.acc) {
-    for (int p = 0; p < np; ++p) {
-      task_addlr(e, L, lds, b0, B_T0U + 2 * p, B_T0V + 2 * p);
+// OP_ADDLR (one local update with the factors in buffers i1, i2) and
+// OP_ADDLR_ACC: the temporaries T0..T(np-1) of an admissible product target
+// (each the truncated sum of the son-pair products, on the rows of t and r)
+// enter the matrix by local updates, one each in order (e.acc == 0), or
+// accumulated: consecutive temporaries are concatenated into the update
+// buffers while the total rank stays within KPMAX, one update per group.
+// One call site of task_addlr for both (a second inlined copy of the update
+// enlarges the interpreter's stack frame).
+__device__ void task_addlr_tk(const DevEnv &e, const Lds &L, double *lds, const Task &tk) {
+  const int b0 = tk.i[0];
+  const bool temps = tk.op == OP_ADDLR_ACC;
+  const int np = temps ? tk.i[1] : 1;
+  const int t = e.brow[b0], r = e.bcol[b0];
+  for (int p = 0; p < np;) {
+    int q = p + 1;
+    int bx = temps ? B_T0U + 2 * p : tk.i[1], by = temps ? B_T0V + 2 * p : tk.i[2];
+    if (temps && e.acc) {
+      int kt = e.bcols[B_T0U + 2 * p];
+      while (q < np && kt + e.bcols[B_T0U + 2 * q] <= KPMAX) kt += e.bcols[B_T0U + 2 * q++];
+      if (q > p + 1) {
+        int c0 = 0;
+        for (int j = p; j < q; ++j) {
+          const int kj = e.bcols[B_T0U + 2 * j];
+          for (int side = 0; side < 2; ++side) {
+            const int c = side == 0 ? t : r;
+            const MV src = bufrows(e, (side == 0 ? B_T0U : B_T0V) + 2 * j, c);
+            const MV dst = bufrows(e, side == 0 ? B_U : B_V, c);
+            const int rows = e.size[c];
+            for (int x = threadIdx.x; x < rows * kj; x += blockDim.x)
+              dst(x % rows, c0 + x / rows) = src(x % rows, x / rows);
+          }
+          c0 += kj;
+        }
+        if (threadIdx.x == 0) { e.bcols[B_U] = kt; e.bcols[B_V] = kt; }
+        __syncthreads();
+        bx = B_U;
+        by = B_V;
+      }
+    }
+    task_addlr(e, L, lds, b0, bx, by);
+    p = q;
+    if (p < np) {
       __syncthreads();
       if (e.err[0] != 0) return;
     }
-    return;
-  }
-  const int t = e.brow[b0], r = e.bcol[b0];
-  int p = 0;
-  while (p < np) {
-    int q = p, kt = 0;
-    while (q < np && kt + e.bcols[B_T0U + 2 * q] <= KPMAX) kt += e.bcols[B_T0U + 2 * q++];
-    if (q == p) kt = e.bcols[B_T0U + 2 * q++];   // (a temporary never exceeds KPMAX)
-    if (q == p + 1) {
-      task_addlr(e, L, lds, b0, B_T0U + 2 * p, B_T0V + 2 * p);
-    } else {
-      int c0 = 0;
-      for (int j = p; j < q; ++j) {
-        const int kj = e.bcols[B_T0U + 2 * j];
-        for (int side = 0; side < 2; ++side) {
-          const int c = side == 0 ? t : r;
-          const MV src = bufrows(e, (side == 0 ? B_T0U : B_T0V) + 2 * j, c);
-          const MV dst = bufrows(e, side == 0 ? B_U : B_V, c);
-          const int rows = e.size[c];
-          for (int x = threadIdx.x; x < rows * kj; x += blockDim.x) dst(x % rows, c0 + x / rows) = src(x % rows, x / rows);
-        }
-        c0 += kj;
-      }
-      if (threadIdx.x == 0) { e.bcols[B_U] = kt; e.bcols[B_V] = kt; }
-      __syncthreads();
-      task_addlr(e, L, lds, b0, B_U, B_V);
-    }
-    __syncthreads();
-    if (e.err[0] != 0) return;
-    p = q;
   }
 }
 
@@ -1756,7 +1759,8 @@ __device__ __forceinline__ void interp_run(const Task *__restrict__ tasks, int n
     const DevEnv &e = env[tk.env];
     const unsigned long long t0 = e.prof ? wall_clock64() : 0ull;
     switch (tk.op) {
-      case OP_ADDLR: task_addlr(e, L, lds_raw, tk.i[0], tk.i[1], tk.i[2]); break;
+      case OP_ADDLR:
+      case OP_ADDLR_ACC: task_addlr_tk(e, L, lds_raw, tk); break;
       case OP_EXPAND: task_expand(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_BAPPLY: {
         task_bapply(e, L, tk.i[0], tk.i[1], tk.i[2], tk.i[3], tk.alpha, tk.beta);
@@ -1790,7 +1794,6 @@ __device__ __forceinline__ void interp_run(const Task *__restrict__ tasks, int n
       case OP_TRSM: task_trsm(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_TRSV: task_trsv(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_GETRF: task_getrf(e, L, tk.i[0], tk.i[1]); break;
-      case OP_ADDLR_ACC: task_addlr_acc(e, L, lds_raw, tk.i[0], tk.i[1]); break;
       case OP_SUB: task_sub(e, tk.i[0], tk.i[1], tk.i[2], tk.i[3]); break;
       case OP_COPY: task_copy(e, tk.i[0], tk.i[1], tk.i[2]); break;
       case OP_SV_ZERO: task_sv_zero(e, tk.i[0], tk.i[1], tk.i[2]); break;
