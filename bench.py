@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--side", type=int, default=256, help="grid side N (n = (N-1)^2)")
+    ap.add_argument("--side", type=int, default=256, help="grid side N (n = (N-1)^2, in 3-D (N-1)^3)")
+    ap.add_argument("--dim", type=int, choices=(2, 3), default=2,
+                    help="2: P1 on the unit square; 3: Q1 on the unit cube (sigma on 4x4x4-cell blocks)")
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--eta", type=float, default=2.0, help="admissibility parameter")
     ap.add_argument("--cluster", choices=("bisection", "dd"), default="bisection",
@@ -110,7 +112,7 @@ def measured_traffic(args):
     """HBM bytes of one factorisation launch from the committed device-counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), for the
     default workload only; None otherwise or when the summary is absent."""
-    default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
+    default = (args.side == 256 and args.dim == 2 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
                and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate)
     if not default:
         return None
@@ -148,7 +150,7 @@ def measured_step_roofline(args):
     """Roofline per update step (a4..a9) of the default workload from the
     committed device-counter summary: algorithmic flops and bytes of each
     step over the wall time of its stage; None for other workloads."""
-    default = (args.side == 256 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
+    default = (args.side == 256 and args.dim == 2 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
                and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate)
     if not default:
         return None
@@ -631,7 +633,7 @@ def main():
     import workloads as w
     from paper_1402_5056_amd import h2lr   # fails loudly if the library is not built
 
-    p = w.problem(args.side, sigma_seed=sigma_seed(args), rhs_seed=11)
+    p = w.problem(args.side, dim=args.dim, sigma_seed=sigma_seed(args), rhs_seed=11)
     n = p["A"].shape[0]
     stream = torch.cuda.current_stream()
     ctx = h2lr.h2_ctx_create(0, stream.cuda_stream)
@@ -736,9 +738,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"P1 FEM unit square {args.side}x{args.side} grid, n={n}, "
+        "config": {"workload": (f"P1 FEM unit square {args.side}x{args.side} grid, n={n}, " if args.dim == 2 else
+                                f"Q1 FEM unit cube {args.side}^3 grid, n={n}, ")
                                + ("sigma = 1" if sigma_seed(args) is None else
-                                  f"sigma 8x8 subdomains log-uniform [1e-2,1e2] seed {args.sigma_seed}")
+                                  (f"sigma 8x8 subdomains" if args.dim == 2 else "sigma 4x4x4-cell blocks")
+                                  + f" log-uniform [1e-2,1e2] seed {args.sigma_seed}")
                                + (", domain-decomposition" if args.cluster == "dd" else
                                   ", geometric-bisection")
                                + f" cluster tree leaf 32, eta {args.eta:g}, "
@@ -850,7 +854,9 @@ def main():
             json.dump({"factorisation": plain(prof), "preconditioner": plain(prof_pre),
                        "units": "seconds of a 100 MHz device clock; (count, seconds) pairs"}, f, indent=1)
         print(f"[bench] device-counter trace written to {args.trace}", file=sys.stderr, flush=True)
-    if args.cpu_baseline:
+    if args.cpu_baseline and args.dim == 3:
+        out["cpu_baseline"] = None          # the bounded oracle sample is 2-D only
+    elif args.cpu_baseline:
         print("[bench] timing the CPU oracle (bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, n)
     print(json.dumps(out), flush=True)
