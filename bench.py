@@ -207,31 +207,60 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(args, n_target: int):
-    """The oracle, one core, timed on complete setup+solve runs of the same
-    workload at smaller grid sides (a bounded sample); ``value`` is the step
-    rate measured at the largest of them.  The estimate for the benchmark
-    size (measured power law over the sample sides) is reported separately
-    and labelled as an extrapolation, next to the oracle time recorded at
-    the benchmark size itself when tests/golden holds it."""
-    import math
+def oracle_runs(args):
+    """Complete setup+solve runs of the oracle (one thread, pinned to one
+    core) at the sample grid sides, one after another; None on a failure."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    try:
+        core = max(os.sched_getaffinity(0))     # away from the launching thread where possible
+    except (AttributeError, OSError):
+        core = 0
     runs = []
     for side in [int(s) for s in args.cpu_sides.split(",") if s]:
         cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker", str(side),
                "--eps", str(args.eps), "--rtol", str(args.rtol), "--eta", str(args.eta),
                "--sigma-seed", args.sigma_seed, "--cluster", args.cluster]
         try:
-            cmd = ["taskset", "-c", "0"] + cmd
-            out = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+            out = subprocess.run(["taskset", "-c", str(core)] + cmd, env=env, capture_output=True, text=True,
+                                 timeout=600)
         except FileNotFoundError:
-            out = subprocess.run(cmd[3:], env=env, capture_output=True, text=True, timeout=600)
+            out = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
         if out.returncode != 0:
             sys.stderr.write(out.stderr[-2000:])
             return None
-        runs.append(json.loads(out.stdout.strip().splitlines()[-1]))
+        runs.append(dict(json.loads(out.stdout.strip().splitlines()[-1]), core=core))
         print(f"[bench] oracle side {side}: setup {runs[-1]['setup_s']:.2f}s "
               f"solve {runs[-1]['solve_s']:.2f}s", file=sys.stderr, flush=True)
+    return runs
+
+
+def start_oracle_runs(args):
+    """Runs oracle_runs on a thread (the oracle works in child processes on
+    one core while the GPU steps run); join with finish_oracle_runs."""
+    import threading
+    box = {}
+    th = threading.Thread(target=lambda: box.update(runs=oracle_runs(args)), daemon=True)
+    th.start()
+    return th, box
+
+
+def finish_oracle_runs(handle):
+    th, box = handle
+    th.join()
+    return box.get("runs")
+
+
+def cpu_baseline(args, n_target: int, runs=None):
+    """The oracle, one core, timed on complete setup+solve runs of the same
+    workload at smaller grid sides (a bounded sample); ``value`` is the step
+    rate measured at the largest of them.  The estimate for the benchmark
+    size (measured power law over the sample sides) is reported separately
+    and labelled as an extrapolation, next to the oracle time recorded at
+    the benchmark size itself when tests/golden holds it.  runs: results of
+    oracle_runs made beforehand (else they are made here)."""
+    import math
+    if runs is None:
+        runs = oracle_runs(args)
     if not runs:
         return None
     tot = [r["setup_s"] + r["solve_s"] for r in runs]
@@ -686,6 +715,9 @@ def main():
         return it, rel
 
     print(f"[bench] n={n}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    # the bounded oracle sample runs in child processes on one core of the
+    # host while the GPU steps run (the launching thread mostly waits)
+    oracle = start_oracle_runs(args) if args.cpu_baseline and args.dim == 2 else None
     for i in range(args.warmup):
         step([torch.cuda.Event(enable_timing=True) for _ in range(4)])
         print(f"[bench] warmup step {i} done", file=sys.stderr, flush=True)
@@ -856,9 +888,12 @@ def main():
         print(f"[bench] device-counter trace written to {args.trace}", file=sys.stderr, flush=True)
     if args.cpu_baseline and args.dim == 3:
         out["cpu_baseline"] = None          # the bounded oracle sample is 2-D only
-    elif args.cpu_baseline:
-        print("[bench] timing the CPU oracle (bounded sample)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args, n)
+    elif oracle is not None:
+        print("[bench] waiting for the CPU oracle sample", file=sys.stderr, flush=True)
+        cb = cpu_baseline(args, n, finish_oracle_runs(oracle))
+        if cb is not None:
+            cb["sample"] += "; run in child processes pinned to one host core while the GPU steps ran"
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
