@@ -98,6 +98,47 @@ def test_update_sequence(lib, eps, mode):
         assert rel2(D, Dref) < TOL, (b, rel2(D, Dref))
 
 
+@pytest.mark.parametrize("mode", ["block_rel", "const_rel"])
+def test_wide_recompression(lib, mode):
+    """Updates of the largest rank (32) on top of existing ranks of about
+    24: the extended bases reach 24 + 32 = 56 columns, so the recompression
+    SVDs are wider than 32 columns (the widest the kernels take is 64),
+    while the result keeps ranks <= 32 (the second update lies in the span
+    of the first up to components below eps).  Global, then on a subdivided
+    block; parity with the oracle after each step."""
+    print(f"case: wide recompression (extended ranks up to 56), {mode}, N=32", flush=True)
+    p, ctx, bt, M, oc, ob = _setup(lib, 32, sigma_seed=6)
+    Z = o_from_csr(p["A"], oc, ob)
+    eps = 1e-6 if mode == "block_rel" else 1e-9
+    tp = TruncParams(eps, mode, 32)
+    tr = lib.trunc(eps, mode, 32)
+    X1 = w.gaussian(oc.n, 24, 61)[oc.perm] * np.logspace(0, -2, 24)
+    Y1 = w.gaussian(oc.n, 24, 62)[oc.perm]
+    G = w.gaussian(24, 20, 63)
+    tiny = 1e-13
+    X2 = np.hstack([X1 @ G, tiny * w.gaussian(oc.n, 12, 64)[oc.perm]])
+    Y2 = np.hstack([Y1 @ w.gaussian(24, 20, 65), w.gaussian(oc.n, 12, 66)[oc.perm]])
+    inner = [b for b in range(ob.nb) if ob.kind[b] == 0 and ob.row[b] != ob.col[b]]
+    b3 = inner[1]
+    t3, s3 = int(ob.row[b3]), int(ob.col[b3])
+    a3, c3 = int(oc.offset[t3]), int(oc.offset[s3])
+    X3 = np.hstack([X1[a3:a3 + int(oc.size[t3])] @ w.gaussian(24, 16, 67),
+                    tiny * w.gaussian(int(oc.size[t3]), 16, 68)])
+    Y3 = np.hstack([Y1[c3:c3 + int(oc.size[s3])] @ w.gaussian(24, 16, 69),
+                    w.gaussian(int(oc.size[s3]), 16, 70)])
+    for b, X, Y in ((0, X1, Y1), (0, X2, Y2), (b3, X3, Y3)):
+        margins = []
+        o_addlr(Z, b, X, Y, tp, margins)
+        if mode == "block_rel" and margins:
+            assert min(margins) > 1e-8, "seed too close to the truncation threshold"
+        lib.h2_lowrank_update(M, b, to_dev_cols(X), to_dev_cols(Y), tr)
+        kr, kc = lib.h2_mat_ranks(M, oc.nc)
+        assert np.array_equal(kr, Z.k[0]) and np.array_equal(kc, Z.k[1])
+        err = rel2(dense_via_matvec(lib, M, oc.n), to_original(o_to_dense(Z), oc.perm))
+        print(f"  block {b}: ranks <= {int(kr.max())}/{int(kc.max())}, vs oracle {err:.2e}", flush=True)
+        assert err < TOL
+
+
 def test_zero_update_skipped(lib):
     torch = gpu()
     p, ctx, bt, M, oc, ob = _setup(lib, 32)
