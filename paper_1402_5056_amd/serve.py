@@ -18,8 +18,8 @@ Scheduling (host side only; every numerical step runs in the h2lr library):
 * completion: a finished launch is checked, and all right-hand sides of its
   requests are solved by one batched PCG (``h2_pcg_batched``: one CG
   iteration per column; per iteration the preconditioner applications of
-  all requests, all columns of a request at once, in one launch; by default
-  the iteration is captured once as a HIP graph and replayed);
+  all requests, all columns of a request at once, in one launch; with
+  pcg_graph the iteration is captured once as a HIP graph and replayed);
 * release: a request's device memory returns to the budget as soon as its
   own results are back ("eager", the default): the library frees matrix
   memory in stream order (hipFreeAsync on the matrix's stream), so a release
@@ -71,7 +71,7 @@ class Request:
 class Server:
     def __init__(self, budget_bytes: int, eps: float = 1e-4, eta: float = 2.0, leaf: int = 32,
                  rtol: float = 1e-8, maxit: int = 500, slots: int = 2, max_batch: int = 32,
-                 device: int = 0, release: str = "eager", pcg_graph: bool = True):
+                 device: int = 0, release: str = "eager", pcg_graph: bool = False):
         self.budget = int(budget_bytes)
         self.tr = h2lr.trunc(eps, "block_rel", 32)
         self.eta, self.leaf, self.rtol, self.maxit = eta, leaf, rtol, maxit
