@@ -49,6 +49,7 @@ class TruncParams:
     matrix (the usual numerical rank): they are indistinguishable from zero
     and their singular vectors are not determined by the data.
     rank_cap: an update that would create a rank above this raises.
+    level_factor: see level_scale (cluster-basis recompression only).
     accumulate: in products (hence Cholesky, LR, triangular inverse), add the
         temporaries of one admissible target by accumulated updates: the
         temporaries, in pair order, are concatenated into as few local
@@ -60,6 +61,20 @@ class TruncParams:
     mode: str = "block_rel"
     rank_cap: int = 64
     accumulate: bool = False
+    level_factor: float = 1.0
+
+    def level_scale(self, level: int, depth: int) -> float:
+        """Variable-order weighting of the cluster-basis recompression (the
+        level-dependent accuracy the last paragraph of Section 4 names, a
+        reading): the threshold of a cluster at level l of a tree of depth p
+        is multiplied by q^(p - l), q = level_factor in (0, 1], so that larger
+        clusters are approximated more accurately (higher rank), as in a
+        variable-order scheme.  q = 1: no change.  Repeated products (not a
+        power function) so that the GPU path can form the same number."""
+        s = 1.0
+        for _ in range(int(depth) - int(level)):
+            s *= self.level_factor
+        return s
 
     def tau(self, sig: np.ndarray) -> float:
         if self.mode == "block_rel":
@@ -70,13 +85,14 @@ class TruncParams:
             return 0.0
         raise ValueError(self.mode)
 
-    def rank(self, sig: np.ndarray, shape: tuple[int, int] | None = None) -> int:
-        """r = min{ r : sigma_{r+1} <= tau } for descending sig; with the
-        matrix shape, tau is at least the rounding level
+    def rank(self, sig: np.ndarray, shape: tuple[int, int] | None = None, scale: float = 1.0) -> int:
+        """r = min{ r : sigma_{r+1} <= tau } for descending sig, tau the
+        mode's threshold times scale (the level scale of the cluster); with
+        the matrix shape, tau is at least the rounding level
         max(m, n) * eps_mach * sigma_1."""
         if len(sig) == 0:
             return 0
-        tau = self.tau(sig)
+        tau = self.tau(sig) * scale
         if shape is not None:
             tau = max(tau, max(shape) * np.finfo(np.float64).eps * sig[0])
         return int(np.count_nonzero(sig > tau))

@@ -190,10 +190,12 @@ def addlr(Z: H2Matrix, b0: int, X: np.ndarray, Y: np.ndarray, tp: TruncParams,
                 Vt = np.vstack([R[side][t1] @ Eext(side, t1), R[side][t2] @ Eext(side, t2)])
             M = Vt @ Bw[side][t].T
             U, sig = svd_left(M)
-            r = tp.rank(sig, M.shape)
+            scale = tp.level_scale(ct.level[t], ct.depth) if getattr(tp, "level_factor", 1.0) != 1.0 else 1.0
+            r = tp.rank(sig, M.shape, scale)
             if margins is not None and len(sig) and tp.mode == "block_rel" and tp.eps > 0:
-                lo = sig[r - 1] / tp.eps - 1.0 if r > 0 else np.inf
-                hi = 1.0 - sig[r] / tp.eps if r < len(sig) else np.inf
+                et = tp.eps * scale
+                lo = sig[r - 1] / et - 1.0 if r > 0 else np.inf
+                hi = 1.0 - sig[r] / et if r < len(sig) else np.inf
                 margins.append(min(lo, hi))
             if r > tp.rank_cap:
                 raise RankCapError(f"rank {r} > cap {tp.rank_cap} at cluster {t}")
