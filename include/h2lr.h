@@ -78,13 +78,19 @@ typedef struct h2_job_s *h2_job;
  * temporaries of one target are concatenated, in order, into as few local
  * updates as the update rank H2_MAX_UPDATE_RANK allows (greedy), so fewer
  * recompressions run (a truncation strategy of the kind named at the end of
- * Section 4; it changes the truncation sequence). */
+ * Section 4; it changes the truncation sequence).  level_factor q in (0, 1]
+ * (0 means 1): variable-order weighting of the cluster-basis recompression,
+ * the threshold of a cluster at level l of a tree of depth p multiplied by
+ * q^(p - l) (formed by repeated products), so larger clusters are kept more
+ * accurately, as in a variable-order scheme (the weighting the end of
+ * Section 4 names; q = 1 changes nothing).  Temporaries are not affected. */
 typedef struct {
   double eps;
   int32_t mode;
   int32_t rank_cap;
   int32_t precision;
   int32_t accumulate;
+  double level_factor;
 } h2_trunc;
 #define H2_PREC_FP64 0
 #define H2_PREC_MIXED 1

@@ -999,15 +999,20 @@ static void upload_tasks_reuse(TaskList &tl, const std::vector<Task> &tasks, con
 }
 
 static void set_trunc(h2_mat_s &m, const h2_trunc *tr) {
-  if (!tr) { m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; m.env.prec = 0; m.env.acc = 0; return; }
+  if (!tr) {
+    m.env.eps = 0.0; m.env.mode = 2; m.env.rank_cap = KC; m.env.prec = 0; m.env.acc = 0; m.env.lvq = 1.0;
+    return;
+  }
   REQUIRE(tr->mode >= 0 && tr->mode <= 2, "truncation mode must be 0, 1 or 2");
   REQUIRE(tr->rank_cap >= 1 && tr->rank_cap <= KC, "rank_cap must be in [1, H2_MAX_RANK]");
   REQUIRE(tr->eps >= 0.0 && std::isfinite(tr->eps), "eps must be finite and >= 0");
   REQUIRE(tr->precision == H2_PREC_FP64 || tr->precision == H2_PREC_MIXED || tr->precision == H2_PREC_MIXED_BF16,
           "precision must be 0, 1 or 2");
   REQUIRE(tr->accumulate == 0 || tr->accumulate == 1, "accumulate must be 0 or 1");
+  REQUIRE(tr->level_factor >= 0.0 && tr->level_factor <= 1.0, "level_factor must be in [0, 1] (0 means 1)");
   m.env.eps = tr->eps; m.env.mode = tr->mode; m.env.rank_cap = tr->rank_cap; m.env.prec = tr->precision;
   m.env.acc = tr->accumulate;
+  m.env.lvq = tr->level_factor == 0.0 ? 1.0 : tr->level_factor;
 }
 
 static bool g_lds_attr_set = false;

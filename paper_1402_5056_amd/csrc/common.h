@@ -71,6 +71,7 @@ struct DevEnv {
   double eps;
   int prec;                        // 0: FP64 products; 1: coupling/transfer products in FP32
   int acc;                         // 1: accumulate the temporaries of a product target
+  double lvq;                      // level factor q of the recompression threshold (1: none)
   // cluster tree
   const int *offset, *size, *son0, *son1, *parent, *level;
   const int *desc_lo, *desc_hi;    // nc x nlev: descendants of t at level l = [lo, hi)

@@ -594,7 +594,12 @@ __device__ int wv_recompress(const DevEnv &e, const Upd &u, const Wv &W, int sid
     // at least the rounding level max(m, n) eps sigma_1 (numerical rank):
     // singular vectors of smaller values are not determined by the data
     const double smax = nG > 0 ? W.sig[W.ord[0]] : 0.0;
-    const double tau = fmax(trunc_tau(e, smax), (double)(mr > mB ? mr : mB) * 2.220446049250313e-16 * smax);
+    // variable-order weighting: the threshold times q^(depth - level(c)),
+    // formed by repeated products (q = 1: unchanged)
+    double lsc = 1.0;
+    if (e.lvq != 1.0)
+      for (int l = e.level[c]; l < e.depth; ++l) lsc *= e.lvq;
+    const double tau = fmax(trunc_tau(e, smax) * lsc, (double)(mr > mB ? mr : mB) * 2.220446049250313e-16 * smax);
     for (int j = 0; j < nG; ++j) r += W.sig[W.ord[j]] > tau ? 1 : 0;
     if (r > e.rank_cap) {
       if (lane == 0) { e.err[1] = c; e.err[0] = E_RANK_CAP; }

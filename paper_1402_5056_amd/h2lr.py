@@ -58,7 +58,7 @@ class H2Error(RuntimeError):
 
 class h2_trunc(C.Structure):
     _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32),
-                ("accumulate", C.c_int32)]
+                ("accumulate", C.c_int32), ("level_factor", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -151,9 +151,10 @@ PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 
 
 def trunc(eps: float = 1e-4, mode: str = "block_rel", rank_cap: int = MAX_RANK,
-          precision: str = "fp64", accumulate: bool = False) -> h2_trunc:
+          precision: str = "fp64", accumulate: bool = False, level_factor: float = 1.0) -> h2_trunc:
     return h2_trunc(float(eps), MODES[mode] if isinstance(mode, str) else int(mode), int(rank_cap),
-                    PRECISIONS[precision] if isinstance(precision, str) else int(precision), int(bool(accumulate)))
+                    PRECISIONS[precision] if isinstance(precision, str) else int(precision), int(bool(accumulate)),
+                    float(level_factor))
 
 
 _LIVE = weakref.WeakSet()

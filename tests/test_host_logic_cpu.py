@@ -24,7 +24,7 @@ CHILD = textwrap.dedent(r'''
 
     class trunc(C.Structure):
         _fields_ = [("eps", C.c_double), ("mode", C.c_int32), ("rank_cap", C.c_int32), ("precision", C.c_int32),
-                    ("accumulate", C.c_int32)]
+                    ("accumulate", C.c_int32), ("level_factor", C.c_double)]
 
     def ok(st):
         assert st == 0, lib.h2_last_error()
