@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--accumulate", action="store_true",
                     help="accumulated updates: the temporaries of a product target in as few local updates "
                          "as the update rank allows")
+    ap.add_argument("--level-factor", type=float, default=1.0,
+                    help="variable-order weighting: recompression threshold times q^(depth - level), q in (0, 1]")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape of the substitutions (no autotuning)")
     ap.add_argument("--tune-cache", type=str, default=None,
@@ -113,7 +115,8 @@ def measured_traffic(args):
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), for the
     default workload only; None otherwise or when the summary is absent."""
     default = (args.side == 256 and args.dim == 2 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
-               and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate)
+               and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate
+               and args.level_factor == 1.0)
     if not default:
         return None
     try:
@@ -151,7 +154,8 @@ def measured_step_roofline(args):
     committed device-counter summary: algorithmic flops and bytes of each
     step over the wall time of its stage; None for other workloads."""
     default = (args.side == 256 and args.dim == 2 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
-               and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate)
+               and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate
+               and args.level_factor == 1.0)
     if not default:
         return None
     steps = []
@@ -540,6 +544,7 @@ def bench_bem(args):
                                f"H2(A) by local updates of the far-field blocks, block-relative eps {eps:.3g}, "
                                f"H2-Cholesky + PCG (dense A) 1 Gaussian RHS to {args.rtol}",
                    "n": n, "precision": args.precision, "accumulate": bool(args.accumulate),
+                   "level_factor": args.level_factor,
                    "parallelism": "1 GPU"},
         "setup_s": setup, "solve_s": solve, "solves_per_s": 1.0 / solve, "pcg_iters": iters,
         "true_relres": float(np.linalg.norm(p["b"] - A @ xr) / np.linalg.norm(p["b"])),
@@ -688,7 +693,8 @@ def main():
     prep["csr_upload_s"] = time.perf_counter() - tp0
     b = torch.tensor(p["b"], device="cuda")
     x = torch.zeros_like(b)
-    tr = h2lr.trunc(args.eps, "block_rel", 32, precision=args.precision, accumulate=args.accumulate)
+    tr = h2lr.trunc(args.eps, "block_rel", 32, precision=args.precision, accumulate=args.accumulate,
+                    level_factor=args.level_factor)
 
     inverse = args.precond == "inverse"
     inv_info = {}
@@ -780,9 +786,11 @@ def main():
                                + f" cluster tree leaf 32, eta {args.eta:g}, "
                                f"block-relative eps {args.eps}, H2-Cholesky"
                                + (" (accumulated updates)" if args.accumulate else "")
+                               + (f" (level factor {args.level_factor:g})" if args.level_factor != 1.0 else "")
                                + (" + triangular inverse" if inverse else "")
                                + f" + PCG 1 Gaussian RHS to {args.rtol}",
                    "n": n, "precision": args.precision, "accumulate": bool(args.accumulate),
+                   "level_factor": args.level_factor,
                    "parallelism": "1 GPU"},
         "setup_s": setup_s,
         "setup_min_s": float(np.min(setup_ms)) / 1e3,
