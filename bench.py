@@ -103,6 +103,10 @@ def parse():
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="only copy a float64 device buffer of this size once and exit: the "
                          "reference dispatch for scaling the HBM byte counters of a profile")
+    ap.add_argument("--progress-s", type=float, default=0.0,
+                    help="if > 0: factorise by an asynchronous launch (h2_cholesky_launch, the same "
+                         "interpreter) and print a progress line every this many seconds while it "
+                         "runs; for grids whose factorisation takes minutes")
     ap.add_argument("--oracle-worker", type=int, default=0, help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -116,7 +120,7 @@ def measured_traffic(args):
     default workload only; None otherwise or when the summary is absent."""
     default = (args.side == 256 and args.dim == 2 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
                and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate
-               and args.level_factor == 1.0)
+               and args.level_factor == 1.0 and args.progress_s == 0)
     if not default:
         return None
     try:
@@ -155,7 +159,7 @@ def measured_step_roofline(args):
     step over the wall time of its stage; None for other workloads."""
     default = (args.side == 256 and args.dim == 2 and args.eps == 1e-4 and args.eta == 2.0 and args.cluster == "bisection"
                and args.sigma_seed == "10" and args.precision == "fp64" and not args.accumulate
-               and args.level_factor == 1.0)
+               and args.level_factor == 1.0 and args.progress_s == 0)
     if not default:
         return None
     steps = []
@@ -702,8 +706,21 @@ def main():
     def step(evs):
         h2lr.h2_mat_assign(L, A0)
         evs[0].record(stream)
-        h2lr.h2_cholesky(L, tr)
-        evs[3].record(stream)
+        if args.progress_s > 0:
+            # one-workgroup launch of the same interpreter on the same stream;
+            # the end event is queued behind it, the host polls and reports
+            job = h2lr.h2_cholesky_launch([L], tr)
+            evs[3].record(stream)
+            tl0 = last = time.perf_counter()
+            while not job.done():
+                time.sleep(0.25)
+                if time.perf_counter() - last >= args.progress_s:
+                    last = time.perf_counter()
+                    print(f"[bench]   factorisation running, {last - tl0:.0f} s", file=sys.stderr, flush=True)
+            job.finish()
+        else:
+            h2lr.h2_cholesky(L, tr)
+            evs[3].record(stream)
         # h2_cholesky returns after its device work has finished; the
         # counters of the factor are read here (two small copies) so that
         # the factorisation is not run a second time for them
