@@ -57,6 +57,19 @@ CHILD = textwrap.dedent(r'''
     d = C.c_int32(); ok(lib.h2_job_query(job, C.byref(d)))
     ok(lib.h2_job_finish(job, st)); assert list(st) == [0, 0]
     ok(lib.h2_cholesky(L1, C.byref(tr)))
+    # truncation parameters are checked before any device work: mode, rank
+    # cap, eps, precision, the accumulation flag and the level factor
+    nan, inf = float("nan"), float("inf")
+    for bad in (trunc(1e-6, 3, 32, 0), trunc(1e-6, -1, 32, 0), trunc(1e-6, 0, 0, 0), trunc(1e-6, 0, 33, 0),
+                trunc(-1e-6, 0, 32, 0), trunc(nan, 0, 32, 0), trunc(inf, 0, 32, 0), trunc(1e-6, 0, 32, 3),
+                trunc(1e-6, 0, 32, 0, 2), trunc(1e-6, 0, 32, 0, -1), trunc(1e-6, 0, 32, 0, 0, 1.5),
+                trunc(1e-6, 0, 32, 0, 0, -0.5), trunc(1e-6, 0, 32, 0, 0, nan)):
+        assert lib.h2_cholesky(L1, C.byref(bad)) == -1, (bad.mode, bad.rank_cap, bad.eps, bad.level_factor)
+        assert b"must" in lib.h2_last_error(), lib.h2_last_error()
+        assert lib.h2_cholesky_batched(arr, 2, C.byref(bad), st) == -1
+    for good in (trunc(1e-6, 1, 32, 1, 1, 0.5), trunc(0.0, 2, 1, 2, 0, 1.0), trunc(1e-6, 0, 32, 0, 0, 0.0)):
+        ok(lib.h2_cholesky(L1, C.byref(good)))
+    ok(lib.h2_cholesky(L1, None))                     # no parameters: exact arithmetic
     # batch argument checks
     dup = (vp * 2)(L1.value, L1.value)
     assert lib.h2_cholesky_batched(dup, 2, C.byref(tr), st) == -1
