@@ -28,6 +28,6 @@ def test_more_than_one_gpu_refused(args, env):
 
 
 def test_large_dd_grid_refused():
-    r = _run(["--cluster", "dd", "--side", "64"])
+    r = _run(["--cluster", "dd", "--side", "256"])
     assert r.returncode == 2
     assert "domain-decomposition" in r.stderr and r.stdout == ""
