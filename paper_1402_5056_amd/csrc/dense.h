@@ -391,8 +391,11 @@ __device__ __forceinline__ void jacobi_rotation_fast(double al, double be, doubl
 // the loads and stores need no branches (a branch per row makes the compiler
 // wait for every LDS store).  Stops after a sweep without rotation, or after
 // a sweep whose largest rotated relative off-diagonal gamma^2/(alpha beta)
-// stayed below 1e-14: by quadratic convergence the next sweep would rotate
-// by angles of order 1e-14.
+// stayed below 1e-14: with quadratic convergence the next sweep would rotate
+// by angles of order 1e-14.  That early stop is not always safe: on a
+// domain-decomposition tree with mirror-symmetric clusters it leaves one
+// recompression's basis off by about 1e-12 relative, which a run to a sweep
+// without rotation avoids (at about one more sweep per call).
 template <int g, int RPL>
 __device__ int wave_jacobi_reg(int m, int n, MV G, MV *J) {
   const int lane = lane_id();
