@@ -155,3 +155,41 @@ def test_table1_level7_setting():
     assert it == g["pcg_steps"] and rel <= 1e-8
     assert power_error(A, prec, ct.n, iters=30) < g["err"]
     assert 8.0 * L.storage_values() / ct.n / 1024.0 < g["mem_per_n_kb"]
+
+
+def test_near_target_products_equal_recursion(monkeypatch):
+    """Products Z|_(t,r) += X|_(t,s) Y|_(r,s)^* whose target is an
+    inadmissible leaf pair while both factors are subdivided (s has sons)
+    are frequent on DD trees, where interface leaves meet large domains
+    (Section 6, the product recursion).  The oracle forms them densely.
+    Recursing over the sons of s instead ends in low-rank emissions added to
+    the dense target.  The two sums are equal in exact arithmetic, so the
+    factors must agree to rounding, with equal ranks; the plain run must
+    contain such products for the check to mean anything."""
+    import oracle.arith as OA
+    from oracle.trees import INNER
+    N = 48
+    ct, bt = _dd(N, 2, 32)
+    A = _matrix(N, 2, None)
+    tp = TruncParams(50.0 / N ** 2, "block_rel", 32)
+    st0 = {}
+    L0 = cholesky(from_csr(A, ct, bt, lower=True), tp, st0)
+    assert st0.get("near_dense_product", 0) > 0
+    plain = OA._Chol.mm
+
+    def recursed(self, t, s, r, alpha, tmp=None):
+        if tmp is None and bt.kind[bt.find(t, s)] == INNER and bt.kind[bt.find(r, s)] == INNER \
+                and bt.kind[bt.find(t, r)] == NEAR:
+            for s2 in ct.sons_plus(s):
+                for t2 in ct.sons_plus(t):
+                    for r2 in ct.sons_plus(r):
+                        recursed(self, t2, s2, r2, alpha)
+            return
+        return plain(self, t, s, r, alpha, tmp)
+    monkeypatch.setattr(OA._Chol, "mm", recursed)
+    st1 = {}
+    L1 = cholesky(from_csr(A, ct, bt, lower=True), tp, st1)
+    assert st1.get("near_dense_product", 0) == 0
+    assert np.array_equal(L1.k[0], L0.k[0]) and np.array_equal(L1.k[1], L0.k[1])
+    D0, D1 = np.tril(to_dense(L0)), np.tril(to_dense(L1))
+    assert np.linalg.norm(D1 - D0, 2) / np.linalg.norm(D0, 2) < 1e-13
